@@ -1,0 +1,319 @@
+"""FP64 CPU oracle for the batched LBM-UQ path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package. It is a plain, slow, single-threaded double-precision
+implementation written from the paper (OpenLB-UQ, arXiv 2508.13867):
+
+* the lattice Boltzmann solve per sample (Sec. "Lattice Boltzmann methods":
+  Eqs. deterministicLBE, bgkCollision, equilibrium, the D2Q9 set and weights,
+  and the collide/stream split) lives in ``oracle.c``;
+* the non-intrusive UQ algorithm (Algorithm alg:uq_openlb: generate samples,
+  solve each one in turn, then Monte Carlo or stochastic-collocation
+  statistics) is ``run_problem`` below, looping over samples one at a time.
+
+It shares no code with the GPU library and imports nothing from it. Problems
+are plain dicts (keys documented in ``run_problem``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from math import comb
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_u64p = C.POINTER(C.c_uint64)
+
+
+def _declare(L):
+    L.oracle_d2q9.argtypes = [_ip, _ip, _dp, _ip]
+    L.oracle_feq.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+    L.oracle_collide.argtypes = [_dp, C.c_double, _dp]
+    L.oracle_table1_units.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
+    L.oracle_legendre_orthonormal.argtypes = [C.c_int, C.c_double]
+    L.oracle_legendre_orthonormal.restype = C.c_double
+    L.oracle_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
+    L.oracle_gl_tensor.argtypes = [C.c_int, C.c_int, _dp, _dp]
+    L.oracle_multi_indices.argtypes = [C.c_int, C.c_int, _ip]
+    L.oracle_multi_indices.restype = C.c_int
+    L.oracle_phi_table.argtypes = [C.c_long, C.c_int, _dp, C.c_int, _ip, _dp]
+    L.oracle_splitmix64_stream.argtypes = [C.c_uint64, C.c_long, _u64p]
+    L.oracle_mc_points.argtypes = [C.c_uint64, C.c_long, C.c_int, _dp, _dp]
+    L.oracle_mc_stats.argtypes = [C.c_long, C.c_long, _dp, _dp, _dp, _dp]
+    L.oracle_gpc_stats.argtypes = [C.c_long, C.c_long, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.oracle_tgv_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_long,
+                                 C.c_double, _dp, _dp, _dp, _dp, _dp]
+    L.oracle_channel_run.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                     C.c_double, C.c_long, C.c_long, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     _dp]
+    L.oracle_cylinder_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.oracle_cylinder_nodes.restype = C.c_long
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+# --------------------------------------------------------------------------
+# lattice constants and single-node operators
+
+
+def d2q9():
+    cx = np.zeros(9, np.int32)
+    cy = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    opp = np.zeros(9, np.int32)
+    lib().oracle_d2q9(cx.ctypes.data_as(_ip), cy.ctypes.data_as(_ip), _p(w), opp.ctypes.data_as(_ip))
+    return cx, cy, w, opp
+
+
+def feq(rho, ux, uy):
+    out = np.zeros(9)
+    lib().oracle_feq(rho, ux, uy, _p(out))
+    return out
+
+
+def collide(f, tau):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(9)
+    lib().oracle_collide(_p(f), tau, _p(out))
+    return out
+
+
+def table1_units(n, Ma, Re):
+    t, dx, dt = C.c_double(), C.c_double(), C.c_double()
+    lib().oracle_table1_units(n, Ma, Re, C.byref(t), C.byref(dx), C.byref(dt))
+    return t.value, dx.value, dt.value
+
+
+# --------------------------------------------------------------------------
+# quadrature, basis and sampling
+
+
+def legendre_orthonormal(n, x):
+    return lib().oracle_legendre_orthonormal(int(n), float(x))
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    if lib().oracle_gauss_legendre(n, _p(x), _p(w)) != 0:
+        raise ValueError("n must be >= 1")
+    return x, w
+
+
+def gl_tensor(d, n):
+    S = n ** d
+    xi = np.zeros((S, d))
+    a = np.zeros(S)
+    lib().oracle_gl_tensor(d, n, _p(xi), _p(a))
+    return xi, a
+
+
+def multi_indices(d, P):
+    K = comb(d + P, P)
+    al = np.zeros((K, d), np.int32)
+    k = lib().oracle_multi_indices(d, P, al.ctypes.data_as(_ip))
+    assert k == K
+    return al
+
+
+def phi_table(xi, alpha):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    alpha = np.ascontiguousarray(alpha, dtype=np.int32)
+    S, d = xi.shape
+    K = alpha.shape[0]
+    phi = np.zeros((S, K))
+    lib().oracle_phi_table(S, d, _p(xi), K, alpha.ctypes.data_as(_ip), _p(phi))
+    return phi
+
+
+def splitmix64_stream(seed, n):
+    out = np.zeros(n, np.uint64)
+    lib().oracle_splitmix64_stream(C.c_uint64(seed), n, out.ctypes.data_as(_u64p))
+    return out
+
+
+def mc_points(seed, N, d):
+    xi = np.zeros((N, d))
+    a = np.zeros(N)
+    lib().oracle_mc_points(C.c_uint64(seed), N, d, _p(xi), _p(a))
+    return xi, a
+
+
+# --------------------------------------------------------------------------
+# statistics
+
+
+def mc_stats(M):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    S = M.shape[0]
+    n_out = int(np.prod(M.shape[1:])) if M.ndim > 1 else 1
+    mean, var, var_n = (np.zeros(n_out) for _ in range(3))
+    lib().oracle_mc_stats(S, n_out, _p(M), _p(mean), _p(var), _p(var_n))
+    return {"mean": mean, "var": var, "var_alt": var_n}
+
+
+def gpc_stats(M, a, phi):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    S = M.shape[0]
+    n_out = int(np.prod(M.shape[1:])) if M.ndim > 1 else 1
+    K = phi.shape[1]
+    coeffs = np.zeros((K, n_out))
+    mean, var, vq = (np.zeros(n_out) for _ in range(3))
+    lib().oracle_gpc_stats(S, n_out, _p(M), _p(a), K, _p(phi), _p(coeffs), _p(mean), _p(var), _p(vq))
+    return {"mean": mean, "var": var, "var_alt": vq, "coeffs": coeffs}
+
+
+# --------------------------------------------------------------------------
+# one deterministic solve
+
+
+def tgv_run(nx, ny, nu, u0, steps, phase_x=0.0, phase_y=0.0, ke_u0=None, want_f=False):
+    n = nx * ny
+    rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
+    f = np.zeros(9 * n) if want_f else None
+    ke = C.c_double()
+    rc = lib().oracle_tgv_run(nx, ny, nu, u0, phase_x, phase_y, steps, u0 if ke_u0 is None else ke_u0,
+                              _p(f), _p(rho), _p(ux), _p(uy), C.byref(ke))
+    if rc != 0:
+        raise ValueError("invalid TGV parameters (tau must exceed 1/2)")
+    out = {"ke": ke.value, "rho": rho.reshape(ny, nx), "ux": ux.reshape(ny, nx), "uy": uy.reshape(ny, nx)}
+    if want_f:
+        out["f"] = f.reshape(9, ny, nx)
+    return out
+
+
+def channel_run(nx, ny, nu, u_peak, steps, D=0, cx=0, cy=0, ramp=0, xbc=0, want_f=False, ux_init=0.0):
+    n = nx * ny
+    rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
+    f = np.zeros(9 * n) if want_f else None
+    force, cdcl, wall = np.zeros(2), np.zeros(2), np.zeros(2)
+    rc = lib().oracle_channel_run(nx, ny, xbc, D, cx, cy, nu, u_peak, ramp, steps, ux_init, _p(f), _p(rho), _p(ux),
+                                  _p(uy), _p(force), _p(cdcl), _p(wall))
+    if rc != 0:
+        raise ValueError("invalid channel parameters")
+    out = {"rho": rho.reshape(ny, nx), "ux": ux.reshape(ny, nx), "uy": uy.reshape(ny, nx),
+           "force": force, "cd": cdcl[0], "cl": cdcl[1], "wall_force": wall}
+    if want_f:
+        out["f"] = f.reshape(9, ny, nx)
+    return out
+
+
+def cylinder_nodes(nx, ny, D, cx, cy):
+    return lib().oracle_cylinder_nodes(nx, ny, D, cx, cy)
+
+
+# --------------------------------------------------------------------------
+# the non-intrusive UQ algorithm, one sample after the other
+
+_TARGETS = ("nu", "u0", "phase_x", "phase_y", "re", "u_peak")
+
+
+def sample_set(problem):
+    """Step 1 of the SC-gPC procedure / MC sample generation: (xi, a)."""
+    d = len(problem["dists"])
+    r = problem["rule"]
+    if r["kind"] == "gl":
+        return gl_tensor(d, r["n"])
+    if r["kind"] == "mc":
+        return mc_points(r.get("seed", 123456), r["N"], d)
+    raise ValueError(r["kind"])
+
+
+def sample_params(problem, xi_row):
+    """Deterministic inputs of one sample: each uncertain input is the affine
+    image (lo+hi)/2 + (hi-lo)/2 xi of its reference variable; a Reynolds-number
+    input sets nu = u_peak_nominal D / Re (the cylinder section's definition
+    of Re with the peak inflow velocity)."""
+    p = {k: problem.get(k, 0.0) for k in _TARGETS}
+    p["u_peak"] = problem.get("u_peak", 0.0)
+    for (target, lo, hi), z in zip(problem["dists"], xi_row):
+        if target not in _TARGETS:
+            raise ValueError(target)
+        p[target] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * z
+    if any(t == "re" for t, _, _ in problem["dists"]):
+        p["nu"] = problem["u_peak"] * problem["D"] / p["re"]
+    return p
+
+
+def solve_sample(problem, params, steps=None):
+    """One deterministic LBM run of the given sample; returns its QoIs."""
+    steps = problem["steps"] if steps is None else steps
+    nx, ny = problem["nx"], problem["ny"]
+    if problem["geometry"] == "tgv":
+        r = tgv_run(nx, ny, params["nu"], params["u0"], steps, params["phase_x"], params["phase_y"],
+                    ke_u0=problem["u0"])
+        return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
+    if problem["geometry"] == "channel":
+        r = channel_run(nx, ny, params["nu"], params["u_peak"], steps, D=problem["D"], cx=problem["cx"],
+                        cy=problem["cy"], ramp=problem.get("ramp", 0), xbc=problem.get("xbc", 0))
+        return {"cd": r["cd"], "cl": r["cl"], "fx": r["force"][0], "fy": r["force"][1],
+                "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
+    raise ValueError(problem["geometry"])
+
+
+def run_problem(problem, samples=None, qois=None, steps=None):
+    """Algorithm alg:uq_openlb, sequentially.
+
+    problem keys: geometry ('tgv' | 'channel'), nx, ny, steps, nominal inputs
+    (nu, u0, phase_x, phase_y for the vortex; u_peak, D, cx, cy, ramp, xbc for
+    the channel), dists = [(target, lo, hi), ...] with target in nu, u0,
+    phase_x, phase_y, re, u_peak, and rule = {'kind': 'gl', 'n': points per
+    dimension, 'order': P} or {'kind': 'mc', 'N': samples, 'seed': s}.
+
+    samples: optional subset of sample indices to solve (statistics are then
+    not computed). Returns per-sample QoIs and, for the full set, statistics.
+    """
+    xi, a = sample_set(problem)
+    S = xi.shape[0]
+    idxs = range(S) if samples is None else samples
+    per = [solve_sample(problem, sample_params(problem, xi[j]), steps) for j in idxs]
+    names = qois or [k for k in per[0].keys()]
+    out = {"xi": xi, "a": a, "samples": {k: np.array([p[k] for p in per]) for k in names}}
+    if samples is not None:
+        return out
+    d = xi.shape[1]
+    r = problem["rule"]
+    stats = {}
+    if r["kind"] == "gl":
+        alpha = multi_indices(d, r["order"])
+        phi = phi_table(xi, alpha)
+        out["alpha"], out["phi"] = alpha, phi
+        for k in names:
+            stats[k] = gpc_stats(out["samples"][k].reshape(S, -1), a, phi)
+    else:
+        for k in names:
+            stats[k] = mc_stats(out["samples"][k].reshape(S, -1))
+    out["stats"] = stats
+    return out

@@ -1,0 +1,633 @@
+/*
+ * FP64 reference implementation of the non-intrusive LBM-UQ method
+ * (OpenLB-UQ, arXiv 2508.13867). TEST INFRASTRUCTURE ONLY: it is called by
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark,
+ * never by the product path. It shares no code, header or table with the GPU
+ * library; every constant below is derived here from the paper's definitions.
+ *
+ * Plain, slow, single-threaded double precision. Per sample it runs a
+ * two-array D2Q9 BGK scheme in the paper's order: collide (Sec. "Lattice
+ * Boltzmann methods", collision/streaming split), then stream, then complete
+ * the populations that streaming leaves undefined (boundaries).
+ *
+ * Readings of passages where the paper is silent or garbled are listed at the
+ * top of each function; all of them are collected in the design notes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* D2Q9 velocity set and weights (Sec. "Lattice Boltzmann methods", velocity
+ * set and Eq. weightsDdQ9). Reading: the scalar prefactor "w" in the weight
+ * equation is 1 (the weights must sum to one). Ordering within the groups is
+ * not fixed by the paper; we use rest, the four axis directions
+ * counter-clockwise from +x, then the four diagonals counter-clockwise from
+ * (+1,+1).                                                                   */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+static double W(int i) {
+    if (i == 0) return 4.0 / 9.0;
+    if (i <= 4) return 1.0 / 9.0;
+    return 1.0 / 36.0;
+}
+
+/* opposite direction: the j with c_j = -c_i, found by search (no table). */
+static int OPP(int i) {
+    for (int j = 0; j < 9; ++j)
+        if (CX[j] == -CX[i] && CY[j] == -CY[i]) return j;
+    return -1;
+}
+
+/* c_s^2 = 1/3 in lattice units. Pinned by reproducing the paper's Table
+ * tab:simulation_parameters with tau = nu/c_s^2 + 1/2.                      */
+static const double CS2 = 1.0 / 3.0;
+
+void oracle_d2q9(int *cx, int *cy, double *w, int *opp) {
+    for (int i = 0; i < 9; ++i) {
+        cx[i] = CX[i];
+        cy[i] = CY[i];
+        w[i] = W(i);
+        opp[i] = OPP(i);
+    }
+}
+
+/* Second-order equilibrium, Eq. "equilibrium":
+ * f_i^eq = w_i rho (1 + u.c_i/cs2 + (u.c_i)^2/(2 cs2^2) - u.u/(2 cs2)).     */
+static double feq(int i, double rho, double ux, double uy) {
+    double cu = ux * CX[i] + uy * CY[i];
+    double uu = ux * ux + uy * uy;
+    return W(i) * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+}
+
+void oracle_feq(double rho, double ux, double uy, double *out) {
+    for (int i = 0; i < 9; ++i) out[i] = feq(i, rho, ux, uy);
+}
+
+/* Moments rho = sum f_i, rho u = sum c_i f_i (Sec. "Lattice Boltzmann
+ * methods", moment equations).                                              */
+static void moments(const double *f, double *rho, double *ux, double *uy) {
+    double r = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        r += f[i];
+        jx += CX[i] * f[i];
+        jy += CY[i] * f[i];
+    }
+    *rho = r;
+    *ux = jx / r;
+    *uy = jy / r;
+}
+
+/* BGK collision, Eq. bgkCollision with the collision half of the
+ * collide/stream split: f* = f - (f - f^eq)/tau.                            */
+static void collide(const double *f, double tau, double *fs) {
+    double rho, ux, uy;
+    moments(f, &rho, &ux, &uy);
+    for (int i = 0; i < 9; ++i) fs[i] = f[i] - (f[i] - feq(i, rho, ux, uy)) / tau;
+}
+
+void oracle_collide(const double *f, double tau, double *out) { collide(f, tau, out); }
+
+/* Unit conversion of the paper's four-dimensional TGV case (Table
+ * tab:simulation_parameters): dx = 2 pi/(n-1), lattice speed Ma/sqrt(3),
+ * dt = dx * u_lat, nu_phys = 1/Re, nu_lat = nu_phys dt/dx^2,
+ * tau = nu_lat/cs2 + 1/2.                                                   */
+void oracle_table1_units(int n, double Ma, double Re, double *tau, double *dx, double *dt) {
+    const double pi = acos(-1.0);
+    double h = 2.0 * pi / (double)(n - 1);
+    double ulat = Ma / sqrt(3.0);
+    double k = h * ulat;
+    double nu_lat = (1.0 / Re) * k / (h * h);
+    *dx = h;
+    *dt = k;
+    *tau = nu_lat / CS2 + 0.5;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature and polynomial basis (Sec. "Generalized polynomial chaos").    */
+
+/* Legendre polynomial P_n(x) by the three-term recurrence
+ * (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}; also returns P_n'(x).           */
+static double legendre(int n, double x, double *dp) {
+    double p0 = 1.0, p1 = x;
+    if (n == 0) {
+        if (dp) *dp = 0.0;
+        return 1.0;
+    }
+    for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+    }
+    if (dp) *dp = n * (x * p1 - p0) / (x * x - 1.0);
+    return p1;
+}
+
+/* Orthonormal Legendre basis for the uniform density on [-1,1]:
+ * E[phi_m phi_n] = delta_mn with phi_n = sqrt(2n+1) P_n (so gamma_k = 1 in
+ * Eq. coef_integral).                                                       */
+double oracle_legendre_orthonormal(int n, double x) {
+    return sqrt(2.0 * n + 1.0) * legendre(n, x, NULL);
+}
+
+/* n-point Gauss-Legendre rule on [-1,1] (textbook weights, sum 2): nodes are
+ * the roots of P_n found by Newton's method from the Chebyshev-like guess
+ * cos(pi (i + 3/4)/(n + 1/2)); weights 2/((1-x^2) P_n'(x)^2). Nodes are
+ * returned in increasing order.                                             */
+int oracle_gauss_legendre(int n, double *x, double *w) {
+    if (n < 1) return -1;
+    const double pi = acos(-1.0);
+    for (int i = 0; i < n; ++i) {
+        double z = cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p = legendre(n, z, &dp);
+            double dz = p / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        legendre(n, z, &dp);
+        /* the guess for index i approaches the i-th largest root */
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0; /* the middle root is exactly zero */
+    return 0;
+}
+
+/* Tensor-product collocation rule over d independent uniform inputs
+ * (Sec. "Quadrature and collocation", tensor products; step 1 of the SC-gPC
+ * procedure). Reading: weights are those of the probability measure h, i.e.
+ * each one-dimensional rule is divided by 2 so the weights sum to one and the
+ * zeroth coefficient is the mean (Eq. gpc_mean). Samples are enumerated with
+ * dimension 0 varying slowest.                                              */
+int oracle_gl_tensor(int d, int n, double *xi, double *a) {
+    if (d < 1 || n < 1) return -1;
+    double *x1 = malloc(sizeof(double) * n), *w1 = malloc(sizeof(double) * n);
+    oracle_gauss_legendre(n, x1, w1);
+    long S = 1;
+    for (int k = 0; k < d; ++k) S *= n;
+    for (long j = 0; j < S; ++j) {
+        long rem = j;
+        double wj = 1.0;
+        for (int k = d - 1; k >= 0; --k) {
+            int m = (int)(rem % n);
+            rem /= n;
+            xi[j * d + k] = x1[m];
+            wj *= 0.5 * w1[m];
+        }
+        a[j] = wj;
+    }
+    free(x1);
+    free(w1);
+    return 0;
+}
+
+/* Total-degree multi-indices |alpha| <= P in d dimensions (reading of the
+ * truncated expansion Eq. gPC for d > 1, which the paper leaves open), in
+ * graded order: by total degree, and within one degree with alpha_0 largest
+ * first, then alpha_1, and so on. Returns K = C(d+P, P); fills alpha[K*d] if
+ * not NULL. Enumeration is a plain odometer over [0,P]^d filtered by degree,
+ * repeated per degree.                                                      */
+int oracle_multi_indices(int d, int P, int *alpha) {
+    int K = 0;
+    int *cur = calloc((size_t)d, sizeof(int));
+    for (int deg = 0; deg <= P; ++deg) {
+        /* odometer that counts down from (P,...,P) to (0,...,0) in the
+         * lexicographic order with the first coordinate most significant   */
+        long total = 1;
+        for (int k = 0; k < d; ++k) total *= (P + 1);
+        for (long code = total - 1; code >= 0; --code) {
+            long rem = code;
+            int s = 0;
+            for (int k = d - 1; k >= 0; --k) {
+                cur[k] = (int)(rem % (P + 1));
+                rem /= (P + 1);
+                s += cur[k];
+            }
+            if (s != deg) continue;
+            if (alpha)
+                for (int k = 0; k < d; ++k) alpha[K * d + k] = cur[k];
+            ++K;
+        }
+    }
+    free(cur);
+    return K;
+}
+
+/* Phi table Phi[j*K + k] = prod_m phi_{alpha_k,m}(xi_{j,m}).                */
+void oracle_phi_table(long S, int d, const double *xi, int K, const int *alpha, double *phi) {
+    for (long j = 0; j < S; ++j)
+        for (int k = 0; k < K; ++k) {
+            double v = 1.0;
+            for (int m = 0; m < d; ++m) v *= oracle_legendre_orthonormal(alpha[k * d + m], xi[j * d + m]);
+            phi[j * K + k] = v;
+        }
+}
+
+/* Monte Carlo draws (Sec. "Monte Carlo and quasi Monte Carlo sampling";
+ * the paper seeds its example with 123456 but names no generator). Reading:
+ * SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) run sequentially from `seed`;
+ * output number c (c = 1, 2, ...) is used for sample j, dimension k with
+ * c = j*d + k + 1. The top 53 bits give u in [0,1), and xi = 2u - 1.
+ * This implementation steps the generator state one increment at a time.   */
+static uint64_t splitmix_next(uint64_t *state) {
+    *state += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = *state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+void oracle_splitmix64_stream(uint64_t seed, long n, uint64_t *out) {
+    uint64_t s = seed;
+    for (long c = 0; c < n; ++c) out[c] = splitmix_next(&s);
+}
+
+void oracle_mc_points(uint64_t seed, long N, int d, double *xi, double *a) {
+    uint64_t s = seed;
+    for (long j = 0; j < N; ++j) {
+        for (int k = 0; k < d; ++k) {
+            uint64_t r = splitmix_next(&s);
+            double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);
+            xi[j * d + k] = 2.0 * u - 1.0;
+        }
+        a[j] = 1.0 / (double)N;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compensated summation (Neumaier's improvement of Kahan's algorithm).      */
+typedef struct {
+    double s, c;
+} nsum;
+
+static void nadd(nsum *a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Statistics over samples (Sec. "Monte Carlo and quasi Monte Carlo
+ * sampling", Eqs. meanMCS and varMCS; Sec. "Generalized polynomial chaos",
+ * Eqs. coef_discrete, gpc_mean, gpc_std). M is [S][n_out] row-major.        */
+
+/* MC: mean (Eq. meanMCS), unbiased variance 1/(N-1) (Eq. varMCS) and the
+ * 1/N variant used in the non-intrusive UQ algorithm's Monte Carlo branch.  */
+void oracle_mc_stats(long S, long n_out, const double *M, double *mean, double *var, double *var_n) {
+    for (long o = 0; o < n_out; ++o) {
+        nsum s = {0, 0};
+        for (long j = 0; j < S; ++j) nadd(&s, M[j * n_out + o]);
+        double m = nval(&s) / (double)S;
+        nsum q = {0, 0};
+        for (long j = 0; j < S; ++j) {
+            double e = M[j * n_out + o] - m;
+            nadd(&q, e * e);
+        }
+        mean[o] = m;
+        var[o] = S > 1 ? nval(&q) / (double)(S - 1) : 0.0;
+        var_n[o] = nval(&q) / (double)S;
+    }
+}
+
+/* SC-gPC: coefficients by discrete projection (Eq. coef_discrete, gamma_k=1
+ * for the orthonormal basis), mean = coefficient 0 (Eq. gpc_mean), variance
+ * = sum of squares of the other retained coefficients (Eq. gpc_std), and the
+ * quadrature variance sum_j a_j (M_j - mean)^2 as a diagnostic.
+ * coeffs is [K][n_out].                                                      */
+void oracle_gpc_stats(long S, long n_out, const double *M, const double *a, int K, const double *phi,
+                      double *coeffs, double *mean, double *var, double *var_quad) {
+    for (long o = 0; o < n_out; ++o) {
+        for (int k = 0; k < K; ++k) {
+            nsum s = {0, 0};
+            for (long j = 0; j < S; ++j) nadd(&s, a[j] * M[j * n_out + o] * phi[j * K + k]);
+            coeffs[(long)k * n_out + o] = nval(&s);
+        }
+        mean[o] = coeffs[o];
+        nsum v = {0, 0};
+        for (int k = 1; k < K; ++k) {
+            double c = coeffs[(long)k * n_out + o];
+            nadd(&v, c * c);
+        }
+        var[o] = nval(&v);
+        nsum q = {0, 0};
+        for (long j = 0; j < S; ++j) {
+            double e = M[j * n_out + o] - mean[o];
+            nadd(&q, a[j] * e * e);
+        }
+        var_quad[o] = nval(&q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Taylor-Green vortex, one deterministic sample (Sec. "Taylor--Green vortex
+ * flow with uncertain viscosity", Eqs. TGV_vel, TGV_press, KineticEnergy).
+ * Readings: nodes x, y = 0..n-1 and k = 2 pi/n; the initial density is
+ * rho = 1 + p/cs2 (the equation of state with the reference pressure P0
+ * taken as the one at rho = 1); two optional phase shifts enter as
+ * (k x + phi_x), (k y + phi_y), a translate of the same exact solution;
+ * tau = nu/cs2 + 1/2 (lattice units, dt = 1).
+ *
+ * State f(x, t) is the post-streaming, pre-collision population; the QoIs at
+ * step n are moments of f(., n). f is stored [9][ny][nx].                  */
+
+static long idx(int i, int y, int x, int nx, int ny) { return ((long)i * ny + y) * nx + x; }
+
+static void tgv_init(int nx, int ny, double u0, double phx, double phy, double *f) {
+    const double pi = acos(-1.0);
+    double kx = 2.0 * pi / nx, ky = 2.0 * pi / ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double ax = kx * x + phx, ay = ky * y + phy;
+            double ux = -u0 * cos(ax) * sin(ay);
+            double uy = u0 * sin(ax) * cos(ay);
+            double p = -0.25 * u0 * u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
+            double rho = 1.0 + p / CS2;
+            for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = feq(i, rho, ux, uy);
+        }
+}
+
+static void periodic_step(int nx, int ny, double tau, double *f, double *tmp) {
+    double fc[9], fs[9];
+    /* collision at every node, written to tmp */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            for (int i = 0; i < 9; ++i) fc[i] = f[idx(i, y, x, nx, ny)];
+            collide(fc, tau, fs);
+            for (int i = 0; i < 9; ++i) tmp[idx(i, y, x, nx, ny)] = fs[i];
+        }
+    /* streaming f_i(x + c_i, t+1) = f*_i(x, t), periodic in both axes */
+    for (int i = 0; i < 9; ++i)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int xd = (x + CX[i] + nx) % nx, yd = (y + CY[i] + ny) % ny;
+                f[idx(i, yd, xd, nx, ny)] = tmp[idx(i, y, x, nx, ny)];
+            }
+}
+
+/* Run one TGV sample for `steps` steps. Outputs (each may be NULL):
+ * f_out [9][ny][nx]; rho/ux/uy [ny][nx]; ke (normalised by ke_u0, the
+ * nominal amplitude: reading of Eq. KineticEnergy when u0 is uncertain).   */
+int oracle_tgv_run(int nx, int ny, double nu, double u0, double phx, double phy, long steps, double ke_u0,
+                   double *f_out, double *rho_out, double *ux_out, double *uy_out, double *ke_out) {
+    double tau = nu / CS2 + 0.5;
+    if (!(tau > 0.5) || nx < 1 || ny < 1) return -1;
+    long n = (long)nx * ny;
+    double *f = malloc(sizeof(double) * 9 * n), *tmp = malloc(sizeof(double) * 9 * n);
+    tgv_init(nx, ny, u0, phx, phy, f);
+    for (long t = 0; t < steps; ++t) periodic_step(nx, ny, tau, f, tmp);
+    nsum ke = {0, 0};
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double fc[9], rho, ux, uy;
+            for (int i = 0; i < 9; ++i) fc[i] = f[idx(i, y, x, nx, ny)];
+            moments(fc, &rho, &ux, &uy);
+            long c = (long)y * nx + x;
+            if (rho_out) rho_out[c] = rho;
+            if (ux_out) ux_out[c] = ux;
+            if (uy_out) uy_out[c] = uy;
+            nadd(&ke, ux * ux + uy * uy);
+        }
+    if (ke_out) *ke_out = 2.0 / ((double)nx * ny * ke_u0 * ke_u0) * nval(&ke);
+    if (f_out) memcpy(f_out, f, sizeof(double) * 9 * n);
+    free(f);
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Channel flow past a cylinder, one deterministic sample. The paper's own
+ * set-up (Sec. "Flow past a circular cylinder with uncertain inlet
+ * velocity") uses interpolated and curved boundaries; this is the simpler
+ * variant with the same structure:
+ *   - channel of nx x ny nodes, walls half-way at y = -1/2 and y = ny - 1/2
+ *     (so H = ny), no-slip by half-way bounce-back;
+ *   - solid cylinder nodes: 4((x-cx)^2 + (y-cy)^2) <= D^2 (integer test);
+ *     half-way bounce-back on every link into it;
+ *   - x boundary mode xbc: 0 = velocity inlet at x = 0 and pressure outlet
+ *     (rho = 1) at x = nx-1, both by Zou & He (Phys. Fluids 9, 1591, 1997)
+ *     on every row of the open columns; at the two corner nodes of a column
+ *     the populations arriving from beyond the wall are filled by
+ *     bounce-back first, and Zou-He then completes the rest;
+ *     1 = solid walls half-way at x = -1/2 and x = nx - 1/2; 2 = periodic;
+ *   - parabolic inlet u_x(y) = s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2, u_y = 0,
+ *     with the start-up ramp s(t) = sin^2(pi t/(2 T_r)) for t < T_r, else 1
+ *     (the paper ramps the inflow without giving the form);
+ *   - initial state: equilibrium at rho = 1, u = 0 (Sec. cylinder,
+ *     equilibrium initialisation; s(0) = 0); tests may start from a uniform
+ *     u = (ux_init, 0) instead;
+ *   - forces by momentum exchange on the cylinder links,
+ *     F = sum_{fluid x, i: x + c_i in cylinder} 2 c_i f*_i(x, t), from the
+ *     post-collision populations of step t (Ladd 1994), a lattice evaluation
+ *     of the surface integrals Eqs. dragForce/liftForce;
+ *   - C_D = 2 F_x/(rho0 u_peak^2 D), C_L = 2 F_y/(rho0 u_peak^2 D) with
+ *     rho0 = 1 and the sample's peak inlet velocity.                        */
+
+typedef struct {
+    int nx, ny, xbc;
+    int D, cx, cy;
+    double tau, u_peak;
+    long ramp;
+    unsigned char *solid; /* [ny][nx] cylinder mask */
+} channel;
+
+static int ch_cyl(const channel *c, int x, int y) {
+    if (c->D <= 0) return 0;
+    long dx = x - c->cx, dy = y - c->cy;
+    return 4 * (dx * dx + dy * dy) <= (long)c->D * c->D;
+}
+
+static double ramp_factor(long t, long T) {
+    if (T <= 0 || t >= T) return 1.0;
+    const double pi = acos(-1.0);
+    double s = sin(pi * (double)t / (2.0 * (double)T));
+    return s * s;
+}
+
+static double inlet_ux(const channel *c, int y, long t) {
+    double H = (double)c->ny;
+    double yy = y + 0.5;
+    return ramp_factor(t, c->ramp) * 4.0 * c->u_peak * yy * (H - yy) / (H * H);
+}
+
+/* classify the source node x - c_i of a pull for node (x, y):
+ * 0 = fluid node inside (coordinates returned), 1 = bounce-back (solid,
+ * or wall), 2 = open boundary (Zou-He fills it).                           */
+static int ch_source(const channel *c, int x, int y, int i, int *xs, int *ys) {
+    int sx = x - CX[i], sy = y - CY[i];
+    if (sy < 0 || sy >= c->ny) return 1;
+    if (sx < 0 || sx >= c->nx) {
+        if (c->xbc == 2) {
+            sx = (sx + c->nx) % c->nx;
+        } else if (c->xbc == 1) {
+            return 1;
+        } else {
+            return 2;
+        }
+    }
+    if (c->solid[(long)sy * c->nx + sx]) return 1;
+    *xs = sx;
+    *ys = sy;
+    return 0;
+}
+
+/* Zou-He completion of the unknown populations at an open-column node. */
+static void zou_he_inlet(double *f, double ux) {
+    double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - ux);
+    f[1] = f[3] + (2.0 / 3.0) * rho * ux;
+    f[5] = f[7] - 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * rho * ux;
+    f[8] = f[6] + 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * rho * ux;
+}
+
+static void zou_he_outlet(double *f) {
+    double rho = 1.0;
+    double ux = -1.0 + (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / rho;
+    f[3] = f[1] - (2.0 / 3.0) * rho * ux;
+    f[7] = f[5] + 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * rho * ux;
+    f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * rho * ux;
+}
+
+static void channel_step(const channel *c, long t, double *f, double *fs) {
+    int nx = c->nx, ny = c->ny;
+    /* collision at every fluid node */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (c->solid[(long)y * nx + x]) continue;
+            double a[9], b[9];
+            for (int i = 0; i < 9; ++i) a[i] = f[idx(i, y, x, nx, ny)];
+            collide(a, c->tau, b);
+            for (int i = 0; i < 9; ++i) fs[idx(i, y, x, nx, ny)] = b[i];
+        }
+    /* streaming by pull, bounce-back where the source is not fluid, then
+     * Zou-He on the open columns with the inflow of time t+1              */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (c->solid[(long)y * nx + x]) continue;
+            double g[9];
+            int open = 0;
+            for (int i = 0; i < 9; ++i) {
+                int xs = 0, ys = 0;
+                int k = ch_source(c, x, y, i, &xs, &ys);
+                if (k == 0)
+                    g[i] = fs[idx(i, ys, xs, nx, ny)];
+                else if (k == 1)
+                    g[i] = fs[idx(OPP(i), y, x, nx, ny)];
+                else {
+                    g[i] = 0.0;
+                    open = 1;
+                }
+            }
+            if (open) {
+                if (x == 0)
+                    zou_he_inlet(g, inlet_ux(c, y, t + 1));
+                else
+                    zou_he_outlet(g);
+            }
+            for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = g[i];
+        }
+}
+
+/* Run one channel sample. Outputs (each may be NULL): f_out [9][ny][nx]
+ * (solid nodes hold 0), rho/ux/uy [ny][nx] (0 at solid nodes), force[2]
+ * = (F_x, F_y) at the final step, cd_cl[2], and wall_force[2], the same
+ * momentum-exchange sum over the links into the channel walls (not a
+ * quantity of interest: it closes the global momentum balance in tests).  */
+int oracle_channel_run(int nx, int ny, int xbc, int D, int cx, int cy, double nu, double u_peak, long ramp,
+                       long steps, double ux_init, double *f_out, double *rho_out, double *ux_out, double *uy_out,
+                       double *force, double *cd_cl, double *wall_force) {
+    channel c;
+    c.nx = nx;
+    c.ny = ny;
+    c.xbc = xbc;
+    c.D = D;
+    c.cx = cx;
+    c.cy = cy;
+    c.tau = nu / CS2 + 0.5;
+    c.u_peak = u_peak;
+    c.ramp = ramp;
+    if (!(c.tau > 0.5) || nx < 2 || ny < 3) return -1;
+    long n = (long)nx * ny;
+    c.solid = calloc((size_t)n, 1);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) c.solid[(long)y * nx + x] = (unsigned char)ch_cyl(&c, x, y);
+    double *f = calloc((size_t)(9 * n), sizeof(double)), *fs = calloc((size_t)(9 * n), sizeof(double));
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (c.solid[(long)y * nx + x]) continue;
+            for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = feq(i, 1.0, ux_init, 0.0);
+        }
+    for (long t = 0; t < steps; ++t) channel_step(&c, t, f, fs);
+
+    nsum Fx = {0, 0}, Fy = {0, 0}, Wx = {0, 0}, Wy = {0, 0};
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long cc = (long)y * nx + x;
+            if (c.solid[cc]) {
+                if (rho_out) rho_out[cc] = 0.0;
+                if (ux_out) ux_out[cc] = 0.0;
+                if (uy_out) uy_out[cc] = 0.0;
+                continue;
+            }
+            double a[9], b[9], rho, ux, uy;
+            for (int i = 0; i < 9; ++i) a[i] = f[idx(i, y, x, nx, ny)];
+            moments(a, &rho, &ux, &uy);
+            if (rho_out) rho_out[cc] = rho;
+            if (ux_out) ux_out[cc] = ux;
+            if (uy_out) uy_out[cc] = uy;
+            collide(a, c.tau, b);
+            for (int i = 1; i < 9; ++i) {
+                /* link x -> x + c_i is a bounce-back link iff the pull of
+                 * direction opp(i) at x has its source there                */
+                int xs = 0, ys = 0;
+                if (ch_source(&c, x, y, OPP(i), &xs, &ys) != 1) continue;
+                int xn = x + CX[i], yn = y + CY[i];
+                int into_cyl = xn >= 0 && xn < nx && yn >= 0 && yn < ny && c.solid[(long)yn * nx + xn];
+                if (into_cyl) {
+                    nadd(&Fx, 2.0 * CX[i] * b[i]);
+                    nadd(&Fy, 2.0 * CY[i] * b[i]);
+                } else {
+                    nadd(&Wx, 2.0 * CX[i] * b[i]);
+                    nadd(&Wy, 2.0 * CY[i] * b[i]);
+                }
+            }
+        }
+    double fx = nval(&Fx), fy = nval(&Fy);
+    if (force) {
+        force[0] = fx;
+        force[1] = fy;
+    }
+    if (wall_force) {
+        wall_force[0] = nval(&Wx);
+        wall_force[1] = nval(&Wy);
+    }
+    if (cd_cl) {
+        double q = 1.0 * u_peak * u_peak * (double)D;
+        cd_cl[0] = D > 0 ? 2.0 * fx / q : 0.0;
+        cd_cl[1] = D > 0 ? 2.0 * fy / q : 0.0;
+    }
+    if (f_out) memcpy(f_out, f, sizeof(double) * 9 * n);
+    free(c.solid);
+    free(f);
+    free(fs);
+    return 0;
+}
+
+/* Count of solid cylinder nodes, for geometry checks. */
+long oracle_cylinder_nodes(int nx, int ny, int D, int cx, int cy) {
+    channel c;
+    memset(&c, 0, sizeof c);
+    c.D = D;
+    c.cx = cx;
+    c.cy = cy;
+    long s = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) s += ch_cyl(&c, x, y);
+    return s;
+}

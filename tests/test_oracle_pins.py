@@ -1,0 +1,383 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, library routines, exact conservation laws and symmetries, values the
+paper prints (tests/golden), or brute force. None of them touches the GPU.
+"""
+import os
+from math import comb, exp, pi, sqrt
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- lattice
+
+def test_d2q9_isotropy_and_opposites():
+    # velocity set and weights (Sec. LBM, Eq. weightsDdQ9): the weights must
+    # reproduce the lattice moments of a Maxwellian with c_s^2 = 1/3
+    cx, cy, w, opp = O.d2q9()
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert abs((w * cx).sum()) < 1e-15 and abs((w * cy).sum()) < 1e-15
+    assert abs((w * cx * cx).sum() - 1 / 3) < 1e-15
+    assert abs((w * cy * cy).sum() - 1 / 3) < 1e-15
+    assert abs((w * cx * cy).sum()) < 1e-15
+    # fourth-order isotropy: sum w c_a^4 = 3 cs^4, sum w cx^2 cy^2 = cs^4
+    assert abs((w * cx ** 4).sum() - 1 / 3) < 1e-15
+    assert abs((w * cx ** 2 * cy ** 2).sum() - 1 / 9) < 1e-15
+    assert sorted(zip(cx.tolist(), cy.tolist())) == sorted((a, b) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    for i in range(9):
+        assert cx[opp[i]] == -cx[i] and cy[opp[i]] == -cy[i]
+    # groups of the paper: rest, four axis speeds, four diagonals
+    assert (cx[0], cy[0]) == (0, 0)
+    assert all(abs(cx[i]) + abs(cy[i]) == 1 for i in range(1, 5))
+    assert all(abs(cx[i]) == 1 and abs(cy[i]) == 1 for i in range(5, 9))
+    assert np.allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("rho,ux,uy", [(1.0, 0.0, 0.0), (1.02, 0.05, -0.03), (0.97, -0.1, 0.08)])
+def test_equilibrium_moments(rho, ux, uy):
+    # Eq. equilibrium: zeroth, first and second moments of f^eq
+    cx, cy, w, _ = O.d2q9()
+    f = O.feq(rho, ux, uy)
+    assert abs(f.sum() - rho) < 1e-14
+    assert abs((cx * f).sum() - rho * ux) < 1e-14
+    assert abs((cy * f).sum() - rho * uy) < 1e-14
+    assert abs((cx * cx * f).sum() - (rho / 3 + rho * ux * ux)) < 1e-14
+    assert abs((cy * cy * f).sum() - (rho / 3 + rho * uy * uy)) < 1e-14
+    assert abs((cx * cy * f).sum() - rho * ux * uy) < 1e-14
+
+
+def test_collision_invariants_and_fixed_point():
+    # Eq. bgkCollision conserves mass and momentum; f^eq is a fixed point
+    cx, cy, w, _ = O.d2q9()
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        f = O.feq(1.0, 0.03, -0.02) + 1e-3 * rng.standard_normal(9)
+        tau = 0.5 + rng.uniform(0.01, 1.0)
+        g = O.collide(f, tau)
+        assert abs(g.sum() - f.sum()) < 1e-14
+        assert abs((cx * g).sum() - (cx * f).sum()) < 1e-15
+        assert abs((cy * g).sum() - (cy * f).sum()) < 1e-15
+        # tau = 1 lands exactly on the equilibrium of the same moments
+        rho = f.sum()
+        e = O.feq(rho, (cx * f).sum() / rho, (cy * f).sum() / rho)
+        assert np.allclose(O.collide(f, 1.0), e, atol=1e-15)
+    e = O.feq(1.01, 0.02, 0.01)
+    assert np.allclose(O.collide(e, 0.73), e, atol=1e-16)
+
+
+def test_table1_units_golden():
+    # Table tab:simulation_parameters: tau, dx, dt from n, Ma, Re pin
+    # c_s^2 = 1/3 and tau = nu/c_s^2 + 1/2. The table prints 6 decimals, some
+    # rounded and some truncated, so the bar is one unit of the last decimal
+    # (c_s^2 = 1/2 would miss tau by 4e-4 already at n = 8).
+    rows = np.loadtxt(os.path.join(GOLDEN, "table1_tgv_units.txt"), comments="#")
+    for N, n, Ma, Re, tau, dx, dt in rows:
+        t, h, k = O.table1_units(int(n), Ma, Re)
+        assert abs(t - tau) < 1e-6, (n, t, tau)
+        assert abs(h - dx) < 1e-6, (n, h, dx)
+        assert abs(k - dt) < 1e-6, (n, k, dt)
+
+
+# ---------------------------------------------------------------- quadrature
+
+def test_gauss_legendre_closed_forms():
+    x, w = O.gauss_legendre(1)
+    assert x[0] == 0.0 and abs(w[0] - 2.0) < 1e-15
+    x, w = O.gauss_legendre(2)
+    assert np.allclose(x, [-1 / sqrt(3), 1 / sqrt(3)], atol=1e-16) and np.allclose(w, [1, 1], atol=1e-15)
+    x, w = O.gauss_legendre(3)
+    assert np.allclose(x, [-sqrt(0.6), 0.0, sqrt(0.6)], atol=1e-16)
+    assert np.allclose(w, [5 / 9, 8 / 9, 5 / 9], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 5, 8, 11, 16, 24])
+def test_gauss_legendre_vs_numpy_and_exactness(n):
+    x, w = O.gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.allclose(x, xr, atol=2e-15) and np.allclose(w, wr, atol=2e-15)
+    # exact on monomials up to degree 2n-1: int_{-1}^{1} x^m dx
+    for m in range(2 * n):
+        exact = 0.0 if m % 2 else 2.0 / (m + 1)
+        assert abs((w * x ** m).sum() - exact) < 1e-13
+
+
+def test_gl_tensor_layout_and_weights():
+    xi, a = O.gl_tensor(3, 4)
+    x1, w1 = np.polynomial.legendre.leggauss(4)
+    assert xi.shape == (64, 3) and abs(a.sum() - 1.0) < 1e-15
+    # dimension 0 varies slowest
+    for j in range(64):
+        m0, m1, m2 = j // 16, (j // 4) % 4, j % 4
+        assert np.allclose(xi[j], [x1[m0], x1[m1], x1[m2]], atol=1e-15)
+        assert abs(a[j] - w1[m0] * w1[m1] * w1[m2] / 8) < 1e-16
+
+
+def test_multi_indices_order_and_count():
+    al = O.multi_indices(2, 2)
+    assert al.tolist() == [[0, 0], [1, 0], [0, 1], [2, 0], [1, 1], [0, 2]]
+    for d, P in [(1, 4), (2, 7), (4, 3), (3, 5)]:
+        al = O.multi_indices(d, P)
+        assert al.shape == (comb(d + P, P), d)
+        deg = al.sum(1)
+        assert (np.diff(deg) >= 0).all() and deg.max() == P
+        assert len({tuple(r) for r in al.tolist()}) == al.shape[0]
+        for g in range(P + 1):
+            rows = [tuple(r) for r in al[deg == g].tolist()]
+            assert rows == sorted(rows, reverse=True)
+
+
+def test_orthonormal_legendre_vs_numpy():
+    xs = np.linspace(-1, 1, 13)
+    for n in range(9):
+        c = np.zeros(n + 1)
+        c[n] = 1.0
+        ref = sqrt(2 * n + 1) * np.polynomial.legendre.legval(xs, c)
+        got = np.array([O.legendre_orthonormal(n, x) for x in xs])
+        assert np.allclose(got, ref, atol=1e-13)
+
+
+def test_discrete_orthonormality():
+    # E[Phi_k Phi_l] = delta_kl (gamma_k = 1) under a rule exact to degree 2P
+    for d, P, n in [(1, 4, 5), (2, 3, 4), (4, 3, 4)]:
+        xi, a = O.gl_tensor(d, n)
+        al = O.multi_indices(d, P)
+        phi = O.phi_table(xi, al)
+        G = phi.T @ (a[:, None] * phi)
+        assert np.allclose(G, np.eye(al.shape[0]), atol=1e-12)
+
+
+def test_gpc_projection_exact_on_polynomials():
+    # Eq. coef_discrete / gpc_mean / gpc_std on closed forms
+    xi, a = O.gl_tensor(1, 3)
+    al = O.multi_indices(1, 2)
+    st = O.gpc_stats(xi[:, 0] ** 2, a, O.phi_table(xi, al))
+    c = st["coeffs"][:, 0]
+    assert abs(c[0] - 1 / 3) < 1e-15 and abs(c[1]) < 1e-15 and abs(c[2] - 2 / (3 * sqrt(5))) < 1e-15
+    assert abs(st["var"][0] - 4 / 45) < 1e-15 and abs(st["mean"][0] - 1 / 3) < 1e-15
+    xi, a = O.gl_tensor(2, 3)
+    al = O.multi_indices(2, 2)
+    st = O.gpc_stats(xi[:, 0] * xi[:, 1], a, O.phi_table(xi, al))
+    c = st["coeffs"][:, 0]
+    k11 = [r.tolist() for r in al].index([1, 1])
+    assert abs(c[k11] - 1 / 3) < 1e-15
+    assert np.abs(np.delete(c, k11)).max() < 1e-15
+    assert abs(st["var"][0] - 1 / 9) < 1e-15
+
+
+def test_gpc_recovers_random_expansion():
+    # a random expansion built with numpy's Legendre routine is recovered
+    # coefficient by coefficient; variance = sum of non-constant squares
+    rng = np.random.default_rng(11)
+    d, P, n = 3, 3, 4
+    al = O.multi_indices(d, P)
+    coef = rng.standard_normal(al.shape[0])
+    xi, a = O.gl_tensor(d, n)
+
+    def phi_np(k, z):
+        v = 1.0
+        for m in range(d):
+            cc = np.zeros(al[k, m] + 1)
+            cc[-1] = 1.0
+            v = v * sqrt(2 * al[k, m] + 1) * np.polynomial.legendre.legval(z[:, m], cc)
+        return v
+
+    M = sum(coef[k] * phi_np(k, xi) for k in range(al.shape[0]))
+    st = O.gpc_stats(M, a, O.phi_table(xi, al))
+    assert np.allclose(st["coeffs"][:, 0], coef, atol=1e-12)
+    assert abs(st["var"][0] - (coef[1:] ** 2).sum()) < 1e-11
+    # full-rank tensor rule with P = n-1 in 1-D: Parseval, var == quadrature var
+    xi1, a1 = O.gl_tensor(1, 6)
+    st1 = O.gpc_stats(np.exp(xi1[:, 0]), a1, O.phi_table(xi1, O.multi_indices(1, 5)))
+    assert abs(st1["var"][0] - st1["var_alt"][0]) < 1e-14
+
+
+# ---------------------------------------------------------------- Monte Carlo
+
+def test_mc_stats_vs_numpy():
+    rng = np.random.default_rng(3)
+    M = 5 + rng.standard_normal((257, 7))
+    st = O.mc_stats(M)
+    assert np.allclose(st["mean"], M.mean(0), rtol=1e-14)
+    assert np.allclose(st["var"], M.var(0, ddof=1), rtol=1e-12)
+    assert np.allclose(st["var_alt"], M.var(0, ddof=0), rtol=1e-12)
+
+
+def test_splitmix64_stream_and_points():
+    # the sample matrix is the generator stream, top 53 bits, row-major
+    seed, N, d = 123456, 300, 4
+    raw = O.splitmix64_stream(seed, N * d)
+    xi, a = O.mc_points(seed, N, d)
+    u = (raw >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    assert np.array_equal(xi.reshape(-1), 2.0 * u - 1.0)
+    assert np.all(a == 1.0 / N)
+    # uniformity: mean 1/2, variance 1/12, no lag-1 correlation (4e5 draws)
+    big = O.splitmix64_stream(7, 400000)
+    v = (big >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    assert abs(v.mean() - 0.5) < 5 * sqrt(1 / 12 / v.size)
+    assert abs(v.var() - 1 / 12) < 2e-3
+    assert abs(np.corrcoef(v[:-1], v[1:])[0, 1]) < 1e-2
+    assert len(np.unique(big)) == big.size
+    # distinct seeds give distinct streams
+    assert not np.array_equal(O.splitmix64_stream(1, 8), O.splitmix64_stream(2, 8))
+
+
+def test_mc_rate_half():
+    # O(N^-1/2) (Sec. MC and QMC sampling): RMS error over 32 seeds
+    g = lambda z: np.exp(0.5 * z[:, 0] + 0.25 * z[:, 1])
+    exact = (np.sinh(0.5) / 0.5) * (np.sinh(0.25) / 0.25)  # E[e^{a z}] = sinh(a)/a
+    Ns = [256, 1024, 4096]
+    rms = []
+    for N in Ns:
+        errs = [O.mc_stats(g(O.mc_points(1000 + s, N, 2)[0]))["mean"][0] - exact for s in range(32)]
+        rms.append(sqrt(np.mean(np.square(errs))))
+    slope = np.polyfit(np.log(Ns), np.log(rms), 1)[0]
+    assert -0.65 < slope < -0.35, slope
+
+
+# ---------------------------------------------------------------- TGV solve
+
+def test_uniform_state_is_stationary():
+    r = O.tgv_run(12, 10, 0.02, 0.0, 25, want_f=True)
+    _, _, w, _ = O.d2q9()
+    # stationary to roundoff (sum of the weights is 1 only to an ulp)
+    assert np.abs(r["f"] - w[:, None, None]).max() < 1e-15
+
+
+def test_periodic_conservation():
+    cx, cy, w, _ = O.d2q9()
+    f0 = O.tgv_run(24, 20, 0.01, 0.05, 0, phase_x=0.3, phase_y=1.1, want_f=True)["f"]
+    f1 = O.tgv_run(24, 20, 0.01, 0.05, 400, phase_x=0.3, phase_y=1.1, want_f=True)["f"]
+    m0, m1 = f0.sum(), f1.sum()
+    assert abs(m1 - m0) / m0 < 1e-13
+    for c in (cx, cy):
+        p0 = (c[:, None, None] * f0).sum()
+        p1 = (c[:, None, None] * f1).sum()
+        assert abs(p1 - p0) < 1e-13 * m0
+
+
+def test_tgv_analytic_decay_and_second_order():
+    # Eq. TGV_vel: u ~ exp(-t/t_d), t_d = 1/(nu (kx^2+ky^2)), so the
+    # normalised energy (Eq. KineticEnergy) is exp(-4 nu k^2 t); the scheme
+    # converges to it at second order under diffusive scaling
+    errs = []
+    for n in (16, 32, 64):
+        nu, u0, T = 0.02, 0.04 * 16 / n, 100 * (n // 16) ** 2
+        k = 2 * pi / n
+        ex = exp(-4 * nu * k * k * T)
+        errs.append(abs(O.tgv_run(n, n, nu, u0, T)["ke"] - ex) / ex)
+    assert errs[-1] < 1e-2
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.8), orders
+
+
+def test_tgv_initial_field_matches_formula():
+    n, u0, px, py = 16, 0.03, 0.4, 2.0
+    r = O.tgv_run(n, n, 0.01, u0, 0, phase_x=px, phase_y=py)
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    k = 2 * pi / n
+    assert np.allclose(r["ux"], -u0 * np.cos(k * x + px) * np.sin(k * y + py), atol=1e-16)
+    assert np.allclose(r["uy"], u0 * np.sin(k * x + px) * np.cos(k * y + py), atol=1e-16)
+    p = -0.25 * u0 ** 2 * (np.cos(2 * (k * x + px)) + np.cos(2 * (k * y + py)))
+    assert np.allclose(r["rho"], 1 + 3 * p, atol=1e-15)
+
+
+def test_tgv_phase_is_translation():
+    # a phase of 2 pi m/n is a shift by m nodes, exactly
+    n, m = 20, 3
+    a = O.tgv_run(n, n, 0.01, 0.05, 150)
+    b = O.tgv_run(n, n, 0.01, 0.05, 150, phase_x=2 * pi * m / n)
+    assert np.allclose(b["ux"], np.roll(a["ux"], -m, axis=1), rtol=0, atol=1e-15)
+    assert np.allclose(b["uy"], np.roll(a["uy"], -m, axis=1), rtol=0, atol=1e-15)
+
+
+def test_tgv_transpose_symmetry():
+    # swapping x and y maps the vortex with amplitude u0 onto -u0
+    n = 16
+    A = O.tgv_run(n, n, 0.02, 0.05, 120)
+    B = O.tgv_run(n, n, 0.02, -0.05, 120)
+    assert np.allclose(B["ux"], A["uy"].T, rtol=0, atol=2e-15)
+    assert np.allclose(B["uy"], A["ux"].T, rtol=0, atol=2e-15)
+
+
+def test_config1_mean_energy_vs_closed_form():
+    # 5-point collocation of nu ~ U(0.008, 0.012) on 64^2, 1000 steps: the
+    # continuum E[K] = mean over nu of exp(-4 nu k^2 t) in closed form; the
+    # LBM differs by its O(k^2) error (~3e-3 here)
+    prob = dict(geometry="tgv", nx=64, ny=64, steps=1000, u0=0.01, nu=0.01,
+                dists=[("nu", 0.008, 0.012)], rule=dict(kind="gl", n=5, order=4))
+    r = O.run_problem(prob, qois=["ke"])
+    k = 2 * pi / 64
+    c = 4 * k * k * 1000
+    Ek = (exp(-c * 0.008) - exp(-c * 0.012)) / (c * 0.004)
+    Ek2 = (exp(-2 * c * 0.008) - exp(-2 * c * 0.012)) / (2 * c * 0.004)
+    st = r["stats"]["ke"]
+    assert abs(st["mean"][0] - Ek) / Ek < 1e-2
+    assert abs(st["var"][0] - (Ek2 - Ek * Ek)) / (Ek2 - Ek * Ek) < 3e-2
+    # the continuum moments are matched by the same 5-point rule to 1e-12
+    xi, a = O.gl_tensor(1, 5)
+    nus = 0.01 + 0.002 * xi[:, 0]
+    assert abs((a * np.exp(-c * nus)).sum() - Ek) < 1e-12
+
+
+# ---------------------------------------------------------------- channel
+
+def test_cylinder_mask_is_gauss_circle_count():
+    # integer points in a disc of radius 10 about a lattice point: 317
+    assert O.cylinder_nodes(440, 82, 20, 40, 41) == 317
+    assert O.cylinder_nodes(100, 100, 2, 50, 50) == 5
+
+
+def test_poiseuille_with_zou_he_and_halfway_walls():
+    # no cylinder: the steady flow is the inlet parabola, carried at constant
+    # mass flux, so rho u / rho_inlet equals the parabola at every column;
+    # half-way bounce-back is exact at tau = 1/2 + sqrt(3/16) for BGK
+    tau = 0.5 + sqrt(3 / 16)
+    nu = (tau - 0.5) / 3
+    nx, ny, up = 40, 21, 0.01
+    r = O.channel_run(nx, ny, nu, up, 12000, D=0, xbc=0)
+    yy = np.arange(ny) + 0.5
+    prof = 4 * up * yy * (ny - yy) / ny ** 2
+    assert np.allclose(r["ux"][:, 0], prof, rtol=1e-13, atol=0)
+    for x in (1, nx // 2, nx - 1):
+        u = r["ux"][:, x] * r["rho"][:, x] / r["rho"][:, 0]
+        assert np.linalg.norm(u - prof) / np.linalg.norm(prof) < 2e-4, x
+    assert abs(r["rho"][:, -1] - 1.0).max() < 1e-14
+
+
+def test_inlet_follows_ramp():
+    nx, ny, up, T = 30, 11, 0.02, 200
+    r = O.channel_run(nx, ny, 0.05, up, 50, D=0, ramp=T)
+    yy = np.arange(ny) + 0.5
+    s = np.sin(pi * 50 / (2 * T)) ** 2
+    assert np.allclose(r["ux"][:, 0], s * 4 * up * yy * (ny - yy) / ny ** 2, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("xbc", [1, 2])
+def test_momentum_exchange_closes_global_balance(xbc):
+    # closed or x-periodic channel with a cylinder: the change of total
+    # momentum over one step equals minus the momentum-exchange force on all
+    # bounce-back links (cylinder + walls); mass is conserved
+    cx, cy, _, _ = O.d2q9()
+    kw = dict(D=10, cx=20, cy=15, xbc=xbc, ux_init=0.05, want_f=True)
+    a = O.channel_run(60, 31, 0.05, 0.0, 50, **kw)
+    b = O.channel_run(60, 31, 0.05, 0.0, 51, **kw)
+    P = lambda f: np.array([(cx[:, None, None] * f).sum(), (cy[:, None, None] * f).sum()])
+    dP = P(b["f"]) - P(a["f"])
+    assert np.allclose(dP, -(a["force"] + a["wall_force"]), rtol=1e-12, atol=1e-12)
+    assert abs(b["f"].sum() - a["f"].sum()) < 1e-11
+    if xbc == 2:
+        assert a["force"][0] > 0  # in the periodic channel the body is pushed downstream
+
+
+def test_symmetric_cylinder_has_no_lift_and_quiescent_no_force():
+    r = O.channel_run(80, 41, 0.05, 0.05, 1500, D=10, cx=20, cy=20, ramp=400)
+    assert r["cd"] > 0 and abs(r["cl"]) < 1e-10 * r["cd"]
+    q = O.channel_run(40, 21, 0.05, 0.0, 100, D=8, cx=12, cy=10)
+    assert np.abs(q["force"]).max() < 1e-13
