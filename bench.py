@@ -1,0 +1,172 @@
+"""Benchmark of the batched LBM-UQ hot path on one MI355X.
+
+One benchmark step is one whole UQ job of the batched-collocation workload
+(Taylor-Green vortex 256^2, 4-D uniform inputs, 4^4 = 256 Gauss-Legendre
+samples, 5000 LBM steps in FP32 shifted populations, gPC order 3): create
+(sampling + equilibrium initialisation on the device), run all samples
+together, then the per-sample QoI reduction and the FP64 moments / gPC
+projection of the kinetic energy and of the velocity field.
+
+Prints one JSON line: aggregate MLUPS (value), the roofline of the dominant
+kernel (the stream-collide step, timed with HIP events on its own stream),
+and the FP64 oracle timed on host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16s": 2, "bf16s": 2}
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_13867_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_tgv256_fp32.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(bytes_alg_per_launch):
+    """HBM bytes per step launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, n_samples=4, lbm_steps=300):
+    """The FP64 oracle, single-threaded, on the full lattice of the workload
+    for a few samples and steps (about 10 s of CPU work)."""
+    import oracle as O
+
+    O.build()
+    xi, a = O.sample_set(spec)
+    t0 = time.perf_counter()
+    for j in range(n_samples):
+        O.solve_sample(spec, O.sample_params(spec, xi[j]), steps=lbm_steps)
+    dt = time.perf_counter() - t0
+    cells = spec["nx"] * spec["ny"]
+    mlups = n_samples * cells * lbm_steps / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n_samples} samples x {lbm_steps} steps on the full {spec['nx']}x{spec['ny']} lattice, "
+                      f"FP64 single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed UQ jobs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed UQ jobs")
+    ap.add_argument("--workload", default="tgv256_fp32_gl4x4")
+    ap.add_argument("--lbm-steps", type=int, default=None, help="override LBM steps per job")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU layout (sample sharding with one "
+              "all-reduce of the FP64 moment partial sums) is described in the design notes but not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_13867_amd as U
+    from paper_2508_13867_amd import workloads as W
+
+    spec = dict(W.WORKLOADS[args.workload])
+    if args.lbm_steps:
+        spec["steps"] = args.lbm_steps
+    prec = spec["precision"]
+    cells = spec["nx"] * spec["ny"]
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def one_job(timed_kernel):
+        job = U.Job(spec, device=0)
+        ms = job.run_timed(spec["steps"]) if timed_kernel else None
+        if not timed_kernel:
+            job.run(spec["steps"])
+        job.moments("ke")
+        job.moments("vel")
+        S = job.S
+        job.close()
+        return S, ms
+
+    log(f"bench: workload {spec['name']} warmup {args.warmup} jobs")
+    for _ in range(args.warmup):
+        one_job(False)
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} jobs")
+    kernel_ms = []
+    t0 = time.perf_counter()
+    S = 0
+    for k in range(args.steps):
+        S, ms = one_job(True)
+        kernel_ms.append(ms)
+        log(f"bench: job {k} done, step launches {ms:.1f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    wall = t1 - t0
+    updates = args.steps * S * cells * spec["steps"]
+    mlups = updates / wall / 1e6
+    ms_per_job = wall / args.steps * 1e3
+
+    # dominant kernel: one step launch updates S * cells nodes, 9 populations
+    # read + 9 written per node
+    bpn = 18 * BYTES_PER_POP[prec]
+    per_launch_ms = sum(kernel_ms) / (args.steps * spec["steps"])
+    alg_bytes = S * cells * bpn
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "uqi::k_step", "bytes_per_launch": alg_bytes, "launch_ms": round(per_launch_ms, 5),
+            "bytes_per_node_update": bpn}
+
+    out = {
+        "metric": "aggregate MLUPS & % HBM peak; UQ solves/hr + p50/p99 latency vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_job, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32", "bf16s": "bf16-storage/f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": spec["name"], "nx": spec["nx"], "ny": spec["ny"], "samples": S,
+                   "lbm_steps": spec["steps"], "rule": spec["rule"], "precision": prec,
+                   "moments": "FP64 compensated, KE + velocity field"},
+        "roofline": roof,
+        "uq_solves_per_hour": round(3600.0 / (wall / args.steps), 1),
+        "hbm_frac_of_peak": roof["frac"],
+    }
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

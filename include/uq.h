@@ -1,0 +1,248 @@
+/*
+ * uq.h -- C-ABI of the MI355X batched lattice-Boltzmann UQ library.
+ *
+ * The library runs the non-intrusive uncertainty-quantification method of
+ * OpenLB-UQ (arXiv 2508.13867): an ensemble of deterministic D2Q9 BGK solves,
+ * one per sample of the uncertain inputs (Sec. "Uncertainty quantification
+ * methods", Algorithm alg:uq_openlb), followed by Monte Carlo statistics
+ * (Eqs. meanMCS, varMCS) or the stochastic-collocation gPC projection
+ * (Eqs. coef_discrete, gpc_mean, gpc_std). All samples of a job advance
+ * together on one GPU; every step of the path runs in the library's HIP
+ * kernels for gfx950.
+ *
+ * Conventions for every call:
+ *  - Functions return uq_status; on failure uq_last_error() returns a
+ *    message for the calling thread. No C++ exception crosses the ABI.
+ *  - Host pointers are caller-owned; the library never keeps them past the
+ *    call. Device memory of a job is owned by the job and released by
+ *    uq_destroy().
+ *  - Calls on distinct jobs may be made from different threads. Calls on the
+ *    same job must not overlap.
+ *  - All quantities are in lattice units (dx = dt = 1).
+ */
+#ifndef UQ_LBM_H
+#define UQ_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UQ_OK = 0,
+    UQ_EINVAL = 1,    /* invalid argument (tau <= 1/2, bad sizes, bad enum) */
+    UQ_ENOMEM = 2,    /* device allocation failed / job can never fit       */
+    UQ_EAGAIN = 3,    /* not finished yet (server polling)                  */
+    UQ_EUNSTABLE = 4, /* a sample produced a non-finite value               */
+    UQ_EDEVICE = 5,   /* a HIP runtime call failed                          */
+    UQ_ESTATE = 6     /* call not valid in the object's current state       */
+} uq_status;
+
+/* Storage precision of the populations. Collision always runs on shifted
+ * populations f_i - w_i; FP64 computes in double, the others in float. */
+typedef enum {
+    UQ_FP64 = 0,  /* double storage, double compute                        */
+    UQ_FP32 = 1,  /* float storage, float compute                          */
+    UQ_FP16S = 2, /* IEEE half storage scaled by 2^s per job, float compute */
+    UQ_BF16S = 3  /* bfloat16 storage scaled by 2^s per job, float compute  */
+} uq_precision;
+
+/* Deterministic problem solved for every sample. */
+typedef enum {
+    /* Taylor-Green vortex on a fully periodic nx x ny lattice (Sec. "Taylor--
+     * Green vortex flow with uncertain viscosity", Eqs. TGV_vel, TGV_press):
+     * u = u0(-cos(kx+px) sin(ky+py), sin(kx+px) cos(ky+py)), k = 2 pi/n,
+     * rho = 1 + 3p, equilibrium start. */
+    UQ_GEOM_TGV = 0,
+    /* Channel of nx x ny nodes with half-way bounce-back walls at y = -1/2
+     * and y = ny - 1/2, an optional solid cylinder of diameter D centred on
+     * node (cx, cy), and an x boundary chosen by `xbc` (Sec. "Flow past a
+     * circular cylinder with uncertain inlet velocity"). */
+    UQ_GEOM_CHANNEL = 1
+} uq_geometry;
+
+typedef enum {
+    UQ_XBC_ZOUHE = 0,   /* Zou-He parabolic velocity inlet at x = 0 and Zou-He
+                           pressure outlet (rho = 1) at x = nx-1            */
+    UQ_XBC_WALLS = 1,   /* half-way bounce-back walls at x = -1/2, nx - 1/2 */
+    UQ_XBC_PERIODIC = 2 /* periodic in x                                    */
+} uq_xbc;
+
+/* Input that an uncertain variable drives. */
+typedef enum {
+    UQ_T_NU = 0,      /* kinematic viscosity; tau = 3 nu + 1/2             */
+    UQ_T_U0 = 1,      /* TGV velocity amplitude                            */
+    UQ_T_PHASE_X = 2, /* TGV phase shift in x (radians)                    */
+    UQ_T_PHASE_Y = 3, /* TGV phase shift in y                              */
+    UQ_T_RE = 4,      /* channel Reynolds number; nu = u_peak_nominal D/Re */
+    UQ_T_U_PEAK = 5   /* channel peak inflow velocity                      */
+} uq_target;
+
+/* One independent uniform input U(lo, hi) (Sec. "Distribution and
+ * polynomial basis"); its reference variable xi on [-1, 1] maps to
+ * lo + (hi - lo)(xi + 1)/2. */
+typedef struct {
+    int32_t target; /* uq_target */
+    double lo, hi;
+} uq_dist;
+
+typedef enum {
+    /* Tensor Gauss-Legendre collocation with n_per_dim nodes per input and
+     * weights of the probability measure (sum 1), dimension 0 varying
+     * slowest; gPC of total degree <= order in graded order (Sec. "Quadrature
+     * and collocation", SC-gPC procedure). */
+    UQ_RULE_GL_TENSOR = 0,
+    /* Monte Carlo: mc_n i.i.d. draws from SplitMix64 seeded with `seed`; draw
+     * number c = j*d + k + 1 feeds sample j, input k (Sec. "Monte Carlo and
+     * quasi Monte Carlo sampling"). */
+    UQ_RULE_MC = 1
+} uq_rule;
+
+#define UQ_MAX_DIMS 8
+
+typedef struct {
+    int32_t geometry;  /* uq_geometry */
+    int32_t precision; /* uq_precision */
+    int32_t nx, ny;    /* lattice nodes, >= 2 (TGV) / nx >= 2, ny >= 3 (channel) */
+    /* nominal (deterministic) inputs */
+    double nu;               /* viscosity (both geometries unless driven)          */
+    double u0;               /* TGV amplitude; also the energy normalisation       */
+    double phase_x, phase_y; /* TGV phases                                        */
+    double u_peak;           /* channel peak inflow velocity (also in Re -> nu)   */
+    int32_t D, cx, cy;       /* cylinder diameter (0 = none) and centre node     */
+    int32_t xbc;             /* uq_xbc                                           */
+    int64_t ramp;            /* inflow ramp length T_r: s(t) = sin^2(pi t/(2T_r)) */
+    /* uncertain inputs */
+    int32_t n_dists;
+    uq_dist dists[UQ_MAX_DIMS];
+    /* sampling / collocation rule */
+    int32_t rule;      /* uq_rule */
+    int32_t n_per_dim; /* GL: nodes per input                               */
+    int32_t order;     /* GL: total gPC degree P (K = C(d+P, P) terms)      */
+    int64_t mc_n;      /* MC: number of samples                             */
+    uint64_t seed;     /* MC: generator seed                                */
+} uq_problem;
+
+/* Device context. `stream` is a hipStream_t (e.g. torch's current stream,
+ * NULL = the null stream). When `alloc`/`free` are NULL the library uses
+ * hipMalloc/hipFree; otherwise every device buffer of a job comes from
+ * alloc(bytes, ctx) (256-byte aligned) and goes back through free(ptr, ctx). */
+typedef void *(*uq_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*uq_free_fn)(void *ptr, void *ctx);
+typedef struct {
+    int32_t device;
+    void *stream;
+    uq_alloc_fn alloc;
+    uq_free_fn free;
+    void *ctx;
+} uq_device;
+
+typedef struct uq_job uq_job;
+
+/* Quantities of interest. */
+typedef enum {
+    /* normalised total kinetic energy K = 2/(nx ny u0^2) sum (u^2 + v^2)
+     * over fluid nodes, u0 the nominal amplitude (Eq. KineticEnergy).    */
+    UQ_QOI_KE = 0,
+    /* velocity field, n_out = 2 nx ny: all u_x in row-major [ny][nx], then
+     * all u_y; 0 at solid nodes (Fig. velocity_stats statistics).        */
+    UQ_QOI_VEL = 1,
+    /* drag / lift coefficient 2F/(u_peak^2 D) from momentum exchange on the
+     * cylinder links, F = sum 2 c_i f*_i over links into the cylinder, with
+     * the sample's u_peak (Eqs. dragForce, liftForce, C_D, C_L).         */
+    UQ_QOI_CD = 2,
+    UQ_QOI_CL = 3,
+    /* density field [ny][nx], 0 at solid nodes */
+    UQ_QOI_RHO = 4
+} uq_qoi;
+
+/* Statistics of one QoI over the samples, caller-owned host buffers; any
+ * pointer may be NULL to skip that output. n_out and K are filled in.
+ *   mean[n_out]      MC: Eq. meanMCS; SC: coefficient 0 (Eq. gpc_mean)
+ *   var[n_out]       MC: Eq. varMCS (1/(N-1)); SC: sum_{k>=1} c_k^2 (Eq. gpc_std)
+ *   var_alt[n_out]   MC: the 1/N variance of Algorithm alg:uq_openlb;
+ *                    SC: quadrature variance sum_j a_j (M_j - mean)^2
+ *   coeffs[K*n_out]  SC only: c_k for k = 0..K-1, row k at coeffs + k*n_out
+ *   alpha[K*d]       SC only: multi-index of term k at alpha + k*d          */
+typedef struct {
+    int64_t n_out;
+    int32_t K;
+    int32_t d;
+    double *mean;
+    double *var;
+    double *var_alt;
+    double *coeffs;
+    int32_t *alpha;
+} uq_moments_out;
+
+typedef struct {
+    int64_t S;          /* samples                                     */
+    int32_t d;          /* uncertain inputs                            */
+    int32_t K;          /* gPC terms (0 for MC)                        */
+    int64_t steps_done; /* LBM steps taken so far                      */
+    int64_t pitch;      /* row pitch of a population plane (elements)  */
+    int64_t device_bytes; /* device memory held by the job            */
+    int32_t scale_exp;  /* FP16S/BF16S storage scale 2^scale_exp       */
+    int32_t fluid_nodes;
+} uq_job_info;
+
+/* Set up a job: sample the inputs, map each sample to its solver parameters,
+ * allocate the population slab and initialise every sample to equilibrium
+ * (enqueued on dev->stream). The problem is copied. */
+uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job **out);
+
+/* Sample matrix and weights (getSamplingPoints of the paper's user API).
+ * xi: [S*d] reference variables in [-1,1], a: [S] weights. Any pointer may
+ * be NULL; S and d are returned through the pointers if not NULL. */
+uq_status uq_samples(const uq_job *job, double *xi, double *a, int64_t *S, int32_t *d);
+
+/* Advance all samples by `steps` LBM steps (fused stream + collide with the
+ * boundaries inline, one launch per step). Asynchronous on the job's stream;
+ * steps >= 0. */
+uq_status uq_run(uq_job *job, int64_t steps);
+
+/* uq_run followed by a wait, with the elapsed device time of the step
+ * launches measured by HIP events on the job's stream: *ms receives the
+ * total over the `steps` steps (divide by steps for the average launch
+ * duration of the step kernel). Blocking. */
+uq_status uq_run_timed(uq_job *job, int64_t steps, double *ms);
+
+/* Wait for all work of the job. */
+uq_status uq_sync(uq_job *job);
+
+/* Per-sample QoI values at the current step, computed on the device and
+ * copied to out[S * n_out] (sample-major). *n_out receives values per
+ * sample. out may be NULL to query n_out. Blocking. */
+uq_status uq_qoi_samples(uq_job *job, int32_t qoi, double *out, int64_t *n_out);
+
+/* Statistics of a QoI at the current step: per-sample reduction, then the
+ * cross-sample moments / gPC projection in compensated FP64, all on the
+ * device; results copied to the caller's buffers. Blocking. Returns
+ * UQ_EUNSTABLE if any sample holds a non-finite value. */
+uq_status uq_moments(uq_job *job, int32_t qoi, uq_moments_out *out);
+
+/* Populations f_i(x, t) of one sample in natural order [9][ny][nx], unshifted
+ * and in double, for inspection and tests (solid nodes hold 0). Blocking. */
+uq_status uq_populations(uq_job *job, int64_t sample, double *out);
+
+uq_status uq_job_get_info(const uq_job *job, uq_job_info *info);
+
+/* Release every device buffer of the job (after its stream is idle). */
+void uq_destroy(uq_job *job);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *uq_last_error(void);
+
+/* Host-only helpers (no device needed): the job's sample set and basis,
+ * for callers that want the rule without creating a job.
+ *   uq_rule_size: S and K of a problem.
+ *   uq_rule_points: xi [S*d], a [S], alpha [K*d], phi [S*K]; any may be NULL. */
+uq_status uq_rule_size(const uq_problem *p, int64_t *S, int32_t *K);
+uq_status uq_rule_points(const uq_problem *p, double *xi, double *a, int32_t *alpha, double *phi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UQ_LBM_H */

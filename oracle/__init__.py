@@ -276,8 +276,9 @@ def solve_sample(problem, params, steps=None):
                     ke_u0=problem["u0"])
         return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
     if problem["geometry"] == "channel":
-        r = channel_run(nx, ny, params["nu"], params["u_peak"], steps, D=problem["D"], cx=problem["cx"],
-                        cy=problem["cy"], ramp=problem.get("ramp", 0), xbc=problem.get("xbc", 0))
+        xbc = {"zouhe": 0, "walls": 1, "periodic": 2}.get(problem.get("xbc", 0), problem.get("xbc", 0))
+        r = channel_run(nx, ny, params["nu"], params["u_peak"], steps, D=problem.get("D", 0),
+                        cx=problem.get("cx", 0), cy=problem.get("cy", 0), ramp=problem.get("ramp", 0), xbc=xbc)
         return {"cd": r["cd"], "cl": r["cl"], "fx": r["force"][0], "fy": r["force"][1],
                 "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
     raise ValueError(problem["geometry"])

@@ -1,0 +1,286 @@
+"""ctypes binding of include/uq.h (argument marshalling only).
+
+Every computation happens in libuqlbm.so; this module only converts Python
+values to the C structs, hands torch-allocated device memory and torch's
+current stream to the library, and copies results into numpy arrays. If the
+library is missing it raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libuqlbm.so")
+
+UQ_OK, UQ_EINVAL, UQ_ENOMEM, UQ_EAGAIN, UQ_EUNSTABLE, UQ_EDEVICE, UQ_ESTATE = range(7)
+STATUS_NAMES = {0: "UQ_OK", 1: "UQ_EINVAL", 2: "UQ_ENOMEM", 3: "UQ_EAGAIN", 4: "UQ_EUNSTABLE",
+                5: "UQ_EDEVICE", 6: "UQ_ESTATE"}
+PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}
+GEOMETRY = {"tgv": 0, "channel": 1}
+XBC = {0: 0, 1: 1, 2: 2, "zouhe": 0, "walls": 1, "periodic": 2}
+TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5}
+RULE = {"gl": 0, "mc": 1}
+QOI = {"ke": 0, "vel": 1, "cd": 2, "cl": 3, "rho": 4}
+MAX_DIMS = 8
+
+
+class UQError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dist(C.Structure):
+    _fields_ = [("target", C.c_int32), ("lo", C.c_double), ("hi", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("geometry", C.c_int32), ("precision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("nu", C.c_double), ("u0", C.c_double), ("phase_x", C.c_double), ("phase_y", C.c_double),
+        ("u_peak", C.c_double), ("D", C.c_int32), ("cx", C.c_int32), ("cy", C.c_int32), ("xbc", C.c_int32),
+        ("ramp", C.c_int64), ("n_dists", C.c_int32), ("dists", Dist * MAX_DIMS), ("rule", C.c_int32),
+        ("n_per_dim", C.c_int32), ("order", C.c_int32), ("mc_n", C.c_int64), ("seed", C.c_uint64),
+    ]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Device(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("ctx", C.c_void_p)]
+
+
+class MomentsOut(C.Structure):
+    _fields_ = [("n_out", C.c_int64), ("K", C.c_int32), ("d", C.c_int32), ("mean", C.c_void_p),
+                ("var", C.c_void_p), ("var_alt", C.c_void_p), ("coeffs", C.c_void_p), ("alpha", C.c_void_p)]
+
+
+class JobInfo(C.Structure):
+    _fields_ = [("S", C.c_int64), ("d", C.c_int32), ("K", C.c_int32), ("steps_done", C.c_int64),
+                ("pitch", C.c_int64), ("device_bytes", C.c_int64), ("scale_exp", C.c_int32),
+                ("fluid_nodes", C.c_int32)]
+
+
+# every symbol the header declares, with its signature
+_P = C.c_void_p
+SIGNATURES = {
+    "uq_create": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.POINTER(_P)]),
+    "uq_samples": (C.c_int, [_P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "uq_run": (C.c_int, [_P, C.c_int64]),
+    "uq_run_timed": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_double)]),
+    "uq_sync": (C.c_int, [_P]),
+    "uq_qoi_samples": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int64)]),
+    "uq_moments": (C.c_int, [_P, C.c_int32, C.POINTER(MomentsOut)]),
+    "uq_populations": (C.c_int, [_P, C.c_int64, _P]),
+    "uq_job_get_info": (C.c_int, [_P, C.POINTER(JobInfo)]),
+    "uq_destroy": (None, [_P]),
+    "uq_last_error": (C.c_char_p, []),
+    "uq_rule_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "uq_rule_points": (C.c_int, [C.POINTER(Problem), _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libuqlbm.so (built in-tree by paper_2508_13867_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_2508_13867_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != UQ_OK:
+        raise UQError(status, lib().uq_last_error().decode())
+
+
+def make_problem(spec: dict) -> Problem:
+    """Marshal a problem dict (keys as in workloads.py) into the C struct."""
+    p = Problem()
+    p.geometry = GEOMETRY[spec["geometry"]]
+    p.precision = PRECISION[spec.get("precision", "fp32")]
+    p.nx, p.ny = int(spec["nx"]), int(spec["ny"])
+    p.nu = float(spec.get("nu", 0.0))
+    p.u0 = float(spec.get("u0", 0.0))
+    p.phase_x = float(spec.get("phase_x", 0.0))
+    p.phase_y = float(spec.get("phase_y", 0.0))
+    p.u_peak = float(spec.get("u_peak", 0.0))
+    p.D = int(spec.get("D", 0))
+    p.cx = int(spec.get("cx", 0))
+    p.cy = int(spec.get("cy", 0))
+    p.xbc = XBC[spec.get("xbc", 0)]
+    p.ramp = int(spec.get("ramp", 0))
+    dists = spec.get("dists", [])
+    if len(dists) > MAX_DIMS:
+        raise ValueError("too many uncertain inputs")
+    p.n_dists = len(dists)
+    for k, (t, lo, hi) in enumerate(dists):
+        p.dists[k].target = TARGET[t]
+        p.dists[k].lo = float(lo)
+        p.dists[k].hi = float(hi)
+    r = spec["rule"]
+    p.rule = RULE[r["kind"]]
+    p.n_per_dim = int(r.get("n", 0))
+    p.order = int(r.get("order", 0))
+    p.mc_n = int(r.get("N", 0))
+    p.seed = int(r.get("seed", 123456))
+    return p
+
+
+def rule_points(spec: dict):
+    """Host-only: the sample set (xi, a) and, for collocation, alpha and Phi."""
+    p = make_problem(spec)
+    S, K = C.c_int64(), C.c_int32()
+    check(lib().uq_rule_size(C.byref(p), C.byref(S), C.byref(K)))
+    d = p.n_dists
+    xi = np.zeros((S.value, d))
+    a = np.zeros(S.value)
+    alpha = np.zeros((K.value, d), np.int32)
+    phi = np.zeros((S.value, K.value))
+    check(lib().uq_rule_points(C.byref(p), xi.ctypes.data, a.ctypes.data, alpha.ctypes.data, phi.ctypes.data))
+    return xi, a, alpha, phi
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator."""
+
+    def __init__(self, device: int):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self._alloc = ALLOC_FN(self.alloc)
+        self._free = FREE_FN(self.free)
+
+    def alloc(self, nbytes, ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        except Exception:
+            return None
+        ptr = t.data_ptr()
+        self.live[ptr] = t
+        return ptr
+
+    def free(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+
+def torch_device(device: int = 0, stream=None, allocator=True):
+    """uq_device for `device`, torch's current stream and torch memory."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the library runs only on an MI355X (gfx950)")
+    dev = Device()
+    dev.device = device
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    dev.stream = C.c_void_p(s.cuda_stream)
+    keep = None
+    if allocator:
+        keep = TorchAllocator(device)
+        dev.alloc = keep._alloc
+        dev.free = keep._free
+    else:
+        dev.alloc = ALLOC_FN()
+        dev.free = FREE_FN()
+    dev.ctx = None
+    return dev, keep
+
+
+class Job:
+    """One UQ job (uq_create ... uq_destroy)."""
+
+    def __init__(self, spec: dict, device: int = 0, stream=None, torch_memory: bool = True):
+        self.spec = dict(spec)
+        self._dev, self._keep = torch_device(device, stream, torch_memory)
+        p = make_problem(spec)
+        h = C.c_void_p()
+        check(lib().uq_create(C.byref(p), C.byref(self._dev), C.byref(h)))
+        self.h = h
+        info = self.info()
+        self.S, self.d, self.K = info.S, info.d, info.K
+
+    def info(self) -> JobInfo:
+        inf = JobInfo()
+        check(lib().uq_job_get_info(self.h, C.byref(inf)))
+        return inf
+
+    def samples(self):
+        xi = np.zeros((self.S, self.d))
+        a = np.zeros(self.S)
+        check(lib().uq_samples(self.h, xi.ctypes.data, a.ctypes.data, None, None))
+        return xi, a
+
+    def run(self, steps: int):
+        check(lib().uq_run(self.h, int(steps)))
+
+    def run_timed(self, steps: int) -> float:
+        """Run and wait; returns the device time of the step launches in ms."""
+        ms = C.c_double()
+        check(lib().uq_run_timed(self.h, int(steps), C.byref(ms)))
+        return ms.value
+
+    def sync(self):
+        check(lib().uq_sync(self.h))
+
+    def qoi_samples(self, qoi: str) -> np.ndarray:
+        n = C.c_int64()
+        check(lib().uq_qoi_samples(self.h, QOI[qoi], None, C.byref(n)))
+        out = np.zeros((self.S, n.value))
+        check(lib().uq_qoi_samples(self.h, QOI[qoi], out.ctypes.data, C.byref(n)))
+        return out
+
+    def moments(self, qoi: str) -> dict:
+        n = C.c_int64()
+        check(lib().uq_qoi_samples(self.h, QOI[qoi], None, C.byref(n)))
+        n = n.value
+        mean, var, alt = np.zeros(n), np.zeros(n), np.zeros(n)
+        res = {"mean": mean, "var": var, "var_alt": alt}
+        m = MomentsOut()
+        m.mean, m.var, m.var_alt = mean.ctypes.data, var.ctypes.data, alt.ctypes.data
+        if self.K > 0:
+            coeffs = np.zeros((self.K, n))
+            alpha = np.zeros((self.K, self.d), np.int32)
+            m.coeffs, m.alpha = coeffs.ctypes.data, alpha.ctypes.data
+            res["coeffs"], res["alpha"] = coeffs, alpha
+        check(lib().uq_moments(self.h, QOI[qoi], C.byref(m)))
+        return res
+
+    def populations(self, sample: int) -> np.ndarray:
+        nx, ny = self.spec["nx"], self.spec["ny"]
+        out = np.zeros((9, ny, nx))
+        check(lib().uq_populations(self.h, int(sample), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().uq_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

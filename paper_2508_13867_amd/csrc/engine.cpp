@@ -1,0 +1,101 @@
+// Time stepping of one job: eager launches or replays of a captured
+// hipGraph of an even number of steps (the AA parity pattern inside the graph
+// is then fixed, and the step count lives in device memory so the same graph
+// serves every replay).
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <string>
+
+#include "uq_job.h"
+
+namespace uqi {
+
+static int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+StepShape default_shape(const uq_problem &p) {
+    StepShape s;
+    s.cpt = env_int("UQ_CPT", p.ny >= 256 ? 4 : 2);
+    s.persistent = env_int("UQ_PERSISTENT", 0);
+    return s;
+}
+
+uq_status Job::enter() {
+    if (user_stream && user_stream != stream) {
+        UQ_HIP_TRY(hipEventRecord(ev_in, user_stream));
+        UQ_HIP_TRY(hipStreamWaitEvent(stream, ev_in, 0));
+    }
+    return UQ_OK;
+}
+
+uq_status Job::leave() {
+    if (user_stream && user_stream != stream) {
+        UQ_HIP_TRY(hipEventRecord(ev_out, stream));
+        UQ_HIP_TRY(hipStreamWaitEvent(user_stream, ev_out, 0));
+    }
+    return UQ_OK;
+}
+
+void Job::release_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_len = 0;
+}
+
+uq_status Job::advance(int64_t steps) {
+    const int L = env_int("UQ_GRAPH_STEPS", 64) & ~1;
+    if (use_graph && L >= 2 && steps >= L + 1) {
+        if (t & 1) {
+            UQ_HIP_TRY(launch_step(jd, d_t, 0, 1, shape, stream));
+            UQ_HIP_TRY(launch_advance(d_t, 1, stream));
+            t += 1;
+            steps -= 1;
+        }
+        if (!gexec || graph_len != L) {
+            release_graph();
+            UQ_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < L && e == hipSuccess; ++k) e = launch_step(jd, d_t, k, k & 1, shape, stream);
+            if (e == hipSuccess) e = launch_advance(d_t, L, stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(UQ_EDEVICE, std::string("graph capture failed: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            graph = g;
+            UQ_HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            graph_len = L;
+        }
+        while (steps >= L) {
+            UQ_HIP_TRY(hipGraphLaunch(gexec, stream));
+            t += L;
+            steps -= L;
+        }
+    }
+    if (steps > 0) {
+        for (int64_t k = 0; k < steps; ++k)
+            UQ_HIP_TRY(launch_step(jd, d_t, (int)k, (int)((t + k) & 1), shape, stream));
+        UQ_HIP_TRY(launch_advance(d_t, steps, stream));
+        t += steps;
+    }
+    return UQ_OK;
+}
+
+Job::~Job() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    release_graph();
+    dfree_all();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace uqi

@@ -1,0 +1,655 @@
+// HIP kernels (gfx950) of the batched D2Q9 BGK ensemble and its
+// statistics: OpenLB-UQ (arXiv 2508.13867), Sec. "Lattice Boltzmann
+// methods" (Eqs. deterministicLBE, bgkCollision, equilibrium, the D2Q9 set
+// and weights, the collide/stream split) and Sec. "Uncertainty
+// quantification methods" (Eqs. meanMCS, varMCS, coef_discrete, gpc_mean,
+// gpc_std).
+//
+// Storage: per job one slab [S][9][ny][pitch] of shifted populations
+// f~_i = f_i - w_i (x fastest, pitch a multiple of 64 elements), updated in
+// place with the AA access pattern (Bailey et al. 2009):
+//   even step t: node x reads its own slots i, collides, and writes f*_i to
+//                its own slot opp(i);
+//   odd step t:  node x reads f_i(x,t) = f*_i(x - c_i, t-1) from slot opp(i)
+//                of node x - c_i, collides, and writes f*_i to slot i of
+//                node x + c_i, leaving the natural layout for step t+1.
+// Each node reads and writes exactly the same nine locations in either
+// parity, so one launch per step needs no second lattice and no barrier.
+//
+// Direction order i = 0..8: (0,0), (1,0), (0,1), (-1,0), (0,-1), (1,1),
+// (-1,1), (-1,-1), (1,-1); opposite pairs (1,3), (2,4), (5,7), (6,8).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "uq_internal.h"
+
+namespace uqi {
+
+// ------------------------------------------------------------------ storage types
+template <int P>
+struct Prec;
+
+template <>
+struct Prec<UQ_FP64> {
+    using T = double;
+    using C = double;
+    __device__ static inline C ld(const T *p, float) { return *p; }
+    __device__ static inline void st(T *p, C v, float) { *p = v; }
+};
+template <>
+struct Prec<UQ_FP32> {
+    using T = float;
+    using C = float;
+    __device__ static inline C ld(const T *p, float) { return *p; }
+    __device__ static inline void st(T *p, C v, float) { *p = v; }
+};
+template <>
+struct Prec<UQ_FP16S> {
+    using T = _Float16;
+    using C = float;
+    // stored value = f~ * 2^s (power-of-two scale, exact); rounding to half is
+    // round-to-nearest-even (v_cvt_f16_f32 in the default mode)
+    __device__ static inline C ld(const T *p, float inv) { return (float)(*p) * inv; }
+    __device__ static inline void st(T *p, C v, float sc) { *p = (_Float16)(v * sc); }
+};
+template <>
+struct Prec<UQ_BF16S> {
+    using T = uint16_t;
+    using C = float;
+    __device__ static inline C ld(const T *p, float inv) {
+        return __uint_as_float((uint32_t)(*p) << 16) * inv;
+    }
+    // round to nearest, ties to even, on the upper 16 bits
+    __device__ static inline void st(T *p, C v, float sc) {
+        uint32_t u = __float_as_uint(v * sc);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        *p = (uint16_t)(u >> 16);
+    }
+};
+
+// ------------------------------------------------------------------ lattice
+__device__ constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPPd[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <typename C>
+__device__ inline C wgt(int i) {
+    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// BGK relaxation of shifted populations toward the second-order equilibrium
+// (Eqs. bgkCollision, equilibrium with c_s^2 = 1/3); f_eq - w = w (drho +
+// rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)). Returns rho - 1 and u.
+template <typename C>
+__device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
+    const C drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+    const C jx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
+    const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
+    const C rho = C(1) + drho;
+    const C ir = C(1) / rho;
+    const C ux = jx * ir, uy = jy * ir;
+    const C base = -C(1.5) * (ux * ux + uy * uy);
+    const C w0 = C(4) / C(9), w1 = C(1) / C(9), w2 = C(1) / C(36);
+    const C om1 = C(1) - omega;
+    f[0] = om1 * f[0] + omega * (w0 * (drho + rho * base));
+    {
+        const C cu = ux, q = rho * (base + C(4.5) * cu * cu), l = rho * C(3) * cu;
+        f[1] = om1 * f[1] + omega * (w1 * (drho + q + l));
+        f[3] = om1 * f[3] + omega * (w1 * (drho + q - l));
+    }
+    {
+        const C cu = uy, q = rho * (base + C(4.5) * cu * cu), l = rho * C(3) * cu;
+        f[2] = om1 * f[2] + omega * (w1 * (drho + q + l));
+        f[4] = om1 * f[4] + omega * (w1 * (drho + q - l));
+    }
+    {
+        const C cu = ux + uy, q = rho * (base + C(4.5) * cu * cu), l = rho * C(3) * cu;
+        f[5] = om1 * f[5] + omega * (w2 * (drho + q + l));
+        f[7] = om1 * f[7] + omega * (w2 * (drho + q - l));
+    }
+    {
+        const C cu = uy - ux, q = rho * (base + C(4.5) * cu * cu), l = rho * C(3) * cu;
+        f[6] = om1 * f[6] + omega * (w2 * (drho + q + l));
+        f[8] = om1 * f[8] + omega * (w2 * (drho + q - l));
+    }
+    drho_o = drho;
+    ux_o = ux;
+    uy_o = uy;
+}
+
+// moments only
+template <typename C>
+__device__ inline void moments(const C f[9], C &drho, C &ux, C &uy) {
+    drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+    const C jx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
+    const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
+    const C ir = C(1) / (C(1) + drho);
+    ux = jx * ir;
+    uy = jy * ir;
+}
+
+// inflow ramp s(t) = sin^2(pi t / (2 T_r)) for t < T_r, else 1
+__device__ inline double ramp_factor(int64_t t, double T) {
+    if (T <= 0.0 || (double)t >= T) return 1.0;
+    double s = sin(M_PI * (double)t / (2.0 * T));
+    return s * s;
+}
+
+// Zou-He (1997) completion of the unknown populations on the open columns,
+// written for shifted populations (the weights cancel in every relation).
+template <typename C>
+__device__ inline void zou_he(C f[9], const JobDev &j, int x, int y, int64_t t, double u_peak) {
+    if (x == 0) {
+        const double H = (double)j.ny, yy = (double)y + 0.5;
+        const C u = (C)(ramp_factor(t, j.ramp) * 4.0 * u_peak * yy * (H - yy) / (H * H));
+        const C S = (f[0] + f[2] + f[4]) + C(2) * (f[3] + f[6] + f[7]);
+        const C drho = (S + u) / (C(1) - u);
+        const C ru = (C(1) + drho) * u;
+        f[1] = f[3] + (C(2) / C(3)) * ru;
+        f[5] = f[7] - C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
+        f[8] = f[6] + C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
+    } else {
+        const C u = (f[0] + f[2] + f[4]) + C(2) * (f[1] + f[5] + f[8]);  // rho = 1
+        f[3] = f[1] - (C(2) / C(3)) * u;
+        f[7] = f[5] + C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * u;
+        f[6] = f[8] - C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * u;
+    }
+}
+
+// Addressing inside one sample's slab.
+struct Site {
+    int x, y, xm, xp, ym, yp;
+};
+
+__device__ inline Site site(const JobDev &j, int x, int y) {
+    Site s;
+    s.x = x;
+    s.y = y;
+    s.xm = x == 0 ? j.nx - 1 : x - 1;
+    s.xp = x == j.nx - 1 ? 0 : x + 1;
+    s.ym = y == 0 ? j.ny - 1 : y - 1;
+    s.yp = y == j.ny - 1 ? 0 : y + 1;
+    return s;
+}
+
+__device__ inline int sx_of(const Site &s, int dx) { return dx == 0 ? s.x : (dx > 0 ? s.xp : s.xm); }
+__device__ inline int sy_of(const Site &s, int dy) { return dy == 0 ? s.y : (dy > 0 ? s.yp : s.ym); }
+
+// Gather f~(x, t) of one node in either parity, with bounce-back and Zou-He.
+template <int P, bool CHANNEL, int PARITY>
+__device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
+                              int64_t t, double u_peak, typename Prec<P>::C f[9]) {
+    using PR = Prec<P>;
+    const float inv = j.inv_scale;
+    const int64_t pitch = j.pitch, plane = j.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (PARITY == 0) {
+            f[i] = PR::ld(base + i * plane + (int64_t)s.y * pitch + s.x, inv);
+        } else {
+            if (CHANNEL && (m & (1u << (M_BB + i)))) {
+                // bounce-back: the node's own post-collision f*_opp(i) sits in slot i
+                f[i] = PR::ld(base + i * plane + (int64_t)s.y * pitch + s.x, inv);
+            } else if (CHANNEL && (m & (1u << (M_OPEN + i)))) {
+                f[i] = 0;
+            } else {
+                const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
+                f[i] = PR::ld(base + OPPd[i] * plane + (int64_t)ys * pitch + xs, inv);
+            }
+        }
+    }
+    if (CHANNEL && (m & (0x1FFu << M_OPEN)) && t > 0) zou_he(f, j, s.x, s.y, t, u_peak);
+}
+
+// Scatter post-collision f*(x, t) to where step t+1 reads it.
+template <int P, bool CHANNEL, int PARITY>
+__device__ inline void scatter(const JobDev &j, typename Prec<P>::T *base, const Site &s, uint32_t m,
+                               const typename Prec<P>::C f[9]) {
+    using PR = Prec<P>;
+    const float sc = j.scale;
+    const int64_t pitch = j.pitch, plane = j.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (PARITY == 0) {
+            PR::st(base + OPPd[i] * plane + (int64_t)s.y * pitch + s.x, f[i], sc);
+        } else {
+            const int o = OPPd[i];
+            if (CHANNEL && (m & (1u << (M_BB + o)))) {
+                // destination is a wall: f*_i returns to this node as f_opp(i)
+                PR::st(base + o * plane + (int64_t)s.y * pitch + s.x, f[i], sc);
+            } else if (CHANNEL && (m & (1u << (M_OPEN + o)))) {
+                // leaves through an open column
+            } else {
+                const int xd = sx_of(s, CXd[i]), yd = sy_of(s, CYd[i]);
+                PR::st(base + i * plane + (int64_t)yd * pitch + xd, f[i], sc);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ tile walk
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
+// gets a contiguous run of tiles (neighbouring rows share its L2).
+__device__ inline int64_t xcd_logical(int64_t b, int64_t G) {
+    const int64_t xcd = b & 7, k = b >> 3;
+    const int64_t q = G >> 3, r = G & 7;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+constexpr int BX = 64;  // nodes along x per tile (one wavefront)
+constexpr int BY = 4;   // wavefronts per workgroup
+
+template <int P, bool CHANNEL, int PARITY>
+__global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int k, int cpt, int tiles_x,
+                                              int tiles_y, int64_t ntiles) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    const int64_t t = *d_t + k;
+    const int64_t G = gridDim.x;
+    const int64_t lb = xcd_logical(blockIdx.x, G);
+    const int64_t per_sample = (int64_t)tiles_x * tiles_y;
+    for (int64_t tile = lb; tile < ntiles; tile += G) {
+        const int64_t smp = tile / per_sample;
+        const int64_t rem = tile - smp * per_sample;
+        const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
+        const int x = tx * BX + threadIdx.x;
+        const C omega = (C)j.smp[smp].omega;
+        const double u_peak = j.smp[smp].u_peak;
+        T *base = (T *)j.f + smp * 9 * j.plane;
+        if (x >= j.nx) continue;
+        const int y0 = ty * BY * cpt + threadIdx.y;
+        for (int r = 0; r < cpt; ++r) {
+            const int y = y0 + r * BY;
+            if (y >= j.ny) break;
+            uint32_t m = 0;
+            if (CHANNEL) {
+                m = j.mask[(int64_t)y * j.pitch + x];
+                if (m & M_SOLID) continue;
+            }
+            const Site s = site(j, x, y);
+            C f[9], drho, ux, uy;
+            gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
+            bgk(f, omega, drho, ux, uy);
+            scatter<P, CHANNEL, PARITY>(j, base, s, m, f);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ init
+template <int P>
+__global__ __launch_bounds__(256) void k_init(JobDev j) {
+    using PR = Prec<P>;
+    using T = typename PR::T;
+    const int64_t cells = (int64_t)j.ny * j.pitch;
+    for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
+    T *base = (T *)j.f + smp * 9 * j.plane;
+    const SampleDev sd = j.smp[smp];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(c / j.pitch), x = (int)(c - (int64_t)y * j.pitch);
+        double f[9];
+        for (int i = 0; i < 9; ++i) f[i] = 0.0;
+        if (x < j.nx && j.geom == 0) {
+            // Taylor-Green vortex (Eqs. TGV_vel, TGV_press at t = 0), rho = 1 + 3p
+            const double kx = 2.0 * M_PI / j.nx, ky = 2.0 * M_PI / j.ny;
+            const double ax = kx * x + sd.phase_x, ay = ky * y + sd.phase_y;
+            const double ux = -sd.u0 * cos(ax) * sin(ay);
+            const double uy = sd.u0 * sin(ax) * cos(ay);
+            const double p = -0.25 * sd.u0 * sd.u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
+            const double drho = 3.0 * p, rho = 1.0 + drho;
+            const double uu = 1.5 * (ux * ux + uy * uy);
+            for (int i = 0; i < 9; ++i) {
+                const double cu = CXd[i] * ux + CYd[i] * uy;
+                f[i] = wgt<double>(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - uu));
+            }
+        }
+        // channel: rest state rho = 1, u = 0, i.e. f~ = 0 everywhere
+        for (int i = 0; i < 9; ++i) PR::st(base + i * j.plane + c, (typename PR::C)f[i], j.scale);
+    }
+    }
+}
+
+// ------------------------------------------------------------------ QoIs
+// Neumaier's compensated sum
+struct NSum {
+    double s = 0.0, c = 0.0;
+    __device__ inline void add(double x) {
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    __device__ inline double val() const { return s + c; }
+};
+
+// One workgroup per sample: KE, momentum-exchange force, non-finite count.
+template <int P, bool CHANNEL, int PARITY>
+__global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    const int64_t smp = blockIdx.x;
+    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const SampleDev sd = j.smp[smp];
+    NSum ke, fx, fy;
+    double bad = 0.0;
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    for (int64_t c = threadIdx.x; c < cells; c += blockDim.x) {
+        const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
+        uint32_t m = 0;
+        if (CHANNEL) {
+            m = j.mask[(int64_t)y * j.pitch + x];
+            if (m & M_SOLID) continue;
+        }
+        const Site s = site(j, x, y);
+        C f[9], drho, ux, uy;
+        gather<P, CHANNEL, PARITY>(j, base, s, m, t, sd.u_peak, f);
+        if (CHANNEL && (m & (0x1FFu << M_CYL))) {
+            bgk(f, (C)sd.omega, drho, ux, uy);
+            for (int i = 1; i < 9; ++i)
+                if (m & (1u << (M_CYL + i))) {
+                    const double fs = (double)f[i] + wgt<double>(i);
+                    fx.add(2.0 * CXd[i] * fs);
+                    fy.add(2.0 * CYd[i] * fs);
+                }
+        } else {
+            moments(f, drho, ux, uy);
+        }
+        const double dux = (double)ux, duy = (double)uy;
+        if (!isfinite(dux) || !isfinite(duy) || !isfinite((double)drho)) bad += 1.0;
+        ke.add(dux * dux + duy * duy);
+    }
+    // fixed-order block reduction (deterministic)
+    __shared__ double red[4][256];
+    red[0][threadIdx.x] = ke.val();
+    red[1][threadIdx.x] = fx.val();
+    red[2][threadIdx.x] = fy.val();
+    red[3][threadIdx.x] = bad;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        NSum acc;
+        for (int k = 0; k < (int)blockDim.x; ++k) acc.add(red[threadIdx.x][k]);
+        double v = acc.val();
+        if (threadIdx.x == 0) v *= j.ke_norm;
+        out[smp * 4 + threadIdx.x] = v;
+    }
+}
+
+// Per-sample fields: out[s][3][ny][nx] = ux, uy, rho (0 at solid nodes).
+template <int P, bool CHANNEL, int PARITY>
+__global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
+    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const double u_peak = j.smp[smp].u_peak;
+    double *o = out + smp * 3 * cells;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
+        uint32_t m = 0;
+        if (CHANNEL) {
+            m = j.mask[(int64_t)y * j.pitch + x];
+            if (m & M_SOLID) {
+                o[c] = 0.0;
+                o[cells + c] = 0.0;
+                o[2 * cells + c] = 0.0;
+                continue;
+            }
+        }
+        const Site s = site(j, x, y);
+        C f[9], drho, ux, uy;
+        gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
+        moments(f, drho, ux, uy);
+        o[c] = (double)ux;
+        o[cells + c] = (double)uy;
+        o[2 * cells + c] = 1.0 + (double)drho;
+    }
+    }
+}
+
+// One sample's unshifted populations, natural order [9][ny][nx] in double.
+template <int P, bool CHANNEL, int PARITY>
+__global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp, double *out) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const double u_peak = j.smp[smp].u_peak;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
+        uint32_t m = 0;
+        if (CHANNEL) {
+            m = j.mask[(int64_t)y * j.pitch + x];
+            if (m & M_SOLID) {
+                for (int i = 0; i < 9; ++i) out[i * cells + c] = 0.0;
+                continue;
+            }
+        }
+        const Site s = site(j, x, y);
+        C f[9];
+        gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
+        for (int i = 0; i < 9; ++i) out[i * cells + c] = (double)f[i] + wgt<double>(i);
+    }
+}
+
+// ------------------------------------------------------------------ moments
+// SC-gPC projection (Eq. coef_discrete with gamma_k = 1): one thread per
+// output value and a chunk of up to KC coefficients; wphi[j][k] = a_j Phi_k
+// is staged through LDS in blocks of samples.
+constexpr int KC = 8;
+constexpr int JB = 64;
+
+__global__ __launch_bounds__(256) void k_gpc_coeffs(const double *M, int64_t S, int64_t n_out, int64_t ld,
+                                                    const double *wphi, int K, double *coeffs) {
+    __shared__ double w_lds[JB][KC];
+    const int k0 = blockIdx.y * KC;
+    const int nk = min(KC, K - k0);
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    NSum acc[KC];
+    for (int64_t j0 = 0; j0 < S; j0 += JB) {
+        const int nj = (int)min((int64_t)JB, S - j0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < JB * KC; e += blockDim.x) {
+            const int jj = e / KC, kk = e % KC;
+            w_lds[jj][kk] = (jj < nj && kk < nk) ? wphi[(j0 + jj) * K + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+        if (o < n_out) {
+            for (int jj = 0; jj < nj; ++jj) {
+                const double m = M[(j0 + jj) * ld + o];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk)
+                    if (kk < nk) acc[kk].add(w_lds[jj][kk] * m);
+            }
+        }
+    }
+    if (o < n_out)
+        for (int kk = 0; kk < nk; ++kk) coeffs[(int64_t)(k0 + kk) * n_out + o] = acc[kk].val();
+}
+
+// mean = c_0 (Eq. gpc_mean), var = sum_{k>=1} c_k^2 (Eq. gpc_std), and the
+// quadrature variance sum_j a_j (M_j - mean)^2.
+__global__ __launch_bounds__(256) void k_gpc_finish(const double *M, int64_t S, int64_t n_out, int64_t ld,
+                                                    const double *a, int K, const double *coeffs, double *mean,
+                                                    double *var, double *var_alt) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n_out) return;
+    const double mu = coeffs[o];
+    NSum v;
+    for (int k = 1; k < K; ++k) {
+        const double c = coeffs[(int64_t)k * n_out + o];
+        v.add(c * c);
+    }
+    NSum q;
+    for (int64_t j = 0; j < S; ++j) {
+        const double e = M[j * ld + o] - mu;
+        q.add(a[j] * e * e);
+    }
+    mean[o] = mu;
+    var[o] = v.val();
+    var_alt[o] = q.val();
+}
+
+// Monte Carlo mean (Eq. meanMCS) and variance (Eq. varMCS, 1/(N-1); 1/N as
+// var_alt), two passes with compensated sums.
+__global__ __launch_bounds__(256) void k_mc_moments(const double *M, int64_t S, int64_t n_out, int64_t ld,
+                                                    double *mean, double *var, double *var_alt) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n_out) return;
+    NSum s;
+    for (int64_t j = 0; j < S; ++j) s.add(M[j * ld + o]);
+    const double mu = s.val() / (double)S;
+    NSum q;
+    for (int64_t j = 0; j < S; ++j) {
+        const double e = M[j * ld + o] - mu;
+        q.add(e * e);
+    }
+    mean[o] = mu;
+    var[o] = S > 1 ? q.val() / (double)(S - 1) : 0.0;
+    var_alt[o] = q.val() / (double)S;
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_advance(int64_t *d_t, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_t += n;
+}
+
+// which: UQ_QOI_KE -> KE; UQ_QOI_CD / UQ_QOI_CL -> 2 F/(u_peak^2 D) with the
+// sample's peak inflow velocity and rho0 = 1
+__global__ void k_select(const double *qoi, const SampleDev *smp, int64_t S, int which, int D, double *M) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (which == UQ_QOI_KE) {
+        M[s] = qoi[4 * s];
+    } else {
+        const double u = smp[s].u_peak;
+        const double F = which == UQ_QOI_CD ? qoi[4 * s + 1] : qoi[4 * s + 2];
+        M[s] = 2.0 * F / (u * u * (double)D);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define UQ_DISPATCH(KERNEL, PARITY, GRID, BLOCK, STREAM, ...)                                      \
+    do {                                                                                           \
+        const int par_ = (int)(PARITY);                                                            \
+        const bool ch_ = j.geom == 1;                                                              \
+        switch (j.prec) {                                                                          \
+            case UQ_FP64:                                                                          \
+                if (ch_) {                                                                         \
+                    if (par_) KERNEL<UQ_FP64, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);   \
+                    else KERNEL<UQ_FP64, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);        \
+                } else {                                                                           \
+                    if (par_) KERNEL<UQ_FP64, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
+                    else KERNEL<UQ_FP64, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
+                }                                                                                  \
+                break;                                                                             \
+            case UQ_FP32:                                                                          \
+                if (ch_) {                                                                         \
+                    if (par_) KERNEL<UQ_FP32, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);   \
+                    else KERNEL<UQ_FP32, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);        \
+                } else {                                                                           \
+                    if (par_) KERNEL<UQ_FP32, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
+                    else KERNEL<UQ_FP32, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
+                }                                                                                  \
+                break;                                                                             \
+            case UQ_FP16S:                                                                         \
+                if (ch_) {                                                                         \
+                    if (par_) KERNEL<UQ_FP16S, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
+                    else KERNEL<UQ_FP16S, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
+                } else {                                                                           \
+                    if (par_) KERNEL<UQ_FP16S, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
+                    else KERNEL<UQ_FP16S, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);      \
+                }                                                                                  \
+                break;                                                                             \
+            default:                                                                               \
+                if (ch_) {                                                                         \
+                    if (par_) KERNEL<UQ_BF16S, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
+                    else KERNEL<UQ_BF16S, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
+                } else {                                                                           \
+                    if (par_) KERNEL<UQ_BF16S, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
+                    else KERNEL<UQ_BF16S, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);      \
+                }                                                                                  \
+                break;                                                                             \
+        }                                                                                          \
+    } while (0)
+
+hipError_t launch_init(const JobDev &j, hipStream_t s) {
+    const int64_t cells = (int64_t)j.ny * j.pitch;
+    dim3 grid((unsigned)std::min<int64_t>((cells + 255) / 256, 1024), (unsigned)std::min<int64_t>(j.S, 65535));
+    switch (j.prec) {
+        case UQ_FP64: k_init<UQ_FP64><<<grid, 256, 0, s>>>(j); break;
+        case UQ_FP32: k_init<UQ_FP32><<<grid, 256, 0, s>>>(j); break;
+        case UQ_FP16S: k_init<UQ_FP16S><<<grid, 256, 0, s>>>(j); break;
+        default: k_init<UQ_BF16S><<<grid, 256, 0, s>>>(j); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
+                       hipStream_t s) {
+    const int cpt = shape.cpt < 1 ? 1 : shape.cpt;
+    const int tiles_x = (j.nx + BX - 1) / BX;
+    const int tiles_y = (j.ny + BY * cpt - 1) / (BY * cpt);
+    const int64_t ntiles = (int64_t)j.S * tiles_x * tiles_y;
+    int64_t G = ntiles;
+    if (shape.persistent > 0) G = std::min<int64_t>(ntiles, (int64_t)256 * shape.persistent);
+    if (G > 0x7fffffff) G = 0x7fffffff;
+    dim3 block(BX, BY);
+    dim3 grid((unsigned)G);
+    UQ_DISPATCH(k_step, parity & 1, grid, block, s, j, d_t, k, cpt, tiles_x, tiles_y, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s) {
+    k_advance<<<1, 64, 0, s>>>(d_t, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s) {
+    k_select<<<(unsigned)((j.S + 255) / 256), 256, 0, s>>>(qoi, j.smp, j.S, which, j.D, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_qoi_scalars(const JobDev &j, int64_t t, double *out, hipStream_t s) {
+    dim3 grid((unsigned)j.S);
+    UQ_DISPATCH(k_qoi, t & 1, grid, 256, s, j, t, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const JobDev &j, int64_t t, double *out, hipStream_t s) {
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    dim3 grid((unsigned)std::min<int64_t>((cells + 255) / 256, 4096), (unsigned)std::min<int64_t>(j.S, 65535));
+    UQ_DISPATCH(k_fields, t & 1, grid, 256, s, j, t, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const JobDev &j, int64_t t, int64_t sample, double *out, hipStream_t s) {
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    dim3 grid((unsigned)std::min<int64_t>((cells + 255) / 256, 4096));
+    UQ_DISPATCH(k_export, t & 1, grid, 256, s, j, t, sample, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_sc(const double *M, int64_t S, int64_t n_out, int64_t ld, const double *wphi,
+                             const double *a, int K, double *coeffs, double *mean, double *var, double *var_alt,
+                             hipStream_t s) {
+    dim3 grid((unsigned)((n_out + 255) / 256), (unsigned)((K + KC - 1) / KC));
+    k_gpc_coeffs<<<grid, 256, 0, s>>>(M, S, n_out, ld, wphi, K, coeffs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_gpc_finish<<<(unsigned)((n_out + 255) / 256), 256, 0, s>>>(M, S, n_out, ld, a, K, coeffs, mean, var,
+                                                                 var_alt);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_mc(const double *M, int64_t S, int64_t n_out, int64_t ld, double *mean, double *var,
+                             double *var_alt, hipStream_t s) {
+    k_mc_moments<<<(unsigned)((n_out + 255) / 256), 256, 0, s>>>(M, S, n_out, ld, mean, var, var_alt);
+    return hipGetLastError();
+}
+
+}  // namespace uqi

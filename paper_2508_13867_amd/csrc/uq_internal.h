@@ -1,0 +1,120 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/uq.h"
+
+namespace uqi {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+uq_status fail(uq_status st, const std::string &msg);
+
+#define UQ_HIP_TRY(expr)                                                                          \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::uqi::fail(UQ_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ host sampler
+struct Rule {
+    int64_t S = 0;
+    int d = 0;
+    int K = 0;                  // 0 for Monte Carlo
+    std::vector<double> xi;     // [S][d]
+    std::vector<double> a;      // [S]
+    std::vector<int32_t> alpha; // [K][d]
+    std::vector<double> phi;    // [S][K]
+};
+
+uq_status validate_problem(const uq_problem &p);
+uq_status build_rule(const uq_problem &p, Rule &r);
+
+// Per-sample solver inputs after mapping the reference variables.
+struct SampleInputs {
+    double nu, u0, phase_x, phase_y, u_peak;
+};
+void map_inputs(const uq_problem &p, const double *xi_row, SampleInputs &out);
+
+// ------------------------------------------------------------------ device-side layout
+// Per-sample parameters read by the kernels (one 64-byte record per sample).
+struct alignas(64) SampleDev {
+    double omega;   // 1/tau
+    double u0;      // TGV amplitude
+    double phase_x; // TGV phases
+    double phase_y;
+    double u_peak;  // channel peak inflow
+    double pad[3];
+};
+
+// Per-node boundary mask of the channel (one 32-bit word per node).
+//  bits 0..8   : the pull source x - c_i is a wall/solid -> bounce-back
+//  bits 9..17  : the pull source x - c_i lies beyond an open column (Zou-He)
+//  bit  18     : node is solid
+//  bit  19     : node is on the inlet column, bit 20: outlet column
+//  bits 21..29 : the link x -> x + c_i enters the cylinder (force links)
+enum : uint32_t {
+    M_BB = 0,
+    M_OPEN = 9,
+    M_SOLID = 1u << 18,
+    M_INLET = 1u << 19,
+    M_OUTLET = 1u << 20,
+    M_CYL = 21,
+};
+
+// A job as the kernels see it.
+struct JobDev {
+    void *f;               // population slab [S][9][ny][pitch]
+    const SampleDev *smp;  // [S]
+    const uint32_t *mask;  // [ny][pitch] or null (TGV)
+    int64_t pitch;         // elements per row
+    int64_t plane;         // ny * pitch
+    int32_t nx, ny, S;
+    int32_t geom;          // 0 TGV, 1 channel
+    int32_t xbc;
+    int32_t prec;
+    float scale, inv_scale; // FP16S/BF16S storage scale
+    double ramp;            // T_r (0: none)
+    double ke_norm;         // 2/(nx ny u0^2)
+    int32_t D;
+    int32_t pad0;
+};
+
+// ------------------------------------------------------------------ kernel launchers
+struct StepShape {
+    int cpt = 2;       // cells per thread along y
+    int persistent = 0; // 0: one workgroup per tile; >0: workgroups per CU
+};
+
+// one stream-collide step for all samples at time t = *d_t + k; `parity`
+// must equal t & 1 (the host keeps a mirror of t)
+hipError_t launch_init(const JobDev &j, hipStream_t s);
+hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
+                       hipStream_t s);
+// *d_t += n (one thread; keeps the device copy of the step count current)
+hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s);
+// per-sample scalar QoIs at time t: out[S][4] = {KE, Fx, Fy, nonfinite}
+hipError_t launch_qoi_scalars(const JobDev &j, int64_t t, double *out, hipStream_t s);
+// M[s] = KE, C_D or C_L of sample s from the scalars above
+hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s);
+// per-sample fields at time t: out[S][3][ny][nx] = {ux, uy, rho}
+hipError_t launch_fields(const JobDev &j, int64_t t, double *out, hipStream_t s);
+// unshifted double populations of one sample in natural order
+hipError_t launch_export(const JobDev &j, int64_t t, int64_t sample, double *out, hipStream_t s);
+
+// Cross-sample statistics on the device. M: value o of sample j at
+// M[j*ld + o], o < n_out. SC: wphi [S][K] = a_j * Phi_k(xi_j); writes
+// coeffs[K][n_out], mean, var, var_alt. MC: mean, var (1/(S-1)), var_alt (1/S).
+hipError_t launch_moments_sc(const double *M, int64_t S, int64_t n_out, int64_t ld, const double *wphi,
+                             const double *a, int K, double *coeffs, double *mean, double *var, double *var_alt,
+                             hipStream_t s);
+hipError_t launch_moments_mc(const double *M, int64_t S, int64_t n_out, int64_t ld, double *mean, double *var,
+                             double *var_alt, hipStream_t s);
+
+}  // namespace uqi

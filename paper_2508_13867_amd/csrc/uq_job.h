@@ -1,0 +1,61 @@
+// A UQ job: problem, sample set, device buffers and time-stepping state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "uq_internal.h"
+
+namespace uqi {
+
+int64_t storage_bytes(int prec);
+int64_t row_pitch(int nx);
+void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, int &fluid);
+StepShape default_shape(const uq_problem &p);
+
+struct Job {
+    uq_problem p{};
+    uq_device dev{};
+    Rule rule;
+    int64_t S = 0;
+    int K = 0;
+    int64_t pitch = 0;
+    int scale_exp = 0;
+    int fluid = 0;
+
+    hipStream_t user_stream = nullptr;  // caller's stream (ordering only)
+    hipStream_t stream = nullptr;       // the job's own work stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+
+    JobDev jd{};
+    StepShape shape{};
+    int64_t t = 0;            // steps done (host mirror)
+    int64_t *d_t = nullptr;   // steps done at the last base update (device)
+
+    std::vector<void *> allocs;
+    int64_t bytes_held = 0;
+    double *d_qoi = nullptr, *d_M = nullptr, *d_out = nullptr, *d_fields = nullptr;
+    double *d_wphi = nullptr, *d_a = nullptr, *d_export = nullptr;
+    int64_t out_cap = 0;
+
+    // hipGraph of `graph_len` steps starting at an even step
+    bool use_graph = true;
+    int graph_len = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    ~Job();
+    void *dalloc(size_t bytes);
+    void dfree_all();
+    uq_status ensure_stats_buffers(int64_t n_out_max);
+    uq_status ensure_fields();
+    uq_status sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld);
+    uq_status advance(int64_t steps);
+    uq_status enter();  // order the job stream after the caller's stream
+    uq_status leave();  // order the caller's stream after the job stream
+    void release_graph();
+};
+
+}  // namespace uqi

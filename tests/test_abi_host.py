@@ -1,0 +1,86 @@
+"""C-ABI library: loads, exports every declared symbol, and its host-only
+logic (sample sets, basis, validation) agrees with the oracle. No GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_13867_amd import _abi as A
+from paper_2508_13867_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "uq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(uq_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    names = declared_functions()
+    assert "uq_create" in names and "uq_moments" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(A.SIGNATURES), set(names) - set(A.SIGNATURES)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # the ctypes mirrors must have the C compiler's layout of uq.h
+    import subprocess
+
+    structs = {"uq_dist": A.Dist, "uq_problem": A.Problem, "uq_device": A.Device,
+               "uq_moments_out": A.MomentsOut, "uq_job_info": A.JobInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "uq.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    for line in out:
+        if not line:
+            continue
+        cname, field, val = line.split()
+        py = structs[cname]
+        got = C.sizeof(py) if field == "sizeof" else getattr(py, field).offset
+        assert got == int(val), (cname, field, got, val)
+
+
+@pytest.mark.parametrize("spec", [W.TGV_SMALL_FP64, W.TGV_BATCHED_FP32, W.CYLINDER_FP32])
+def test_collocation_rule_matches_oracle(spec):
+    xi, a, alpha, phi = A.rule_points(spec)
+    d, n, P = len(spec["dists"]), spec["rule"]["n"], spec["rule"]["order"]
+    xo, ao = O.gl_tensor(d, n)
+    assert np.abs(xi - xo).max() < 1e-15 and np.abs(a - ao).max() < 1e-15
+    assert np.array_equal(alpha, O.multi_indices(d, P))
+    assert np.abs(phi - O.phi_table(xo, alpha)).max() < 1e-12
+
+
+def test_monte_carlo_points_bit_exact_with_oracle():
+    xi, a, alpha, phi = A.rule_points(W.TGV_MC)
+    xo, ao = O.mc_points(W.SEED, 4096, 4)
+    assert np.array_equal(xi, xo) and np.array_equal(a, ao)
+    assert alpha.shape == (0, 4)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(ny=1), dict(precision="fp64", rule=dict(kind="gl", n=0, order=1)),
+    dict(rule=dict(kind="mc", N=1, seed=1)), dict(dists=[("re", 10, 20)]),
+    dict(dists=[("nu", 0.02, 0.01)]), dict(dists=[("nu", 0.1, 0.2), ("nu", 0.1, 0.2)]),
+])
+def test_invalid_problems_are_rejected(bad):
+    spec = W.scaled(W.TGV_SMALL_FP64, **bad)
+    with pytest.raises(A.UQError) as e:
+        A.rule_points(spec)
+    assert e.value.status == A.UQ_EINVAL
+    assert A.lib().uq_last_error().decode()

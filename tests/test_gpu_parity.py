@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on
+identical seeded inputs. Tolerances are the relative-L2 bars of the design:
+1e-10 for FP64 runs, 1e-4 for FP32, 5e-3 for FP16 storage (BF16 storage is
+reported against a looser 5e-2). Sizes are chosen so the oracle finishes in
+seconds while the lattices span several 64 x (4 cpt) tiles with ragged edges;
+full-size workloads are checked on sampled samples."""
+import os
+import sys
+from math import pi
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import gpu_available, rel_l2
+from paper_2508_13867_amd import Job, UQError
+from paper_2508_13867_amd import _abi as A
+from paper_2508_13867_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16s": 5e-3, "bf16s": 5e-2}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_fields(spec, samples=None):
+    return O.run_problem(spec, samples=samples)
+
+
+# ----------------------------------------------------------------- small TGV, FP64
+
+TGV_RAGGED = dict(name="tgv72x40", geometry="tgv", precision="fp64", nx=72, ny=40, steps=40, u0=0.03, nu=0.02,
+                  dists=[("nu", 0.01, 0.03), ("u0", 0.02, 0.04)], rule=dict(kind="gl", n=3, order=2),
+                  phase_x=0.3, phase_y=-0.7)
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 7, 40])
+def test_tgv_fp64_populations_match_oracle(steps):
+    say("case tgv72x40 fp64 steps", steps)
+    with Job(TGV_RAGGED) as job:
+        job.run(steps)
+        xi, a = job.samples()
+        for s in (0, 4, 8):
+            p = O.sample_params(TGV_RAGGED, xi[s])
+            ref = O.tgv_run(72, 40, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+            got = job.populations(s)
+            assert np.abs(got - ref).max() < 1e-13, (s, np.abs(got - ref).max())
+
+
+def test_tgv_fp64_moments_match_oracle():
+    say("case tgv72x40 fp64 moments")
+    ref = O.run_problem(TGV_RAGGED)
+    with Job(TGV_RAGGED) as job:
+        job.run(TGV_RAGGED["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        assert rel_l2(ke, ref["samples"]["ke"]) < TOL["fp64"]
+        vel = job.qoi_samples("vel")
+        assert rel_l2(vel, ref["samples"]["vel"].reshape(9, -1)) < TOL["fp64"]
+        for q in ("ke", "vel", "rho"):
+            st = job.moments(q)
+            rs = ref["stats"][q]
+            for k in ("mean", "var", "var_alt", "coeffs"):
+                assert rel_l2(st[k], rs[k]) < TOL["fp64"], (q, k, rel_l2(st[k], rs[k]))
+            assert np.array_equal(st["alpha"], ref["alpha"])
+
+
+def test_config1_tgv64_fp64_full():
+    # the 64^2 FP64 collocation workload at full size (5 samples, 1000 steps)
+    spec = W.TGV_SMALL_FP64
+    say("case", spec["name"])
+    ref = O.run_problem(spec)
+    with Job(spec) as job:
+        job.run(spec["steps"])
+        for q in ("ke", "vel"):
+            st = job.moments(q)
+            rs = ref["stats"][q]
+            for k in ("mean", "var", "var_alt", "coeffs"):
+                assert rel_l2(st[k], rs[k]) < TOL["fp64"], (q, k, rel_l2(st[k], rs[k]))
+
+
+# ----------------------------------------------------------------- reduced precisions
+
+TGV_4D_SMALL = dict(name="tgv96x80_4d", geometry="tgv", precision="fp32", nx=96, ny=80, steps=300, u0=0.02,
+                    nu=0.005, dists=W.FOUR_D_INPUTS, rule=dict(kind="gl", n=2, order=1))
+
+
+@pytest.fixture(scope="module")
+def tgv4d_ref():
+    return O.run_problem(TGV_4D_SMALL)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+def test_tgv_4d_reduced_precision(prec, tgv4d_ref):
+    spec = W.scaled(TGV_4D_SMALL, precision=prec)
+    say("case tgv96x80_4d", prec)
+    ref = tgv4d_ref
+    tol = TOL[prec]
+    with Job(spec) as job:
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        assert rel_l2(ke, ref["samples"]["ke"]) < tol
+        vel = job.qoi_samples("vel")
+        vref = ref["samples"]["vel"].reshape(vel.shape)
+        assert rel_l2(vel, vref) < tol
+        st = job.moments("ke")
+        for k in ("mean", "var", "coeffs"):
+            assert rel_l2(st[k], ref["stats"]["ke"][k]) < tol, (k, rel_l2(st[k], ref["stats"]["ke"][k]))
+        sv = job.moments("vel")
+        # the mean velocity under uniform phases is near zero: normalise the
+        # field statistics by the RMS of the per-sample fields
+        rms = np.sqrt(np.mean(vref ** 2)) * np.sqrt(vref.shape[1])
+        assert rel_l2(sv["mean"], ref["stats"]["vel"]["mean"], scale=rms) < tol
+        assert rel_l2(sv["coeffs"], ref["stats"]["vel"]["coeffs"], scale=rms) < tol
+        assert rel_l2(sv["var"], ref["stats"]["vel"]["var"]) < tol
+
+
+def test_tgv_monte_carlo_fp32():
+    spec = dict(name="tgv48_mc", geometry="tgv", precision="fp32", nx=48, ny=48, steps=200, u0=0.02, nu=0.005,
+                dists=W.FOUR_D_INPUTS, rule=dict(kind="mc", N=32, seed=W.SEED + 7))
+    say("case", spec["name"])
+    ref = O.run_problem(spec)
+    with Job(spec) as job:
+        xi, a = job.samples()
+        assert np.array_equal(xi, ref["xi"]) and np.array_equal(a, ref["a"])
+        job.run(spec["steps"])
+        st = job.moments("ke")
+        for k in ("mean", "var", "var_alt"):
+            assert rel_l2(st[k], ref["stats"]["ke"][k]) < TOL["fp32"]
+        assert "coeffs" not in st
+
+
+# ----------------------------------------------------------------- channel
+
+CHANNEL_SMALL = dict(name="chan100x41", geometry="channel", precision="fp64", nx=100, ny=41, steps=401,
+                     u_peak=0.05, nu=0.05, D=10, cx=25, cy=18, ramp=200, xbc="zouhe",
+                     dists=[("re", 16.0, 24.0), ("u_peak", 0.045, 0.055)], rule=dict(kind="gl", n=2, order=1))
+
+
+@pytest.mark.parametrize("steps", [1, 2, 201, 401])
+def test_channel_fp64_populations(steps):
+    say("case chan100x41 fp64 steps", steps)
+    with Job(CHANNEL_SMALL) as job:
+        job.run(steps)
+        xi, a = job.samples()
+        for s in (0, 3):
+            p = O.sample_params(CHANNEL_SMALL, xi[s])
+            ref = O.channel_run(100, 41, p["nu"], p["u_peak"], steps, D=10, cx=25, cy=18, ramp=200,
+                                want_f=True)["f"]
+            got = job.populations(s)
+            assert np.abs(got - ref).max() < 1e-13, (s, np.abs(got - ref).max())
+
+
+def test_channel_fp64_drag_lift_moments():
+    say("case chan100x41 fp64 moments")
+    ref = O.run_problem(CHANNEL_SMALL)
+    with Job(CHANNEL_SMALL) as job:
+        job.run(CHANNEL_SMALL["steps"])
+        for q in ("cd", "cl"):
+            got = job.qoi_samples(q)[:, 0]
+            assert rel_l2(got, ref["samples"][q]) < TOL["fp64"], q
+            st = job.moments(q)
+            for k in ("mean", "var", "coeffs"):
+                assert rel_l2(st[k], ref["stats"][q][k]) < TOL["fp64"], (q, k)
+        st = job.moments("vel")
+        assert rel_l2(st["coeffs"], ref["stats"]["vel"]["coeffs"]) < TOL["fp64"]
+
+
+def test_cylinder_config_geometry_fp32_sampled():
+    # the 440 x 82 cylinder workload (64 samples) at reduced steps; two
+    # samples are re-solved by the oracle one by one
+    spec = W.scaled(W.CYLINDER_FP32, steps=600)
+    say("case", spec["name"], "600 steps")
+    with Job(spec) as job:
+        job.run(spec["steps"])
+        xi, a = job.samples()
+        cd = job.qoi_samples("cd")[:, 0]
+        cl = job.qoi_samples("cl")[:, 0]
+        vel = job.qoi_samples("vel")
+        ref = O.run_problem(spec, samples=[0, 63])
+        assert rel_l2(cd[[0, 63]], ref["samples"]["cd"]) < TOL["fp32"]
+        assert rel_l2(vel[[0, 63]], ref["samples"]["vel"].reshape(2, -1)) < TOL["fp32"]
+        assert np.all(np.isfinite(cl))
+        st = job.moments("cd")
+        assert st["coeffs"].shape == (36, 1)
+
+
+# ----------------------------------------------------------------- full-size batched TGV
+
+def test_batched_tgv256_fp32_sampled():
+    # 256^2 x 256 samples in the benchmark's launch configuration, 100 steps;
+    # three samples re-solved by the oracle
+    spec = W.scaled(W.TGV_BATCHED_FP32, steps=100)
+    say("case", spec["name"], "100 steps")
+    with Job(spec) as job:
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        vel = job.qoi_samples("vel")
+        pick = [0, 137, 255]
+        ref = O.run_problem(spec, samples=pick)
+        assert rel_l2(ke[pick], ref["samples"]["ke"]) < TOL["fp32"]
+        assert rel_l2(vel[pick], ref["samples"]["vel"].reshape(3, -1)) < TOL["fp32"]
+
+
+# ----------------------------------------------------------------- engine behaviour
+
+def test_graph_replay_equals_eager(monkeypatch):
+    spec = W.scaled(TGV_4D_SMALL, steps=150)
+    say("case graph vs eager")
+    monkeypatch.setenv("UQ_GRAPH_STEPS", "32")
+    with Job(spec) as a:
+        a.run(3)
+        a.run(147)
+        fa = a.populations(5)
+        ka = a.qoi_samples("ke")
+    monkeypatch.setenv("UQ_GRAPH_STEPS", "0")
+    with Job(spec) as b:
+        b.run(150)
+        fb = b.populations(5)
+        kb = b.qoi_samples("ke")
+    assert np.array_equal(fa, fb) and np.array_equal(ka, kb)
+
+
+def test_unstable_sample_is_reported():
+    spec = dict(name="tgv_unstable", geometry="tgv", precision="fp32", nx=32, ny=32, steps=400, u0=0.9,
+                nu=1e-5, dists=[("u0", 0.8, 0.9)], rule=dict(kind="gl", n=2, order=1))
+    say("case unstable")
+    with Job(spec) as job:
+        job.run(400)
+        with pytest.raises(UQError) as e:
+            job.moments("ke")
+        assert e.value.status == A.UQ_EUNSTABLE
+
+
+def test_nonpositive_viscosity_rejected():
+    spec = W.scaled(TGV_RAGGED, dists=[("nu", -0.01, 0.01)])
+    with pytest.raises(UQError) as e:
+        Job(spec)
+    assert e.value.status == A.UQ_EINVAL
