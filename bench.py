@@ -50,6 +50,26 @@ def measured_traffic(bytes_alg_per_launch):
     return t.get("bytes_per_launch")
 
 
+def copy_probe(torch, nbytes=1207959552, reps=10):
+    """Device-to-device copy of a buffer the size of one step's slab with
+    torch's plain copy kernel: the achievable read+write bandwidth (and the
+    counter calibration run for the traffic measurement)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(spec, n_samples=4, lbm_steps=300):
     """The FP64 oracle, single-threaded, on the full lattice of the workload
     for a few samples and steps (about 10 s of CPU work)."""
@@ -76,6 +96,10 @@ def main():
     ap.add_argument("--workload", default="tgv256_fp32_gl4x4")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override LBM steps per job")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
+    ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip tuning (shapes then come from UQ_TUNE_CACHE or the defaults)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -97,9 +121,24 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    copy_gbs = copy_probe(torch)
+    log(f"bench: device copy {copy_gbs:.0f} GB/s")
+    if args.copy_probe:
+        print(json.dumps({"copy_gbs": round(copy_gbs, 1)}), flush=True)
+        return
+
+    tune = None
+    if not args.no_tune:
+        log("bench: tuning the launch shape")
+        tune = U.autotune(spec, steps=args.tune_steps)
+        log(f"bench: tuned {tune}")
+    launch = {}
 
     def one_job(timed_kernel):
         job = U.Job(spec, device=0)
+        inf = job.info()
+        launch.update(layout={1: "aa", 2: "ab"}[inf.layout], cpt=inf.cpt, nt_store=inf.nt_store,
+                      plane_pad=inf.plane_pad, device_bytes=inf.device_bytes)
         ms = job.run_timed(spec["steps"]) if timed_kernel else None
         if not timed_kernel:
             job.run(spec["steps"])
@@ -140,7 +179,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "uqi::k_step", "bytes_per_launch": alg_bytes, "launch_ms": round(per_launch_ms, 5),
-            "bytes_per_node_update": bpn}
+            "bytes_per_node_update": bpn, "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     out = {
         "metric": "aggregate MLUPS & % HBM peak; UQ solves/hr + p50/p99 latency vs plain",
@@ -157,7 +197,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec["name"], "nx": spec["nx"], "ny": spec["ny"], "samples": S,
                    "lbm_steps": spec["steps"], "rule": spec["rule"], "precision": prec,
-                   "moments": "FP64 compensated, KE + velocity field"},
+                   "moments": "FP64 compensated, KE + velocity field", "launch": launch,
+                   "tuner_best_gbs": None if tune is None else round(tune["gbs"], 1)},
         "roofline": roof,
         "uq_solves_per_hour": round(3600.0 / (wall / args.steps), 1),
         "hbm_frac_of_peak": roof["frac"],

@@ -49,6 +49,13 @@ typedef enum {
     UQ_BF16S = 3  /* bfloat16 storage scaled by 2^s per job, float compute  */
 } uq_precision;
 
+/* Memory layout of the populations (an execution choice; results agree to
+ * rounding). AA: one slab updated in place (AA access pattern). AB: two slabs,
+ * pull from one and write aligned to the other (twice the memory, higher
+ * HBM rate on MI355X). AUTO: the launch-shape tuner's choice for the
+ * problem class (AA unless a measured AB entry exists or UQ_LAYOUT is set). */
+typedef enum { UQ_LAYOUT_AUTO = 0, UQ_LAYOUT_AA = 1, UQ_LAYOUT_AB = 2 } uq_layout;
+
 /* Deterministic problem solved for every sample. */
 typedef enum {
     /* Taylor-Green vortex on a fully periodic nx x ny lattice (Sec. "Taylor--
@@ -123,6 +130,7 @@ typedef struct {
     int32_t order;     /* GL: total gPC degree P (K = C(d+P, P) terms)      */
     int64_t mc_n;      /* MC: number of samples                             */
     uint64_t seed;     /* MC: generator seed                                */
+    int32_t layout;    /* uq_layout                                         */
 } uq_problem;
 
 /* Device context. `stream` is a hipStream_t (e.g. torch's current stream,
@@ -186,6 +194,10 @@ typedef struct {
     int64_t device_bytes; /* device memory held by the job            */
     int32_t scale_exp;  /* FP16S/BF16S storage scale 2^scale_exp       */
     int32_t fluid_nodes;
+    int32_t layout;     /* uq_layout in use (AA or AB)                 */
+    int32_t cpt;        /* rows per thread of the step kernel          */
+    int32_t nt_store;   /* 1 if AB stores bypass the caches            */
+    int32_t plane_pad;  /* padding elements after each population plane */
 } uq_job_info;
 
 /* Set up a job: sample the inputs, map each sample to its solver parameters,
@@ -234,6 +246,26 @@ void uq_destroy(uq_job *job);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *uq_last_error(void);
+
+/* Launch-shape autotuning. Times the step kernel of the problem (its real
+ * lattice and sample count) for every candidate shape -- layout AA or AB
+ * (only the problem's layout unless it is UQ_LAYOUT_AUTO), 1 or 2 rows per
+ * thread, plane padding 0 or 64 elements, cached or non-temporal AB stores --
+ * over `steps` steps each (rounded down to even, >= 2), on dev's device with
+ * temporary jobs. The fastest becomes the shape of every later job of the
+ * same class (precision, geometry, nx, ny, S, layout field) in this process,
+ * and is appended to the file named by UQ_TUNE_CACHE if set. Candidates that
+ * do not fit in device memory are skipped. Blocking. */
+typedef struct {
+    int32_t layout;
+    int32_t cpt;
+    int32_t nt_store;
+    int32_t plane_pad;
+    double gbs;         /* algorithmic GB/s of the best candidate (18 b per node) */
+    double ms_per_step; /* its average step duration                           */
+    int32_t n_candidates;
+} uq_tune_result;
+uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out);
 
 /* Host-only helpers (no device needed): the job's sample set and basis,
  * for callers that want the rule without creating a job.

@@ -23,6 +23,7 @@ GEOMETRY = {"tgv": 0, "channel": 1}
 XBC = {0: 0, 1: 1, 2: 2, "zouhe": 0, "walls": 1, "periodic": 2}
 TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5}
 RULE = {"gl": 0, "mc": 1}
+LAYOUT = {"auto": 0, "aa": 1, "ab": 2}
 QOI = {"ke": 0, "vel": 1, "cd": 2, "cl": 3, "rho": 4}
 MAX_DIMS = 8
 
@@ -44,6 +45,7 @@ class Problem(C.Structure):
         ("u_peak", C.c_double), ("D", C.c_int32), ("cx", C.c_int32), ("cy", C.c_int32), ("xbc", C.c_int32),
         ("ramp", C.c_int64), ("n_dists", C.c_int32), ("dists", Dist * MAX_DIMS), ("rule", C.c_int32),
         ("n_per_dim", C.c_int32), ("order", C.c_int32), ("mc_n", C.c_int64), ("seed", C.c_uint64),
+        ("layout", C.c_int32),
     ]
 
 
@@ -64,7 +66,13 @@ class MomentsOut(C.Structure):
 class JobInfo(C.Structure):
     _fields_ = [("S", C.c_int64), ("d", C.c_int32), ("K", C.c_int32), ("steps_done", C.c_int64),
                 ("pitch", C.c_int64), ("device_bytes", C.c_int64), ("scale_exp", C.c_int32),
-                ("fluid_nodes", C.c_int32)]
+                ("fluid_nodes", C.c_int32), ("layout", C.c_int32), ("cpt", C.c_int32), ("nt_store", C.c_int32),
+                ("plane_pad", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("layout", C.c_int32), ("cpt", C.c_int32), ("nt_store", C.c_int32), ("plane_pad", C.c_int32),
+                ("gbs", C.c_double), ("ms_per_step", C.c_double), ("n_candidates", C.c_int32)]
 
 
 # every symbol the header declares, with its signature
@@ -81,6 +89,7 @@ SIGNATURES = {
     "uq_job_get_info": (C.c_int, [_P, C.POINTER(JobInfo)]),
     "uq_destroy": (None, [_P]),
     "uq_last_error": (C.c_char_p, []),
+    "uq_autotune": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.c_int64, C.POINTER(TuneResult)]),
     "uq_rule_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "uq_rule_points": (C.c_int, [C.POINTER(Problem), _P, _P, _P, _P]),
 }
@@ -139,6 +148,7 @@ def make_problem(spec: dict) -> Problem:
     p.order = int(r.get("order", 0))
     p.mc_n = int(r.get("N", 0))
     p.seed = int(r.get("seed", 123456))
+    p.layout = LAYOUT[spec.get("layout", "auto")]
     return p
 
 
@@ -201,6 +211,18 @@ def torch_device(device: int = 0, stream=None, allocator=True):
         dev.free = FREE_FN()
     dev.ctx = None
     return dev, keep
+
+
+def autotune(spec: dict, steps: int = 40, device: int = 0) -> dict:
+    """uq_autotune: measure every launch-shape candidate of the problem class
+    and make the fastest the shape of later jobs of that class."""
+    dev, keep = torch_device(device, None, True)
+    p = make_problem(spec)
+    r = TuneResult()
+    check(lib().uq_autotune(C.byref(p), C.byref(dev), int(steps), C.byref(r)))
+    del keep
+    return {"layout": {1: "aa", 2: "ab"}[r.layout], "cpt": r.cpt, "nt_store": r.nt_store,
+            "plane_pad": r.plane_pad, "gbs": r.gbs, "ms_per_step": r.ms_per_step, "n_candidates": r.n_candidates}
 
 
 class Job:

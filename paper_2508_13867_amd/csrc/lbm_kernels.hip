@@ -5,16 +5,24 @@
 // quantification methods" (Eqs. meanMCS, varMCS, coef_discrete, gpc_mean,
 // gpc_std).
 //
-// Storage: per job one slab [S][9][ny][pitch] of shifted populations
-// f~_i = f_i - w_i (x fastest, pitch a multiple of 64 elements), updated in
-// place with the AA access pattern (Bailey et al. 2009):
+// Storage: shifted populations f~_i = f_i - w_i in slabs [S][9][ny][pitch]
+// (x fastest, pitch a multiple of 64 elements). Two layouts:
+//
+// AA (one slab, in place; Bailey et al. 2009):
 //   even step t: node x reads its own slots i, collides, and writes f*_i to
 //                its own slot opp(i);
 //   odd step t:  node x reads f_i(x,t) = f*_i(x - c_i, t-1) from slot opp(i)
 //                of node x - c_i, collides, and writes f*_i to slot i of
 //                node x + c_i, leaving the natural layout for step t+1.
-// Each node reads and writes exactly the same nine locations in either
-// parity, so one launch per step needs no second lattice and no barrier.
+//   Each node reads and writes exactly the same nine locations in either
+//   parity, so one launch per step needs no second lattice and no barrier.
+//
+// AB (two slabs, pull): slab t&1 holds g_i(x) = f*_i(x, t-1), the
+//   post-collision populations of the previous step; step t reads
+//   f_i(x,t) = g_i(x - c_i) (bounce-back: g_opp(i)(x)), collides and writes
+//   f*_i(x,t) to slot i of node x in the other slab: every store is aligned
+//   and can bypass the caches. Twice the memory of AA; on MI355X a
+//   two-buffer stream reaches a higher HBM rate than an in-place one.
 //
 // Direction order i = 0..8: (0,0), (1,0), (0,1), (-1,0), (0,-1), (1,1),
 // (-1,1), (-1,-1), (1,-1); opposite pairs (1,3), (2,4), (5,7), (6,8).
@@ -37,6 +45,7 @@ struct Prec<UQ_FP64> {
     using C = double;
     __device__ static inline C ld(const T *p, float) { return *p; }
     __device__ static inline void st(T *p, C v, float) { *p = v; }
+    __device__ static inline void st_nt(T *p, C v, float) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Prec<UQ_FP32> {
@@ -44,6 +53,7 @@ struct Prec<UQ_FP32> {
     using C = float;
     __device__ static inline C ld(const T *p, float) { return *p; }
     __device__ static inline void st(T *p, C v, float) { *p = v; }
+    __device__ static inline void st_nt(T *p, C v, float) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Prec<UQ_FP16S> {
@@ -53,6 +63,7 @@ struct Prec<UQ_FP16S> {
     // round-to-nearest-even (v_cvt_f16_f32 in the default mode)
     __device__ static inline C ld(const T *p, float inv) { return (float)(*p) * inv; }
     __device__ static inline void st(T *p, C v, float sc) { *p = (_Float16)(v * sc); }
+    __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store((_Float16)(v * sc), p); }
 };
 template <>
 struct Prec<UQ_BF16S> {
@@ -62,11 +73,13 @@ struct Prec<UQ_BF16S> {
         return __uint_as_float((uint32_t)(*p) << 16) * inv;
     }
     // round to nearest, ties to even, on the upper 16 bits
-    __device__ static inline void st(T *p, C v, float sc) {
-        uint32_t u = __float_as_uint(v * sc);
+    __device__ static inline uint16_t rne(float v) {
+        uint32_t u = __float_as_uint(v);
         u += 0x7FFFu + ((u >> 16) & 1u);
-        *p = (uint16_t)(u >> 16);
+        return (uint16_t)(u >> 16);
     }
+    __device__ static inline void st(T *p, C v, float sc) { *p = rne(v * sc); }
+    __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store(rne(v * sc), p); }
 };
 
 // ------------------------------------------------------------------ lattice
@@ -177,48 +190,62 @@ __device__ inline Site site(const JobDev &j, int x, int y) {
 __device__ inline int sx_of(const Site &s, int dx) { return dx == 0 ? s.x : (dx > 0 ? s.xp : s.xm); }
 __device__ inline int sy_of(const Site &s, int dy) { return dy == 0 ? s.y : (dy > 0 ? s.yp : s.ym); }
 
-// Gather f~(x, t) of one node in either parity, with bounce-back and Zou-He.
-template <int P, bool CHANNEL, int PARITY>
+// Access modes of a step / QoI read.
+enum : int { AA_EVEN = 0, AA_ODD = 1, AB_PULL = 2 };
+
+template <int LAYOUT, int PARITY>
+struct ModeOf {
+    static constexpr int value = LAYOUT == UQ_LAYOUT_AB ? AB_PULL : (PARITY ? AA_ODD : AA_EVEN);
+};
+
+// Gather f~(x, t) of one node, with bounce-back and Zou-He.
+template <int P, bool CHANNEL, int MODE>
 __device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
                               int64_t t, double u_peak, typename Prec<P>::C f[9]) {
     using PR = Prec<P>;
     const float inv = j.inv_scale;
     const int64_t pitch = j.pitch, plane = j.plane;
+    const int64_t own = (int64_t)s.y * pitch + s.x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        if (PARITY == 0) {
-            f[i] = PR::ld(base + i * plane + (int64_t)s.y * pitch + s.x, inv);
+        if (MODE == AA_EVEN) {
+            f[i] = PR::ld(base + i * plane + own, inv);
+        } else if (CHANNEL && (m & (1u << (M_BB + i)))) {
+            // bounce-back: f_i(x,t) = f*_opp(i)(x,t-1), stored at this node
+            // (AA odd: in slot i; AB: in slot opp(i))
+            f[i] = PR::ld(base + (MODE == AA_ODD ? i : OPPd[i]) * plane + own, inv);
+        } else if (CHANNEL && (m & (1u << (M_OPEN + i)))) {
+            f[i] = 0;  // rest state at t = 0, else filled by Zou-He below
         } else {
-            if (CHANNEL && (m & (1u << (M_BB + i)))) {
-                // bounce-back: the node's own post-collision f*_opp(i) sits in slot i
-                f[i] = PR::ld(base + i * plane + (int64_t)s.y * pitch + s.x, inv);
-            } else if (CHANNEL && (m & (1u << (M_OPEN + i)))) {
-                f[i] = 0;
-            } else {
-                const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
-                f[i] = PR::ld(base + OPPd[i] * plane + (int64_t)ys * pitch + xs, inv);
-            }
+            const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
+            f[i] = PR::ld(base + (MODE == AA_ODD ? OPPd[i] : i) * plane + (int64_t)ys * pitch + xs, inv);
         }
     }
     if (CHANNEL && (m & (0x1FFu << M_OPEN)) && t > 0) zou_he(f, j, s.x, s.y, t, u_peak);
 }
 
 // Scatter post-collision f*(x, t) to where step t+1 reads it.
-template <int P, bool CHANNEL, int PARITY>
+template <int P, bool CHANNEL, int MODE, bool NT>
 __device__ inline void scatter(const JobDev &j, typename Prec<P>::T *base, const Site &s, uint32_t m,
                                const typename Prec<P>::C f[9]) {
     using PR = Prec<P>;
     const float sc = j.scale;
     const int64_t pitch = j.pitch, plane = j.plane;
+    const int64_t own = (int64_t)s.y * pitch + s.x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        if (PARITY == 0) {
-            PR::st(base + OPPd[i] * plane + (int64_t)s.y * pitch + s.x, f[i], sc);
+        if (MODE == AB_PULL) {
+            if (NT)
+                PR::st_nt(base + i * plane + own, f[i], sc);
+            else
+                PR::st(base + i * plane + own, f[i], sc);
+        } else if (MODE == AA_EVEN) {
+            PR::st(base + OPPd[i] * plane + own, f[i], sc);
         } else {
             const int o = OPPd[i];
             if (CHANNEL && (m & (1u << (M_BB + o)))) {
                 // destination is a wall: f*_i returns to this node as f_opp(i)
-                PR::st(base + o * plane + (int64_t)s.y * pitch + s.x, f[i], sc);
+                PR::st(base + o * plane + own, f[i], sc);
             } else if (CHANNEL && (m & (1u << (M_OPEN + o)))) {
                 // leaves through an open column
             } else {
@@ -227,6 +254,12 @@ __device__ inline void scatter(const JobDev &j, typename Prec<P>::T *base, const
             }
         }
     }
+}
+
+// Slab holding the state at step t (AA: the only one; AB: slab t & 1).
+template <int LAYOUT>
+__device__ inline void *state_slab(const JobDev &j, int64_t t) {
+    return (LAYOUT == UQ_LAYOUT_AB && (t & 1)) ? j.f2 : j.f;
 }
 
 // ------------------------------------------------------------------ tile walk
@@ -241,73 +274,102 @@ __device__ inline int64_t xcd_logical(int64_t b, int64_t G) {
 constexpr int BX = 64;  // nodes along x per tile (one wavefront)
 constexpr int BY = 4;   // wavefronts per workgroup
 
-template <int P, bool CHANNEL, int PARITY>
-__global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int k, int cpt, int tiles_x,
-                                              int tiles_y, int64_t ntiles) {
+// One step for every live node of every sample. A workgroup is 64 x 4
+// threads; a tile is 64 nodes along x by 4*CPT rows, and each thread takes
+// CPT rows 4 apart. All CPT nodes of a thread are gathered before any is
+// written back: in the AA pattern a node reads and writes only its own nine
+// locations (and in AB reads and writes different slabs), so the nodes are
+// independent and the loads of all CPT rows can be in flight together.
+template <int P, bool CHANNEL, int PARITY, int CPT, int LAYOUT, bool NT>
+__global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int k, int tiles_x, int tiles_y,
+                                              int64_t ntiles) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
+    constexpr int MODE = ModeOf<LAYOUT, PARITY>::value;
     const int64_t t = *d_t + k;
     const int64_t G = gridDim.x;
     const int64_t lb = xcd_logical(blockIdx.x, G);
     const int64_t per_sample = (int64_t)tiles_x * tiles_y;
+    T *src_all = (T *)(LAYOUT == UQ_LAYOUT_AB && PARITY ? j.f2 : j.f);
+    T *dst_all = (T *)(LAYOUT == UQ_LAYOUT_AB && !PARITY ? j.f2 : j.f);
     for (int64_t tile = lb; tile < ntiles; tile += G) {
         const int64_t smp = tile / per_sample;
         const int64_t rem = tile - smp * per_sample;
         const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
         const int x = tx * BX + threadIdx.x;
-        const C omega = (C)j.smp[smp].omega;
-        const double u_peak = j.smp[smp].u_peak;
-        T *base = (T *)j.f + smp * 9 * j.plane;
         if (x >= j.nx) continue;
-        const int y0 = ty * BY * cpt + threadIdx.y;
-        for (int r = 0; r < cpt; ++r) {
+        const C omega = (C)j.smp[smp].omega;
+        const double u_peak = CHANNEL ? j.smp[smp].u_peak : 0.0;
+        const T *src = src_all + smp * 9 * j.plane;
+        T *dst = dst_all + smp * 9 * j.plane;
+        const int y0 = ty * BY * CPT + threadIdx.y;
+        C f[CPT][9];
+        uint32_t m[CPT];
+        bool live[CPT];
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
             const int y = y0 + r * BY;
-            if (y >= j.ny) break;
-            uint32_t m = 0;
-            if (CHANNEL) {
-                m = j.mask[(int64_t)y * j.pitch + x];
-                if (m & M_SOLID) continue;
+            live[r] = y < j.ny;
+            m[r] = 0;
+            if (CHANNEL && live[r]) {
+                m[r] = j.mask[(int64_t)y * j.pitch + x];
+                live[r] = !(m[r] & M_SOLID);
             }
-            const Site s = site(j, x, y);
-            C f[9], drho, ux, uy;
-            gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
-            bgk(f, omega, drho, ux, uy);
-            scatter<P, CHANNEL, PARITY>(j, base, s, m, f);
+            if (live[r]) gather<P, CHANNEL, MODE>(j, src, site(j, x, y), m[r], t, u_peak, f[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            if (!live[r]) continue;
+            C drho, ux, uy;
+            bgk(f[r], omega, drho, ux, uy);
+            scatter<P, CHANNEL, MODE, NT>(j, dst, site(j, x, y0 + r * BY), m[r], f[r]);
         }
     }
 }
 
 // ------------------------------------------------------------------ init
-template <int P>
+// Equilibrium start. AA stores f~_eq(x) in slot i of node x. AB stores
+// g_i(x - c_i) = f~_eq,i(x) (the value the first pull of node x reads), so
+// every node computes its own equilibrium once and writes it to the nine
+// nodes x - c_i (periodic wrap; the channel starts at rest, f~ = 0).
+template <int P, int LAYOUT>
 __global__ __launch_bounds__(256) void k_init(JobDev j) {
     using PR = Prec<P>;
     using T = typename PR::T;
     const int64_t cells = (int64_t)j.ny * j.pitch;
     for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
-    T *base = (T *)j.f + smp * 9 * j.plane;
-    const SampleDev sd = j.smp[smp];
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
-        const int y = (int)(c / j.pitch), x = (int)(c - (int64_t)y * j.pitch);
-        double f[9];
-        for (int i = 0; i < 9; ++i) f[i] = 0.0;
-        if (x < j.nx && j.geom == 0) {
-            // Taylor-Green vortex (Eqs. TGV_vel, TGV_press at t = 0), rho = 1 + 3p
-            const double kx = 2.0 * M_PI / j.nx, ky = 2.0 * M_PI / j.ny;
-            const double ax = kx * x + sd.phase_x, ay = ky * y + sd.phase_y;
-            const double ux = -sd.u0 * cos(ax) * sin(ay);
-            const double uy = sd.u0 * sin(ax) * cos(ay);
-            const double p = -0.25 * sd.u0 * sd.u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
-            const double drho = 3.0 * p, rho = 1.0 + drho;
-            const double uu = 1.5 * (ux * ux + uy * uy);
-            for (int i = 0; i < 9; ++i) {
-                const double cu = CXd[i] * ux + CYd[i] * uy;
-                f[i] = wgt<double>(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - uu));
+        T *base = (T *)j.f + smp * 9 * j.plane;
+        const SampleDev sd = j.smp[smp];
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+             c += (int64_t)gridDim.x * blockDim.x) {
+            const int y = (int)(c / j.pitch), x = (int)(c - (int64_t)y * j.pitch);
+            double f[9];
+            for (int i = 0; i < 9; ++i) f[i] = 0.0;
+            if (x < j.nx && j.geom == 0) {
+                // Taylor-Green vortex (Eqs. TGV_vel, TGV_press at t = 0), rho = 1 + 3p
+                const double kx = 2.0 * M_PI / j.nx, ky = 2.0 * M_PI / j.ny;
+                const double ax = kx * x + sd.phase_x, ay = ky * y + sd.phase_y;
+                const double ux = -sd.u0 * cos(ax) * sin(ay);
+                const double uy = sd.u0 * sin(ax) * cos(ay);
+                const double p = -0.25 * sd.u0 * sd.u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
+                const double drho = 3.0 * p, rho = 1.0 + drho;
+                const double uu = 1.5 * (ux * ux + uy * uy);
+                for (int i = 0; i < 9; ++i) {
+                    const double cu = CXd[i] * ux + CYd[i] * uy;
+                    f[i] = wgt<double>(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - uu));
+                }
+            }
+            if (LAYOUT == UQ_LAYOUT_AB && x < j.nx) {
+                const Site s = site(j, x, y);
+                for (int i = 0; i < 9; ++i) {
+                    const int xd = sx_of(s, -CXd[i]), yd = sy_of(s, -CYd[i]);
+                    PR::st(base + i * j.plane + (int64_t)yd * j.pitch + xd, (typename PR::C)f[i], j.scale);
+                }
+            } else if (LAYOUT != UQ_LAYOUT_AB) {
+                for (int i = 0; i < 9; ++i) PR::st(base + i * j.plane + c, (typename PR::C)f[i], j.scale);
             }
         }
-        // channel: rest state rho = 1, u = 0, i.e. f~ = 0 everywhere
-        for (int i = 0; i < 9; ++i) PR::st(base + i * j.plane + c, (typename PR::C)f[i], j.scale);
-    }
     }
 }
 
@@ -324,13 +386,13 @@ struct NSum {
 };
 
 // One workgroup per sample: KE, momentum-exchange force, non-finite count.
-template <int P, bool CHANNEL, int PARITY>
+template <int P, bool CHANNEL, int MODE>
 __global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     const int64_t smp = blockIdx.x;
-    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
     const SampleDev sd = j.smp[smp];
     NSum ke, fx, fy;
     double bad = 0.0;
@@ -344,7 +406,7 @@ __global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
         }
         const Site s = site(j, x, y);
         C f[9], drho, ux, uy;
-        gather<P, CHANNEL, PARITY>(j, base, s, m, t, sd.u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, sd.u_peak, f);
         if (CHANNEL && (m & (0x1FFu << M_CYL))) {
             bgk(f, (C)sd.omega, drho, ux, uy);
             for (int i = 1; i < 9; ++i)
@@ -377,14 +439,14 @@ __global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
 }
 
 // Per-sample fields: out[s][3][ny][nx] = ux, uy, rho (0 at solid nodes).
-template <int P, bool CHANNEL, int PARITY>
+template <int P, bool CHANNEL, int MODE>
 __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     const int64_t cells = (int64_t)j.nx * j.ny;
     for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
-    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
     const double u_peak = j.smp[smp].u_peak;
     double *o = out + smp * 3 * cells;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
@@ -401,7 +463,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
         }
         const Site s = site(j, x, y);
         C f[9], drho, ux, uy;
-        gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, f);
         moments(f, drho, ux, uy);
         o[c] = (double)ux;
         o[cells + c] = (double)uy;
@@ -411,13 +473,13 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
 }
 
 // One sample's unshifted populations, natural order [9][ny][nx] in double.
-template <int P, bool CHANNEL, int PARITY>
+template <int P, bool CHANNEL, int MODE>
 __global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp, double *out) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     const int64_t cells = (int64_t)j.nx * j.ny;
-    const T *base = (const T *)j.f + smp * 9 * j.plane;
+    const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
     const double u_peak = j.smp[smp].u_peak;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
@@ -431,7 +493,7 @@ __global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp
         }
         const Site s = site(j, x, y);
         C f[9];
-        gather<P, CHANNEL, PARITY>(j, base, s, m, t, u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, f);
         for (int i = 0; i < 9; ++i) out[i * cells + c] = (double)f[i] + wgt<double>(i);
     }
 }
@@ -467,8 +529,11 @@ __global__ __launch_bounds__(256) void k_gpc_coeffs(const double *M, int64_t S, 
             }
         }
     }
-    if (o < n_out)
-        for (int kk = 0; kk < nk; ++kk) coeffs[(int64_t)(k0 + kk) * n_out + o] = acc[kk].val();
+    if (o < n_out) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+            if (kk < nk) coeffs[(int64_t)(k0 + kk) * n_out + o] = acc[kk].val();
+    }
 }
 
 // mean = c_0 (Eq. gpc_mean), var = sum_{k>=1} c_k^2 (Eq. gpc_std), and the
@@ -533,65 +598,98 @@ __global__ void k_select(const double *qoi, const SampleDev *smp, int64_t S, int
 }
 
 // ------------------------------------------------------------------ launchers
+// Launch a read-only state kernel (QoIs, fields, export) in the access mode
+// of the job's layout and the parity of t.
+#define UQ_DISPATCH_P(KERNEL, PP, MODE_, CH_, GRID, BLOCK, STREAM, ...)                               \
+    do {                                                                                           \
+        if (CH_) {                                                                                 \
+            if (MODE_ == AA_EVEN) KERNEL<PP, true, AA_EVEN><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
+            else if (MODE_ == AA_ODD) KERNEL<PP, true, AA_ODD><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
+            else KERNEL<PP, true, AB_PULL><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);               \
+        } else {                                                                                   \
+            if (MODE_ == AA_EVEN) KERNEL<PP, false, AA_EVEN><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
+            else if (MODE_ == AA_ODD) KERNEL<PP, false, AA_ODD><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
+            else KERNEL<PP, false, AB_PULL><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);              \
+        }                                                                                          \
+    } while (0)
+
 #define UQ_DISPATCH(KERNEL, PARITY, GRID, BLOCK, STREAM, ...)                                      \
     do {                                                                                           \
-        const int par_ = (int)(PARITY);                                                            \
+        const int md_ = j.layout == UQ_LAYOUT_AB ? AB_PULL : ((PARITY) ? AA_ODD : AA_EVEN);        \
         const bool ch_ = j.geom == 1;                                                              \
         switch (j.prec) {                                                                          \
-            case UQ_FP64:                                                                          \
-                if (ch_) {                                                                         \
-                    if (par_) KERNEL<UQ_FP64, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);   \
-                    else KERNEL<UQ_FP64, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);        \
-                } else {                                                                           \
-                    if (par_) KERNEL<UQ_FP64, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
-                    else KERNEL<UQ_FP64, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
-                }                                                                                  \
-                break;                                                                             \
-            case UQ_FP32:                                                                          \
-                if (ch_) {                                                                         \
-                    if (par_) KERNEL<UQ_FP32, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);   \
-                    else KERNEL<UQ_FP32, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);        \
-                } else {                                                                           \
-                    if (par_) KERNEL<UQ_FP32, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
-                    else KERNEL<UQ_FP32, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
-                }                                                                                  \
-                break;                                                                             \
-            case UQ_FP16S:                                                                         \
-                if (ch_) {                                                                         \
-                    if (par_) KERNEL<UQ_FP16S, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
-                    else KERNEL<UQ_FP16S, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
-                } else {                                                                           \
-                    if (par_) KERNEL<UQ_FP16S, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
-                    else KERNEL<UQ_FP16S, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);      \
-                }                                                                                  \
-                break;                                                                             \
-            default:                                                                               \
-                if (ch_) {                                                                         \
-                    if (par_) KERNEL<UQ_BF16S, true, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);  \
-                    else KERNEL<UQ_BF16S, true, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);       \
-                } else {                                                                           \
-                    if (par_) KERNEL<UQ_BF16S, false, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__); \
-                    else KERNEL<UQ_BF16S, false, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);      \
-                }                                                                                  \
-                break;                                                                             \
+            case UQ_FP64: UQ_DISPATCH_P(KERNEL, UQ_FP64, md_, ch_, GRID, BLOCK, STREAM, __VA_ARGS__); break;   \
+            case UQ_FP32: UQ_DISPATCH_P(KERNEL, UQ_FP32, md_, ch_, GRID, BLOCK, STREAM, __VA_ARGS__); break;   \
+            case UQ_FP16S: UQ_DISPATCH_P(KERNEL, UQ_FP16S, md_, ch_, GRID, BLOCK, STREAM, __VA_ARGS__); break; \
+            default: UQ_DISPATCH_P(KERNEL, UQ_BF16S, md_, ch_, GRID, BLOCK, STREAM, __VA_ARGS__); break;       \
         }                                                                                          \
     } while (0)
 
 hipError_t launch_init(const JobDev &j, hipStream_t s) {
     const int64_t cells = (int64_t)j.ny * j.pitch;
     dim3 grid((unsigned)std::min<int64_t>((cells + 255) / 256, 1024), (unsigned)std::min<int64_t>(j.S, 65535));
+    const bool ab = j.layout == UQ_LAYOUT_AB;
     switch (j.prec) {
-        case UQ_FP64: k_init<UQ_FP64><<<grid, 256, 0, s>>>(j); break;
-        case UQ_FP32: k_init<UQ_FP32><<<grid, 256, 0, s>>>(j); break;
-        case UQ_FP16S: k_init<UQ_FP16S><<<grid, 256, 0, s>>>(j); break;
-        default: k_init<UQ_BF16S><<<grid, 256, 0, s>>>(j); break;
+        case UQ_FP64:
+            if (ab) k_init<UQ_FP64, UQ_LAYOUT_AB><<<grid, 256, 0, s>>>(j);
+            else k_init<UQ_FP64, UQ_LAYOUT_AA><<<grid, 256, 0, s>>>(j);
+            break;
+        case UQ_FP32:
+            if (ab) k_init<UQ_FP32, UQ_LAYOUT_AB><<<grid, 256, 0, s>>>(j);
+            else k_init<UQ_FP32, UQ_LAYOUT_AA><<<grid, 256, 0, s>>>(j);
+            break;
+        case UQ_FP16S:
+            if (ab) k_init<UQ_FP16S, UQ_LAYOUT_AB><<<grid, 256, 0, s>>>(j);
+            else k_init<UQ_FP16S, UQ_LAYOUT_AA><<<grid, 256, 0, s>>>(j);
+            break;
+        default:
+            if (ab) k_init<UQ_BF16S, UQ_LAYOUT_AB><<<grid, 256, 0, s>>>(j);
+            else k_init<UQ_BF16S, UQ_LAYOUT_AA><<<grid, 256, 0, s>>>(j);
+            break;
     }
     return hipGetLastError();
 }
 
+template <int P, bool CH, int CPT>
+static void step_p(const JobDev &j, const int64_t *d_t, int k, int parity, bool nt, dim3 grid, dim3 block,
+                   hipStream_t s, int tiles_x, int tiles_y, int64_t ntiles) {
+#define UQ_STEP(PAR, LAY, NT_) k_step<P, CH, PAR, CPT, LAY, NT_><<<grid, block, 0, s>>>(j, d_t, k, tiles_x, tiles_y, ntiles)
+    if (j.layout == UQ_LAYOUT_AB) {
+        if (nt) { if (parity) UQ_STEP(1, UQ_LAYOUT_AB, true); else UQ_STEP(0, UQ_LAYOUT_AB, true); }
+        else { if (parity) UQ_STEP(1, UQ_LAYOUT_AB, false); else UQ_STEP(0, UQ_LAYOUT_AB, false); }
+    } else {
+        if (parity) UQ_STEP(1, UQ_LAYOUT_AA, false); else UQ_STEP(0, UQ_LAYOUT_AA, false);
+    }
+#undef UQ_STEP
+}
+
+template <int CPT>
+static void step_cpt(const JobDev &j, const int64_t *d_t, int k, int parity, bool nt, dim3 grid, dim3 block,
+                     hipStream_t s, int tiles_x, int tiles_y, int64_t ntiles) {
+    const bool ch = j.geom == 1;
+    switch (j.prec) {
+        case UQ_FP64:
+            if (ch) step_p<UQ_FP64, true, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            else step_p<UQ_FP64, false, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            break;
+        case UQ_FP32:
+            if (ch) step_p<UQ_FP32, true, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            else step_p<UQ_FP32, false, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            break;
+        case UQ_FP16S:
+            if (ch) step_p<UQ_FP16S, true, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            else step_p<UQ_FP16S, false, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            break;
+        default:
+            if (ch) step_p<UQ_BF16S, true, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            else step_p<UQ_BF16S, false, CPT>(j, d_t, k, parity, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+            break;
+    }
+}
+
 hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
                        hipStream_t s) {
-    const int cpt = shape.cpt < 1 ? 1 : shape.cpt;
+    const int cpt = shape.cpt <= 1 ? 1 : 2;
     const int tiles_x = (j.nx + BX - 1) / BX;
     const int tiles_y = (j.ny + BY * cpt - 1) / (BY * cpt);
     const int64_t ntiles = (int64_t)j.S * tiles_x * tiles_y;
@@ -600,7 +698,9 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
     if (G > 0x7fffffff) G = 0x7fffffff;
     dim3 block(BX, BY);
     dim3 grid((unsigned)G);
-    UQ_DISPATCH(k_step, parity & 1, grid, block, s, j, d_t, k, cpt, tiles_x, tiles_y, ntiles);
+    const bool nt = shape.nt != 0;
+    if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
+    else step_cpt<2>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
     return hipGetLastError();
 }
 

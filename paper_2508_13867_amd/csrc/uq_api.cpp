@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -127,12 +128,10 @@ uq_status Job::ensure_fields() {
 
 }  // namespace uqi
 
-using namespace uqi;
+namespace uqi {
 
-struct uq_job : public uqi::Job {};
-
-extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job **out) {
-    if (!p || !out) return fail(UQ_EINVAL, "null argument");
+uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepShape *forced, uq_job **out) {
+    const uq_problem *p = &prob;
     *out = nullptr;
     std::unique_ptr<uq_job> j(new uq_job());
     j->p = *p;
@@ -143,7 +142,8 @@ extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job
     j->S = j->rule.S;
     j->K = j->rule.K;
     j->pitch = row_pitch(P.nx);
-    if (9 * (int64_t)P.ny * j->pitch >= ((int64_t)1 << 31)) return fail(UQ_EINVAL, "lattice too large for one sample");
+    if (9 * ((int64_t)P.ny * j->pitch + 4096) >= ((int64_t)1 << 31))
+        return fail(UQ_EINVAL, "lattice too large for one sample");
     j->user_stream = (hipStream_t)j->dev.stream;
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
     UQ_HIP_TRY(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
@@ -188,9 +188,21 @@ extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job
     if (P.geometry == UQ_GEOM_CHANNEL) build_mask(P, j->pitch, mask, j->fluid);
 
     // device buffers
-    const int64_t plane = (int64_t)P.ny * j->pitch;
+    j->shape = forced ? *forced : choose_shape(P, j->S);
+    // padding after each population plane (elements, multiple of 64): spreads
+    // the nine plane streams of a wavefront over HBM channels
+    const int64_t pad = std::max(0, j->shape.pad) / 64 * 64;
+    const int64_t plane = (int64_t)P.ny * j->pitch + pad;
     const int64_t slab_bytes = j->S * 9 * plane * storage_bytes(P.precision);
     void *slab = j->dalloc((size_t)slab_bytes);
+    void *slab2 = nullptr;
+    if (j->shape.layout == UQ_LAYOUT_AB) {
+        slab2 = j->dalloc((size_t)slab_bytes);
+        if (!slab2) {
+            j->dfree_all();
+            return fail(UQ_ENOMEM, "out of device memory for the second slab (" + std::to_string(slab_bytes) + " B)");
+        }
+    }
     SampleDev *d_smp = (SampleDev *)j->dalloc(sizeof(SampleDev) * j->S);
     j->d_t = (int64_t *)j->dalloc(sizeof(int64_t));
     uint32_t *d_mask = nullptr;
@@ -231,6 +243,8 @@ extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job
     JobDev &jd = j->jd;
     std::memset(&jd, 0, sizeof jd);
     jd.f = slab;
+    jd.f2 = slab2;
+    jd.layout = j->shape.layout;
     jd.smp = d_smp;
     jd.mask = d_mask;
     jd.pitch = j->pitch;
@@ -247,7 +261,7 @@ extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job
     const double uref = P.geometry == UQ_GEOM_TGV ? P.u0 : P.u_peak;
     jd.ke_norm = uref != 0.0 ? 2.0 / ((double)P.nx * P.ny * uref * uref) : 1.0;
     jd.D = P.D;
-    j->shape = default_shape(P);
+    j->plane_pad = (int)pad;
 
     UQ_HIP_TRY(launch_init(jd, j->stream));
     {
@@ -256,6 +270,15 @@ extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job
     }
     *out = j.release();
     return UQ_OK;
+}
+
+}  // namespace uqi
+
+using namespace uqi;
+
+extern "C" uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job **out) {
+    if (!p || !out) return fail(UQ_EINVAL, "null argument");
+    return create_job(*p, dev, nullptr, out);
 }
 
 extern "C" uq_status uq_samples(const uq_job *j, double *xi, double *a, int64_t *S, int32_t *d) {
@@ -423,6 +446,10 @@ extern "C" uq_status uq_job_get_info(const uq_job *j, uq_job_info *info) {
     info->device_bytes = j->bytes_held;
     info->scale_exp = j->scale_exp;
     info->fluid_nodes = j->fluid;
+    info->layout = j->shape.layout;
+    info->cpt = j->shape.cpt;
+    info->nt_store = j->shape.nt;
+    info->plane_pad = j->plane_pad;
     return UQ_OK;
 }
 

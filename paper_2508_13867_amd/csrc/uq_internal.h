@@ -70,7 +70,8 @@ enum : uint32_t {
 
 // A job as the kernels see it.
 struct JobDev {
-    void *f;               // population slab [S][9][ny][pitch]
+    void *f;               // population slab [S][9][ny][pitch] (AB: state at even t)
+    void *f2;              // AB: second slab (state at odd t); AA: null
     const SampleDev *smp;  // [S]
     const uint32_t *mask;  // [ny][pitch] or null (TGV)
     int64_t pitch;         // elements per row
@@ -83,13 +84,16 @@ struct JobDev {
     double ramp;            // T_r (0: none)
     double ke_norm;         // 2/(nx ny u0^2)
     int32_t D;
-    int32_t pad0;
+    int32_t layout;         // UQ_LAYOUT_AA or UQ_LAYOUT_AB
 };
 
 // ------------------------------------------------------------------ kernel launchers
 struct StepShape {
-    int cpt = 2;       // cells per thread along y
+    int cpt = 1;        // rows per thread (1 or 2)
     int persistent = 0; // 0: one workgroup per tile; >0: workgroups per CU
+    int nt = 1;         // AB layout: non-temporal (cache-bypassing) stores
+    int layout = UQ_LAYOUT_AA;
+    int pad = 64;       // elements of padding after each population plane
 };
 
 // one stream-collide step for all samples at time t = *d_t + k; `parity`

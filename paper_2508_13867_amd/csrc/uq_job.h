@@ -13,7 +13,9 @@ namespace uqi {
 int64_t storage_bytes(int prec);
 int64_t row_pitch(int nx);
 void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, int &fluid);
-StepShape default_shape(const uq_problem &p);
+StepShape choose_shape(const uq_problem &p, int64_t S);
+// tuned shape for a problem class, if one was measured in this process
+bool tuned_shape(const uq_problem &p, int64_t S, StepShape *out);
 
 struct Job {
     uq_problem p{};
@@ -24,6 +26,7 @@ struct Job {
     int64_t pitch = 0;
     int scale_exp = 0;
     int fluid = 0;
+    int plane_pad = 0;
 
     hipStream_t user_stream = nullptr;  // caller's stream (ordering only)
     hipStream_t stream = nullptr;       // the job's own work stream
@@ -58,4 +61,11 @@ struct Job {
     void release_graph();
 };
 
+}  // namespace uqi
+
+struct uq_job : public uqi::Job {};
+
+namespace uqi {
+// Build a job; `forced` (may be null) fixes layout and launch shape.
+uq_status create_job(const uq_problem &p, const uq_device *dev, const StepShape *forced, uq_job **out);
 }  // namespace uqi

@@ -38,10 +38,11 @@ TGV_RAGGED = dict(name="tgv72x40", geometry="tgv", precision="fp64", nx=72, ny=4
                   phase_x=0.3, phase_y=-0.7)
 
 
+@pytest.mark.parametrize("layout", ["aa", "ab"])
 @pytest.mark.parametrize("steps", [0, 1, 2, 7, 40])
-def test_tgv_fp64_populations_match_oracle(steps):
-    say("case tgv72x40 fp64 steps", steps)
-    with Job(TGV_RAGGED) as job:
+def test_tgv_fp64_populations_match_oracle(steps, layout):
+    say("case tgv72x40 fp64 steps", steps, layout)
+    with Job(W.scaled(TGV_RAGGED, layout=layout)) as job:
         job.run(steps)
         xi, a = job.samples()
         for s in (0, 4, 8):
@@ -51,10 +52,11 @@ def test_tgv_fp64_populations_match_oracle(steps):
             assert np.abs(got - ref).max() < 1e-13, (s, np.abs(got - ref).max())
 
 
-def test_tgv_fp64_moments_match_oracle():
-    say("case tgv72x40 fp64 moments")
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_tgv_fp64_moments_match_oracle(layout):
+    say("case tgv72x40 fp64 moments", layout)
     ref = O.run_problem(TGV_RAGGED)
-    with Job(TGV_RAGGED) as job:
+    with Job(W.scaled(TGV_RAGGED, layout=layout)) as job:
         job.run(TGV_RAGGED["steps"])
         ke = job.qoi_samples("ke")[:, 0]
         assert rel_l2(ke, ref["samples"]["ke"]) < TOL["fp64"]
@@ -93,10 +95,11 @@ def tgv4d_ref():
     return O.run_problem(TGV_4D_SMALL)
 
 
+@pytest.mark.parametrize("layout", ["aa", "ab"])
 @pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
-def test_tgv_4d_reduced_precision(prec, tgv4d_ref):
-    spec = W.scaled(TGV_4D_SMALL, precision=prec)
-    say("case tgv96x80_4d", prec)
+def test_tgv_4d_reduced_precision(prec, layout, tgv4d_ref):
+    spec = W.scaled(TGV_4D_SMALL, precision=prec, layout=layout)
+    say("case tgv96x80_4d", prec, layout)
     ref = tgv4d_ref
     tol = TOL[prec]
     with Job(spec) as job:
@@ -140,10 +143,11 @@ CHANNEL_SMALL = dict(name="chan100x41", geometry="channel", precision="fp64", nx
                      dists=[("re", 16.0, 24.0), ("u_peak", 0.045, 0.055)], rule=dict(kind="gl", n=2, order=1))
 
 
-@pytest.mark.parametrize("steps", [1, 2, 201, 401])
-def test_channel_fp64_populations(steps):
-    say("case chan100x41 fp64 steps", steps)
-    with Job(CHANNEL_SMALL) as job:
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+@pytest.mark.parametrize("steps", [0, 1, 2, 201, 401])
+def test_channel_fp64_populations(steps, layout):
+    say("case chan100x41 fp64 steps", steps, layout)
+    with Job(W.scaled(CHANNEL_SMALL, layout=layout)) as job:
         job.run(steps)
         xi, a = job.samples()
         for s in (0, 3):
@@ -154,10 +158,11 @@ def test_channel_fp64_populations(steps):
             assert np.abs(got - ref).max() < 1e-13, (s, np.abs(got - ref).max())
 
 
-def test_channel_fp64_drag_lift_moments():
-    say("case chan100x41 fp64 moments")
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_channel_fp64_drag_lift_moments(layout):
+    say("case chan100x41 fp64 moments", layout)
     ref = O.run_problem(CHANNEL_SMALL)
-    with Job(CHANNEL_SMALL) as job:
+    with Job(W.scaled(CHANNEL_SMALL, layout=layout)) as job:
         job.run(CHANNEL_SMALL["steps"])
         for q in ("cd", "cl"):
             got = job.qoi_samples(q)[:, 0]
@@ -169,11 +174,12 @@ def test_channel_fp64_drag_lift_moments():
         assert rel_l2(st["coeffs"], ref["stats"]["vel"]["coeffs"]) < TOL["fp64"]
 
 
-def test_cylinder_config_geometry_fp32_sampled():
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_cylinder_config_geometry_fp32_sampled(layout):
     # the 440 x 82 cylinder workload (64 samples) at reduced steps; two
     # samples are re-solved by the oracle one by one
-    spec = W.scaled(W.CYLINDER_FP32, steps=600)
-    say("case", spec["name"], "600 steps")
+    spec = W.scaled(W.CYLINDER_FP32, steps=600, layout=layout)
+    say("case", spec["name"], "600 steps", layout)
     with Job(spec) as job:
         job.run(spec["steps"])
         xi, a = job.samples()
@@ -190,11 +196,12 @@ def test_cylinder_config_geometry_fp32_sampled():
 
 # ----------------------------------------------------------------- full-size batched TGV
 
-def test_batched_tgv256_fp32_sampled():
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_batched_tgv256_fp32_sampled(layout):
     # 256^2 x 256 samples in the benchmark's launch configuration, 100 steps;
     # three samples re-solved by the oracle
-    spec = W.scaled(W.TGV_BATCHED_FP32, steps=100)
-    say("case", spec["name"], "100 steps")
+    spec = W.scaled(W.TGV_BATCHED_FP32, steps=100, layout=layout)
+    say("case", spec["name"], "100 steps", layout)
     with Job(spec) as job:
         job.run(spec["steps"])
         ke = job.qoi_samples("ke")[:, 0]
@@ -207,9 +214,10 @@ def test_batched_tgv256_fp32_sampled():
 
 # ----------------------------------------------------------------- engine behaviour
 
-def test_graph_replay_equals_eager(monkeypatch):
-    spec = W.scaled(TGV_4D_SMALL, steps=150)
-    say("case graph vs eager")
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_graph_replay_equals_eager(monkeypatch, layout):
+    spec = W.scaled(TGV_4D_SMALL, steps=150, layout=layout)
+    say("case graph vs eager", layout)
     monkeypatch.setenv("UQ_GRAPH_STEPS", "32")
     with Job(spec) as a:
         a.run(3)
@@ -222,6 +230,21 @@ def test_graph_replay_equals_eager(monkeypatch):
         fb = b.populations(5)
         kb = b.qoi_samples("ke")
     assert np.array_equal(fa, fb) and np.array_equal(ka, kb)
+
+
+def test_layouts_agree_fp64():
+    # AA and AB perform the same per-node arithmetic (up to the compiler's
+    # fused multiply-adds): results agree to rounding
+    spec = W.scaled(CHANNEL_SMALL, steps=77)
+    say("case layouts agree")
+    with Job(W.scaled(spec, layout="aa")) as a, Job(W.scaled(spec, layout="ab")) as b:
+        assert a.info().layout == 1 and b.info().layout == 2
+        a.run(77)
+        b.run(77)
+        for s_ in range(4):
+            d = float(np.abs(a.populations(s_) - b.populations(s_)).max())
+            assert d < 1e-14, d
+        assert rel_l2(a.qoi_samples("cd"), b.qoi_samples("cd")) < 1e-12
 
 
 def test_unstable_sample_is_reported():
@@ -240,3 +263,16 @@ def test_nonpositive_viscosity_rejected():
     with pytest.raises(UQError) as e:
         Job(spec)
     assert e.value.status == A.UQ_EINVAL
+
+
+def test_autotune_picks_a_candidate_and_jobs_use_it():
+    spec = W.scaled(TGV_4D_SMALL, steps=20)
+    say("case autotune")
+    r = A.autotune(spec, steps=10)
+    assert r["n_candidates"] == 12 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    with Job(spec) as job:
+        inf = job.info()
+        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad) == (r["layout"], r["cpt"], r["plane_pad"])
+        job.run(20)
+        ref = O.run_problem(spec, qois=["ke"])
+        assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
