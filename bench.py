@@ -70,6 +70,45 @@ def copy_probe(torch, nbytes=1207959552, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def serving(U, W, n_jobs, load, log):
+    """Replay one seeded Poisson trace of mixed UQ jobs through the
+    continuous-batching server and through the plain server (one job at a
+    time, one sample per launch, no graph; same kernels): solves/hour, job
+    latency percentiles (completion - arrival), aggregate MLUPS, and the
+    largest relative difference between the two modes' moments."""
+    trace = W.serving_trace(n_jobs=n_jobs, load=load)
+    out = {"jobs": n_jobs, "load": load, "trace_seed": W.SEED,
+           "trace_work_node_updates": sum(s["work"] for _, s in trace)}
+    means = {}
+    for mode in ("batched", "plain"):
+        log(f"bench: serving trace, {mode} mode")
+        with U.Server(memory_budget_gb=32, max_jobs=64, steps_per_tick=64, mode=mode) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for arrival, spec in trace:
+                dt = arrival - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(srv.submit(spec))
+            results = [srv.wait(t, 900) for t in tickets]
+            st = srv.stats()
+        bad = [r for r in results if r["status"] != 0]
+        lat = sorted(r["latency_s"] for r in results)
+        means[mode] = [(r["mean"], r["var"]) for r in results]
+        out[mode] = {"solves_per_hour": round(st["solves_per_hour"], 1), "p50_s": round(st["latency_p50_s"], 4),
+                     "p99_s": round(st["latency_p99_s"], 4), "mean_latency_s": round(st["latency_mean_s"], 4),
+                     "mlups": round(st["mlups"], 1), "makespan_s": round(st["elapsed_s"], 3),
+                     "failed": len(bad), "arena_peak_gb": round(st["arena_peak_bytes"] / 2 ** 30, 3),
+                     "max_latency_s": round(lat[-1], 4)}
+        log(f"bench: {mode}: {out[mode]}")
+    diff = 0.0
+    for (mb, vb), (mp, vp) in zip(means["batched"], means["plain"]):
+        diff = max(diff, abs(mb - mp) / max(abs(mp), 1e-300), abs(vb - vp) / max(abs(vp), 1e-300))
+    out["max_rel_diff_batched_vs_plain"] = diff
+    out["speedup_solves_per_hour"] = round(out["batched"]["solves_per_hour"] / out["plain"]["solves_per_hour"], 2)
+    return out
+
+
 def cpu_baseline(spec, n_samples=4, lbm_steps=300):
     """The FP64 oracle, single-threaded, on the full lattice of the workload
     for a few samples and steps (about 10 s of CPU work)."""
@@ -98,6 +137,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
+    ap.add_argument("--serving-jobs", type=int, default=24)
+    ap.add_argument("--serving-load", type=float, default=1.2)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip tuning (shapes then come from UQ_TUNE_CACHE or the defaults)")
     args = ap.parse_args()
@@ -203,6 +245,11 @@ def main():
         "uq_solves_per_hour": round(3600.0 / (wall / args.steps), 1),
         "hbm_frac_of_peak": roof["frac"],
     }
+    if not args.no_serving:
+        out["serving"] = serving(U, W, args.serving_jobs, args.serving_load, log)
+        out["uq_solves_per_hour_serving"] = out["serving"]["batched"]["solves_per_hour"]
+        out["p50_s"] = out["serving"]["batched"]["p50_s"]
+        out["p99_s"] = out["serving"]["batched"]["p99_s"]
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(spec)

@@ -267,6 +267,69 @@ typedef struct {
 } uq_tune_result;
 uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop on its own host thread. Jobs are admitted first
+ * come, first served while their device footprint fits in the server's
+ * memory arena (allocated once at creation; serving itself never calls
+ * hipMalloc/hipFree) and fewer than max_jobs are live. In BATCHED mode every
+ * sample of every live job advances in one fused launch per step (jobs of
+ * different lattices, geometries, sample counts and step parities share the
+ * launch; AA layout), in hipGraph replays of steps_per_tick steps while the
+ * job set is unchanged. PLAIN mode runs one job at a time and one sample per
+ * launch per step, with no graph: the same kernels and arithmetic, for
+ * comparison. All jobs of a server share its precision. Results are one
+ * scalar QoI per job (KE, CD or CL): its statistics as in uq_moments. */
+typedef enum { UQ_SERVE_BATCHED = 0, UQ_SERVE_PLAIN = 1 } uq_serve_mode;
+
+typedef struct {
+    int64_t memory_budget;  /* bytes of device memory for resident jobs        */
+    int32_t max_jobs;       /* live jobs at once (1..4096)                     */
+    int32_t steps_per_tick; /* steps between admission checks (even, >= 2)     */
+    int32_t mode;           /* uq_serve_mode                                   */
+    int32_t use_graph;      /* capture each tick of the batched mode           */
+    int32_t precision;      /* uq_precision of every job                       */
+} uq_server_config;
+
+#define UQ_RESULT_MAX_COEFFS 256
+typedef struct {
+    uint64_t ticket;
+    int32_t status; /* UQ_OK, UQ_EUNSTABLE, ...                              */
+    int32_t qoi;
+    int64_t S;
+    int32_t K;      /* gPC terms (0 for MC); coeffs holds the first 256       */
+    int32_t pad0;
+    double mean, var, var_alt;
+    double coeffs[UQ_RESULT_MAX_COEFFS];
+    double t_submit, t_admit, t_done; /* seconds since server creation       */
+    double node_updates;              /* S * nx * ny * steps                 */
+} uq_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, pending, live;
+    double elapsed_s;       /* since creation                                  */
+    double busy_s;          /* host time spent in step ticks                   */
+    double node_updates;    /* of completed jobs                               */
+    double solves_per_hour; /* completed / elapsed                             */
+    double mlups;           /* node_updates / elapsed / 1e6                    */
+    double latency_p50_s, latency_p99_s, latency_mean_s; /* done - submit      */
+    int64_t arena_bytes, arena_peak_bytes;
+} uq_server_stats;
+
+typedef struct uq_server uq_server;
+
+/* Start a server on `device` (its arena is allocated here). */
+uq_status uq_server_create(const uq_server_config *cfg, int32_t device, uq_server **out);
+/* Queue a job; never blocks. UQ_ENOMEM if it can never fit the arena. The
+ * problem is copied. *ticket identifies the result. */
+uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t steps, int32_t qoi, uint64_t *ticket);
+/* Result of a finished job (copied out and forgotten), else UQ_EAGAIN. */
+uq_status uq_server_poll(uq_server *s, uint64_t ticket, uq_result *out);
+/* Wait up to timeout_s (< 0: forever) for a result; UQ_EAGAIN on timeout. */
+uq_status uq_server_wait(uq_server *s, uint64_t ticket, double timeout_s, uq_result *out);
+uq_status uq_server_get_stats(uq_server *s, uq_server_stats *out);
+/* Stop the loop, abandon queued and live jobs, release all device memory. */
+void uq_server_destroy(uq_server *s);
+
 /* Host-only helpers (no device needed): the job's sample set and basis,
  * for callers that want the rule without creating a job.
  *   uq_rule_size: S and K of a problem.

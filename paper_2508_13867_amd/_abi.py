@@ -75,6 +75,30 @@ class TuneResult(C.Structure):
                 ("gbs", C.c_double), ("ms_per_step", C.c_double), ("n_candidates", C.c_int32)]
 
 
+RESULT_MAX_COEFFS = 256
+SERVE = {"batched": 0, "plain": 1}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("memory_budget", C.c_int64), ("max_jobs", C.c_int32), ("steps_per_tick", C.c_int32),
+                ("mode", C.c_int32), ("use_graph", C.c_int32), ("precision", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("qoi", C.c_int32), ("S", C.c_int64),
+                ("K", C.c_int32), ("pad0", C.c_int32), ("mean", C.c_double), ("var", C.c_double),
+                ("var_alt", C.c_double), ("coeffs", C.c_double * RESULT_MAX_COEFFS), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("node_updates", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("pending", C.c_int64),
+                ("live", C.c_int64), ("elapsed_s", C.c_double), ("busy_s", C.c_double),
+                ("node_updates", C.c_double), ("solves_per_hour", C.c_double), ("mlups", C.c_double),
+                ("latency_p50_s", C.c_double), ("latency_p99_s", C.c_double), ("latency_mean_s", C.c_double),
+                ("arena_bytes", C.c_int64), ("arena_peak_bytes", C.c_int64)]
+
+
 # every symbol the header declares, with its signature
 _P = C.c_void_p
 SIGNATURES = {
@@ -90,6 +114,12 @@ SIGNATURES = {
     "uq_destroy": (None, [_P]),
     "uq_last_error": (C.c_char_p, []),
     "uq_autotune": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.c_int64, C.POINTER(TuneResult)]),
+    "uq_server_create": (C.c_int, [C.POINTER(ServerConfig), C.c_int32, C.POINTER(_P)]),
+    "uq_server_submit": (C.c_int, [_P, C.POINTER(Problem), C.c_int64, C.c_int32, C.POINTER(C.c_uint64)]),
+    "uq_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
+    "uq_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
+    "uq_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "uq_server_destroy": (None, [_P]),
     "uq_rule_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "uq_rule_points": (C.c_int, [C.POINTER(Problem), _P, _P, _P, _P]),
 }
@@ -293,6 +323,75 @@ class Job:
     def close(self):
         if getattr(self, "h", None):
             lib().uq_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _result_dict(r: Result) -> dict:
+    K = r.K
+    return {"ticket": r.ticket, "status": r.status, "qoi": r.qoi, "S": r.S, "K": K, "mean": r.mean,
+            "var": r.var, "var_alt": r.var_alt, "coeffs": np.array(r.coeffs[:min(K, RESULT_MAX_COEFFS)]),
+            "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done, "node_updates": r.node_updates,
+            "latency_s": r.t_done - r.t_submit}
+
+
+class Server:
+    """A continuous-batching UQ server (uq_server_*) on one GPU."""
+
+    def __init__(self, memory_budget_gb: float = 16.0, max_jobs: int = 64, steps_per_tick: int = 64,
+                 mode: str = "batched", use_graph: bool = True, precision: str = "fp32", device: int = 0):
+        cfg = ServerConfig()
+        cfg.memory_budget = int(memory_budget_gb * (1 << 30))
+        cfg.max_jobs = max_jobs
+        cfg.steps_per_tick = steps_per_tick
+        cfg.mode = SERVE[mode]
+        cfg.use_graph = 1 if use_graph else 0
+        cfg.precision = PRECISION[precision]
+        h = C.c_void_p()
+        check(lib().uq_server_create(C.byref(cfg), device, C.byref(h)))
+        self.h = h
+
+    def submit(self, spec: dict, steps: int | None = None, qoi: str | None = None) -> int:
+        p = make_problem(spec)
+        if qoi is None:
+            qoi = "ke" if spec["geometry"] == "tgv" else "cd"
+        t = C.c_uint64()
+        check(lib().uq_server_submit(self.h, C.byref(p), int(spec["steps"] if steps is None else steps), QOI[qoi],
+                                     C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        r = Result()
+        st = lib().uq_server_poll(self.h, ticket, C.byref(r))
+        if st == UQ_EAGAIN:
+            return None
+        check(st)
+        return _result_dict(r)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> dict:
+        r = Result()
+        check(lib().uq_server_wait(self.h, ticket, float(timeout_s), C.byref(r)))
+        return _result_dict(r)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().uq_server_get_stats(self.h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().uq_server_destroy(self.h)
             self.h = None
 
     def __enter__(self):

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libuqlbm.so")
-SOURCES = ["sampler.cpp", "uq_api.cpp", "engine.cpp", "tuner.cpp", "lbm_kernels.hip"]
+SOURCES = ["sampler.cpp", "uq_api.cpp", "engine.cpp", "tuner.cpp", "server.cpp", "lbm_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -274,58 +274,101 @@ __device__ inline int64_t xcd_logical(int64_t b, int64_t G) {
 constexpr int BX = 64;  // nodes along x per tile (one wavefront)
 constexpr int BY = 4;   // wavefronts per workgroup
 
-// One step for every live node of every sample. A workgroup is 64 x 4
-// threads; a tile is 64 nodes along x by 4*CPT rows, and each thread takes
+// One tile of one sample: 64 nodes along x by 4*CPT rows; each thread takes
 // CPT rows 4 apart. All CPT nodes of a thread are gathered before any is
 // written back: in the AA pattern a node reads and writes only its own nine
 // locations (and in AB reads and writes different slabs), so the nodes are
 // independent and the loads of all CPT rows can be in flight together.
 template <int P, bool CHANNEL, int PARITY, int CPT, int LAYOUT, bool NT>
-__global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int k, int tiles_x, int tiles_y,
-                                              int64_t ntiles) {
+__device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int tx, int ty) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int MODE = ModeOf<LAYOUT, PARITY>::value;
-    const int64_t t = *d_t + k;
-    const int64_t G = gridDim.x;
-    const int64_t lb = xcd_logical(blockIdx.x, G);
-    const int64_t per_sample = (int64_t)tiles_x * tiles_y;
+    const int x = tx * BX + threadIdx.x;
+    if (x >= j.nx) return;
     T *src_all = (T *)(LAYOUT == UQ_LAYOUT_AB && PARITY ? j.f2 : j.f);
     T *dst_all = (T *)(LAYOUT == UQ_LAYOUT_AB && !PARITY ? j.f2 : j.f);
-    for (int64_t tile = lb; tile < ntiles; tile += G) {
+    const C omega = (C)j.smp[smp].omega;
+    const double u_peak = CHANNEL ? j.smp[smp].u_peak : 0.0;
+    const T *src = src_all + smp * 9 * j.plane;
+    T *dst = dst_all + smp * 9 * j.plane;
+    const int y0 = ty * BY * CPT + threadIdx.y;
+    C f[CPT][9];
+    uint32_t m[CPT];
+    bool live[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        const int y = y0 + r * BY;
+        live[r] = y < j.ny;
+        m[r] = 0;
+        if (CHANNEL && live[r]) {
+            m[r] = j.mask[(int64_t)y * j.pitch + x];
+            live[r] = !(m[r] & M_SOLID);
+        }
+        if (live[r]) gather<P, CHANNEL, MODE>(j, src, site(j, x, y), m[r], t, u_peak, f[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        if (!live[r]) continue;
+        C drho, ux, uy;
+        bgk(f[r], omega, drho, ux, uy);
+        scatter<P, CHANNEL, MODE, NT>(j, dst, site(j, x, y0 + r * BY), m[r], f[r]);
+    }
+}
+
+// One step for every live node of every sample of one job.
+template <int P, bool CHANNEL, int PARITY, int CPT, int LAYOUT, bool NT>
+__global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int k, int tiles_x, int tiles_y,
+                                              int64_t ntiles) {
+    const int64_t t = *d_t + k;
+    const int64_t G = gridDim.x;
+    const int64_t per_sample = (int64_t)tiles_x * tiles_y;
+    for (int64_t tile = xcd_logical(blockIdx.x, G); tile < ntiles; tile += G) {
         const int64_t smp = tile / per_sample;
         const int64_t rem = tile - smp * per_sample;
         const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
-        const int x = tx * BX + threadIdx.x;
-        if (x >= j.nx) continue;
-        const C omega = (C)j.smp[smp].omega;
-        const double u_peak = CHANNEL ? j.smp[smp].u_peak : 0.0;
-        const T *src = src_all + smp * 9 * j.plane;
-        T *dst = dst_all + smp * 9 * j.plane;
-        const int y0 = ty * BY * CPT + threadIdx.y;
-        C f[CPT][9];
-        uint32_t m[CPT];
-        bool live[CPT];
-#pragma unroll
-        for (int r = 0; r < CPT; ++r) {
-            const int y = y0 + r * BY;
-            live[r] = y < j.ny;
-            m[r] = 0;
-            if (CHANNEL && live[r]) {
-                m[r] = j.mask[(int64_t)y * j.pitch + x];
-                live[r] = !(m[r] & M_SOLID);
-            }
-            if (live[r]) gather<P, CHANNEL, MODE>(j, src, site(j, x, y), m[r], t, u_peak, f[r]);
+        tile_update<P, CHANNEL, PARITY, CPT, LAYOUT, NT>(j, t, smp, tx, ty);
+    }
+}
+
+// One step for every live node of every sample of every job in a table
+// (continuous batching). Jobs may differ in geometry, lattice, sample count
+// and step parity; all use the AA layout, one row per thread. Tiles of job q
+// are the global tiles [tile0_q, tile0_{q+1}); a job whose step count has
+// reached its target is skipped, so the same launch (or captured graph) stays
+// valid while jobs finish.
+template <int P>
+__global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k) {
+    const int64_t G = gridDim.x;
+    for (int64_t tile = xcd_logical(blockIdx.x, G); tile < ntiles; tile += G) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile0 <= tile) lo = mid;
+            else hi = mid - 1;
         }
-#pragma unroll
-        for (int r = 0; r < CPT; ++r) {
-            if (!live[r]) continue;
-            C drho, ux, uy;
-            bgk(f[r], omega, drho, ux, uy);
-            scatter<P, CHANNEL, MODE, NT>(j, dst, site(j, x, y0 + r * BY), m[r], f[r]);
+        const MultiJob &q = jobs[lo];
+        const int64_t t = q.t + k;
+        if (t >= q.n_steps) continue;
+        const int64_t per_sample = (int64_t)q.tiles_x * q.tiles_y;
+        const int64_t local = tile - q.tile0;
+        const int64_t smp = local / per_sample;
+        const int64_t rem = local - smp * per_sample;
+        const int ty = (int)(rem / q.tiles_x), tx = (int)(rem - (int64_t)ty * q.tiles_x);
+        if (q.j.geom == 1) {
+            if (t & 1) tile_update<P, true, 1, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
+            else tile_update<P, true, 0, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
+        } else {
+            if (t & 1) tile_update<P, false, 1, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
+            else tile_update<P, false, 0, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
         }
     }
+}
+
+__global__ void k_advance_multi(MultiJob *jobs, int njobs, int64_t n) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < njobs) jobs[q].t += n;
 }
 
 // ------------------------------------------------------------------ init
@@ -702,6 +745,30 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
     if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
     else step_cpt<2>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
     return hipGetLastError();
+}
+
+hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s) {
+    if (ntiles <= 0 || njobs <= 0) return hipSuccess;
+    const int64_t G = std::min<int64_t>(ntiles, 0x7fffffff);
+    dim3 block(BX, BY);
+    switch (prec) {
+        case UQ_FP64: k_step_multi<UQ_FP64><<<(unsigned)G, block, 0, s>>>(jobs, njobs, ntiles, k); break;
+        case UQ_FP32: k_step_multi<UQ_FP32><<<(unsigned)G, block, 0, s>>>(jobs, njobs, ntiles, k); break;
+        case UQ_FP16S: k_step_multi<UQ_FP16S><<<(unsigned)G, block, 0, s>>>(jobs, njobs, ntiles, k); break;
+        default: k_step_multi<UQ_BF16S><<<(unsigned)G, block, 0, s>>>(jobs, njobs, ntiles, k); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_advance_multi<<<(unsigned)((njobs + 63) / 64), 64, 0, s>>>(jobs, njobs, n);
+    return hipGetLastError();
+}
+
+void tile_counts(const JobDev &j, int cpt, int *tiles_x, int *tiles_y) {
+    *tiles_x = (j.nx + BX - 1) / BX;
+    *tiles_y = (j.ny + BY * cpt - 1) / (BY * cpt);
 }
 
 hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s) {

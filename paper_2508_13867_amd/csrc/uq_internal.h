@@ -87,6 +87,15 @@ struct JobDev {
     int32_t layout;         // UQ_LAYOUT_AA or UQ_LAYOUT_AB
 };
 
+// A job in the continuous-batching table (device memory).
+struct alignas(16) MultiJob {
+    JobDev j;
+    int64_t t;        // steps done at the current base
+    int64_t n_steps;  // the job's target; tiles of finished jobs are skipped
+    int64_t tile0;    // first global tile of the job
+    int32_t tiles_x, tiles_y;
+};
+
 // ------------------------------------------------------------------ kernel launchers
 struct StepShape {
     int cpt = 1;        // rows per thread (1 or 2)
@@ -101,6 +110,11 @@ struct StepShape {
 hipError_t launch_init(const JobDev &j, hipStream_t s);
 hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
                        hipStream_t s);
+// one step of every job in a table (AA layout, one row per thread); all jobs
+// must share precision `prec`
+hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s);
+hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_t s);
+void tile_counts(const JobDev &j, int cpt, int *tiles_x, int *tiles_y);
 // *d_t += n (one thread; keeps the device copy of the step count current)
 hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s);
 // per-sample scalar QoIs at time t: out[S][4] = {KE, Fx, Fy, nonfinite}

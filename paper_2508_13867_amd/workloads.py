@@ -48,3 +48,58 @@ def scaled(spec, **over):
     out = dict(spec)
     out.update(over)
     return out
+
+
+def serving_trace(n_jobs=16, seed=SEED, load=1.2, rate_nodes_per_s=5.0e10, max_S_steps=7.0e5,
+                  steps_range=(400, 3000)):
+    """Seeded Poisson-arrival stream of UQ jobs (the serving mix): Taylor-Green
+    vortices of 64^2..256^2 or cylinder channels of diameter 10..20 (22D x
+    4.1D lattice), 1- to 4-D uniform inputs, tensor Gauss-Legendre rules of
+    5..256 nodes or Monte Carlo with 256..1024 samples, FP32, steps
+    log-uniform in steps_range with samples x steps capped at max_S_steps.
+    Inter-arrival times are exponential with mean (mean job work) /
+    (load x rate_nodes_per_s). Returns [(arrival_s, spec), ...]."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for q in range(n_jobs):
+        steps = int(round(np.exp(rng.uniform(np.log(steps_range[0]), np.log(steps_range[1])))))
+        if rng.random() < 0.6:
+            n = int(rng.choice([64, 96, 128, 192, 256]))
+            d = int(rng.integers(1, 5))
+            dists = FOUR_D_INPUTS[:d] if d > 1 else [("nu", 0.004, 0.006)]
+            if rng.random() < 0.5:
+                per = {1: (5, 16), 2: (3, 16), 3: (2, 6), 4: (2, 4)}[d]
+                npd = int(rng.integers(per[0], per[1] + 1))
+                rule = dict(kind="gl", n=npd, order=min(npd - 1, 3))
+                S = npd ** d
+            else:
+                S = int(rng.choice([256, 512, 1024]))
+                rule = dict(kind="mc", N=S, seed=SEED + q)
+            spec = dict(name=f"trace{q}_tgv{n}", geometry="tgv", precision="fp32", nx=n, ny=n, u0=0.02,
+                        nu=0.005, dists=dists, rule=rule)
+        else:
+            D = int(rng.choice([10, 14, 20]))
+            nx, ny = 22 * D, int(round(4.1 * D))
+            d = int(rng.integers(1, 3))
+            dists = [("re", 16.0, 24.0), ("u_peak", 0.045, 0.055)][:d]
+            if rng.random() < 0.6:
+                npd = int(rng.integers(3, 9)) if d == 2 else int(rng.integers(5, 17))
+                rule = dict(kind="gl", n=npd, order=min(npd - 1, 5))
+                S = npd ** d
+            else:
+                S = int(rng.choice([256, 512]))
+                rule = dict(kind="mc", N=S, seed=SEED + q)
+            spec = dict(name=f"trace{q}_cyl{D}", geometry="channel", precision="fp32", nx=nx, ny=ny, u_peak=0.05,
+                        nu=0.05 * D / 20.0, D=D, cx=2 * D, cy=ny // 2, xbc="zouhe", dists=dists, rule=rule)
+        steps = max(2, min(steps, int(max_S_steps / S)))
+        spec["steps"] = steps
+        if spec["geometry"] == "channel":
+            spec["ramp"] = steps // 5
+        spec["work"] = float(S) * spec["nx"] * spec["ny"] * steps
+        jobs.append(spec)
+    mean_service = sum(j["work"] for j in jobs) / len(jobs) / rate_nodes_per_s
+    gaps = rng.exponential(mean_service / load, size=n_jobs)
+    t = np.cumsum(gaps) - gaps[0]
+    return [(float(a), j) for a, j in zip(t, jobs)]

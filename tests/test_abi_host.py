@@ -35,7 +35,8 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
 
     structs = {"uq_dist": A.Dist, "uq_problem": A.Problem, "uq_device": A.Device,
-               "uq_moments_out": A.MomentsOut, "uq_job_info": A.JobInfo, "uq_tune_result": A.TuneResult}
+               "uq_moments_out": A.MomentsOut, "uq_job_info": A.JobInfo, "uq_tune_result": A.TuneResult,
+               "uq_server_config": A.ServerConfig, "uq_result": A.Result, "uq_server_stats": A.ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "uq.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
