@@ -109,6 +109,98 @@ def serving(U, W, n_jobs, load, log):
     return out
 
 
+def study_precision(U, W, log, oracle_samples=8):
+    """Monte Carlo workload (128^2 vortex, 4-D inputs, 4096 samples, 2000
+    steps) in FP64, FP32, FP16- and BF16-storage: throughput and roofline per
+    precision, the error of E[K] and Var[K] against the FP64 run (itself
+    re-checked sample by sample against the FP64 oracle), and the Monte Carlo
+    rate: RMS error of the mean over disjoint groups of N samples against a
+    6^4-node Gauss-Legendre collocation reference."""
+    import numpy as np
+
+    import oracle as O
+
+    base = dict(W.TGV_MC)
+    out = {"workload": base["name"], "runs": {}}
+    ke = {}
+    for prec in ("fp64", "fp32", "fp16s", "bf16s"):
+        spec = dict(base, precision=prec)
+        tune = U.autotune(spec, steps=20)
+        with U.Job(spec) as job:
+            inf = job.info()
+            ms = job.run_timed(spec["steps"])
+            st = job.moments("ke")
+            ke[prec] = job.qoi_samples("ke")[:, 0]
+        nodes = job.S * spec["nx"] * spec["ny"]
+        bpn = 18 * BYTES_PER_POP[prec]
+        launch_ms = ms / spec["steps"]
+        out["runs"][prec] = {"mean": st["mean"][0], "var": st["var"][0],
+                             "mlups": round(nodes * spec["steps"] / (ms * 1e-3) / 1e6, 1),
+                             "gbs": round(nodes * bpn / (launch_ms * 1e-3) / 1e9, 1),
+                             "frac_hbm": round(nodes * bpn / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "bytes_per_node_update": bpn, "layout": {1: "aa", 2: "ab"}[inf.layout],
+                             "scale_exp": inf.scale_exp, "tuned_gbs": round(tune["gbs"], 1)}
+        log(f"bench: precision {prec}: {out['runs'][prec]}")
+    r64 = out["runs"]["fp64"]
+    for prec, r in out["runs"].items():
+        r["err_mean_vs_fp64"] = abs(r["mean"] - r64["mean"]) / abs(r64["mean"])
+        r["err_var_vs_fp64"] = abs(r["var"] - r64["var"]) / abs(r64["var"])
+        r["err_samples_rel_l2_vs_fp64"] = float(np.linalg.norm(ke[prec] - ke["fp64"]) / np.linalg.norm(ke["fp64"]))
+    # the FP64 run against the oracle, sample by sample
+    pick = list(range(0, 4096, 4096 // oracle_samples))[:oracle_samples]
+    log(f"bench: oracle re-solves samples {pick}")
+    ref = O.run_problem(base, samples=pick, qois=["ke"])
+    err = float(np.linalg.norm(ke["fp64"][pick] - ref["samples"]["ke"]) / np.linalg.norm(ref["samples"]["ke"]))
+    out["fp64_vs_oracle_rel_l2_sampled"] = err
+    out["oracle_samples"] = pick
+    # Monte Carlo rate against a collocation reference
+    gl = dict(base, precision="fp64", rule=dict(kind="gl", n=6, order=5), name="tgv128_gl6x4")
+    with U.Job(gl) as job:
+        job.run(gl["steps"])
+        ref_mean = job.moments("ke")["mean"][0]
+    rates = []
+    for N in (16, 64, 256, 1024):
+        groups = ke["fp64"][: 4096 // N * N].reshape(-1, N).mean(axis=1)
+        rates.append((N, float(np.sqrt(np.mean((groups - ref_mean) ** 2)))))
+    slope = float(np.polyfit(np.log([n for n, _ in rates]), np.log([e for _, e in rates]), 1)[0])
+    out["mc_reference_gl6x4_mean"] = ref_mean
+    out["mc_rms_error_by_N"] = rates
+    out["mc_rate_slope"] = slope
+    return out
+
+
+def study_cylinder(U, W, log, oracle_samples=1):
+    """The cylinder workload at full size (440 x 82, 8 x 8 collocation,
+    20000 steps, FP32): C_D and C_L statistics and gPC coefficients, with one
+    sample re-solved by the FP64 oracle over the full 20000 steps."""
+    import numpy as np
+
+    import oracle as O
+
+    spec = dict(W.CYLINDER_FP32)
+    tune = U.autotune(spec, steps=40)
+    with U.Job(spec) as job:
+        ms = job.run_timed(spec["steps"])
+        cd, cl = job.moments("cd"), job.moments("cl")
+        cd_s = job.qoi_samples("cd")[:, 0]
+        cl_s = job.qoi_samples("cl")[:, 0]
+        nodes = job.S * spec["nx"] * spec["ny"]
+    out = {"workload": spec["name"], "tuned": tune, "ms": ms,
+           "mlups": round(nodes * spec["steps"] / (ms * 1e-3) / 1e6, 1),
+           "cd": {"mean": cd["mean"][0], "std": float(np.sqrt(cd["var"][0])), "var_quad": cd["var_alt"][0],
+                  "coeffs_first6": cd["coeffs"][:6, 0].tolist()},
+           "cl": {"mean": cl["mean"][0], "std": float(np.sqrt(cl["var"][0]))}}
+    pick = [27][:oracle_samples]
+    log(f"bench: oracle re-solves cylinder sample {pick} over {spec['steps']} steps")
+    ref = O.run_problem(spec, samples=pick, qois=["cd", "cl"])
+    out["oracle_samples"] = pick
+    out["cd_sample_rel_err_vs_oracle"] = float(abs(cd_s[pick] - ref["samples"]["cd"]).max() /
+                                               abs(ref["samples"]["cd"]).max())
+    out["cl_sample_abs_err_vs_oracle"] = float(abs(cl_s[pick] - ref["samples"]["cl"]).max())
+    out["cd_sample_oracle"] = ref["samples"]["cd"].tolist()
+    return out
+
+
 def cpu_baseline(spec, n_samples=4, lbm_steps=300):
     """The FP64 oracle, single-threaded, on the full lattice of the workload
     for a few samples and steps (about 10 s of CPU work)."""
@@ -138,6 +230,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
+    ap.add_argument("--study", choices=["precision", "cylinder"], default=None,
+                    help="run a measurement study instead of the benchmark and print its JSON")
     ap.add_argument("--serving-jobs", type=int, default=24)
     ap.add_argument("--serving-load", type=float, default=1.2)
     ap.add_argument("--no-tune", action="store_true",
@@ -167,6 +261,12 @@ def main():
     log(f"bench: device copy {copy_gbs:.0f} GB/s")
     if args.copy_probe:
         print(json.dumps({"copy_gbs": round(copy_gbs, 1)}), flush=True)
+        return
+    if args.study == "precision":
+        print(json.dumps(study_precision(U, W, log)), flush=True)
+        return
+    if args.study == "cylinder":
+        print(json.dumps(study_cylinder(U, W, log)), flush=True)
         return
 
     tune = None

@@ -276,3 +276,24 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
         job.run(20)
         ref = O.run_problem(spec, qois=["ke"])
         assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
+
+
+def test_mc4096_full_size_precisions_vs_fp64_and_oracle():
+    # the 128^2 x 4096-sample Monte Carlo workload at full size and length:
+    # FP64 re-checked on sampled samples by the oracle, FP32 and FP16-storage
+    # statistics against FP64 at their bars
+    base = W.TGV_MC
+    say("case", base["name"], "full")
+    ke, st = {}, {}
+    for prec in ("fp64", "fp32", "fp16s"):
+        with Job(W.scaled(base, precision=prec)) as job:
+            job.run(base["steps"])
+            ke[prec] = job.qoi_samples("ke")[:, 0]
+            st[prec] = job.moments("ke")
+    pick = [5, 2222]
+    ref = O.run_problem(base, samples=pick, qois=["ke"])
+    assert rel_l2(ke["fp64"][pick], ref["samples"]["ke"]) < TOL["fp64"]
+    for prec in ("fp32", "fp16s"):
+        for k in ("mean", "var"):
+            assert rel_l2(st[prec][k], st["fp64"][k]) < TOL[prec], (prec, k, rel_l2(st[prec][k], st["fp64"][k]))
+        assert rel_l2(ke[prec], ke["fp64"]) < TOL[prec]
