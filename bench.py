@@ -159,7 +159,7 @@ def study_precision(U, W, log, oracle_samples=8):
         job.run(gl["steps"])
         ref_mean = job.moments("ke")["mean"][0]
     rates = []
-    for N in (16, 64, 256, 1024):
+    for N in (16, 32, 64, 128, 256):  # at least 16 disjoint groups each
         groups = ke["fp64"][: 4096 // N * N].reshape(-1, N).mean(axis=1)
         rates.append((N, float(np.sqrt(np.mean((groups - ref_mean) ** 2)))))
     slope = float(np.polyfit(np.log([n for n, _ in rates]), np.log([e for _, e in rates]), 1)[0])
@@ -280,7 +280,7 @@ def main():
         job = U.Job(spec, device=0)
         inf = job.info()
         launch.update(layout={1: "aa", 2: "ab"}[inf.layout], cpt=inf.cpt, nt_store=inf.nt_store,
-                      plane_pad=inf.plane_pad, device_bytes=inf.device_bytes)
+                      plane_pad=inf.plane_pad, bx=inf.bx, device_bytes=inf.device_bytes)
         ms = job.run_timed(spec["steps"]) if timed_kernel else None
         if not timed_kernel:
             job.run(spec["steps"])

@@ -198,6 +198,7 @@ typedef struct {
     int32_t cpt;        /* rows per thread of the step kernel          */
     int32_t nt_store;   /* 1 if AB stores bypass the caches            */
     int32_t plane_pad;  /* padding elements after each population plane */
+    int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
 } uq_job_info;
 
 /* Set up a job: sample the inputs, map each sample to its solver parameters,
@@ -249,8 +250,9 @@ const char *uq_last_error(void);
 
 /* Launch-shape autotuning. Times the step kernel of the problem (its real
  * lattice and sample count) for every candidate shape -- layout AA or AB
- * (only the problem's layout unless it is UQ_LAYOUT_AUTO), 1 or 2 rows per
- * thread, plane padding 0 or 64 elements, cached or non-temporal AB stores --
+ * (only the problem's layout unless it is UQ_LAYOUT_AUTO), workgroups of
+ * 64 x 4, 128 x 2 or 256 x 1 threads, 1 or 2 rows per thread, plane padding
+ * 0 or 64 elements, cached or non-temporal AB stores --
  * over `steps` steps each (rounded down to even, >= 2), on dev's device with
  * temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
@@ -261,6 +263,7 @@ typedef struct {
     int32_t cpt;
     int32_t nt_store;
     int32_t plane_pad;
+    int32_t bx;         /* workgroup width along x: 64, 128 or 256          */
     double gbs;         /* algorithmic GB/s of the best candidate (18 b per node) */
     double ms_per_step; /* its average step duration                           */
     int32_t n_candidates;

@@ -30,6 +30,7 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
     s.persistent = env_int("UQ_PERSISTENT", 0);
     s.nt = env_int("UQ_NT_STORE", 1);
     s.pad = env_int("UQ_PLANE_PAD", 64);
+    s.bx = env_int("UQ_BX", 64);
     s.layout = UQ_LAYOUT_AA;
     if (p.layout == UQ_LAYOUT_AA || p.layout == UQ_LAYOUT_AB) {
         s.layout = p.layout;

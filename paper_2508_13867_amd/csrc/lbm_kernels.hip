@@ -304,11 +304,12 @@ __device__ inline int64_t xcd_logical(int64_t b, int64_t G) {
     return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-constexpr int BX = 64;  // nodes along x per tile (one wavefront)
-constexpr int BY = 4;   // wavefronts per workgroup
+constexpr int BX = 64;  // default workgroup shape: 64 nodes along x (one
+constexpr int BY = 4;   // wavefront) by 4 rows; the step kernel takes any
+                        // 256-thread shape bx x (256/bx) from its launch
 
-// One tile of one sample: 64 nodes along x by 4*CPT rows; each thread takes
-// CPT rows 4 apart. All CPT nodes of a thread are gathered before any is
+// One tile of one sample: blockDim.x nodes along x by blockDim.y*CPT rows;
+// each thread takes CPT rows blockDim.y apart. All CPT nodes of a thread are gathered before any is
 // written back: in the AA pattern a node reads and writes only its own nine
 // locations (and in AB reads and writes different slabs), so the nodes are
 // independent and the loads of all CPT rows can be in flight together.
@@ -318,7 +319,7 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int MODE = ModeOf<LAYOUT, PARITY>::value;
-    const int x = tx * BX + threadIdx.x;
+    const int x = tx * (int)blockDim.x + threadIdx.x;
     if (x >= j.nx) return;
     T *src_all = (T *)(LAYOUT == UQ_LAYOUT_AB && PARITY ? j.f2 : j.f);
     T *dst_all = (T *)(LAYOUT == UQ_LAYOUT_AB && !PARITY ? j.f2 : j.f);
@@ -326,13 +327,14 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
     const double u_peak = CHANNEL ? j.smp[smp].u_peak : 0.0;
     const T *src = src_all + smp * 9 * j.plane;
     T *dst = dst_all + smp * 9 * j.plane;
-    const int y0 = ty * BY * CPT + threadIdx.y;
+    const int by = (int)blockDim.y;
+    const int y0 = ty * by * CPT + threadIdx.y;
     C f[CPT][9];
     uint32_t m[CPT];
     bool live[CPT];
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
-        const int y = y0 + r * BY;
+        const int y = y0 + r * by;
         live[r] = y < j.ny;
         m[r] = 0;
         if (CHANNEL && live[r]) {
@@ -346,7 +348,7 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
         if (!live[r]) continue;
         C drho, ux, uy;
         bgk(f[r], omega, drho, ux, uy);
-        scatter<P, CHANNEL, MODE, NT>(j, dst, site(j, x, y0 + r * BY), m[r], f[r]);
+        scatter<P, CHANNEL, MODE, NT>(j, dst, site(j, x, y0 + r * by), m[r], f[r]);
     }
 }
 
@@ -766,13 +768,15 @@ static void step_cpt(const JobDev &j, const int64_t *d_t, int k, int parity, boo
 hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
                        hipStream_t s) {
     const int cpt = shape.cpt <= 1 ? 1 : 2;
-    const int tiles_x = (j.nx + BX - 1) / BX;
-    const int tiles_y = (j.ny + BY * cpt - 1) / (BY * cpt);
+    const int bx = shape.bx == 128 || shape.bx == 256 ? shape.bx : BX;
+    const int by = 256 / bx;
+    const int tiles_x = (j.nx + bx - 1) / bx;
+    const int tiles_y = (j.ny + by * cpt - 1) / (by * cpt);
     const int64_t ntiles = (int64_t)j.S * tiles_x * tiles_y;
     int64_t G = ntiles;
     if (shape.persistent > 0) G = std::min<int64_t>(ntiles, (int64_t)256 * shape.persistent);
     if (G > 0x7fffffff) G = 0x7fffffff;
-    dim3 block(BX, BY);
+    dim3 block(bx, by);
     dim3 grid((unsigned)G);
     const bool nt = shape.nt != 0;
     if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);

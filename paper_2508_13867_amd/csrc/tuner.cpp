@@ -45,16 +45,17 @@ void load_cache_locked() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad;
+    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad, bx;
     long long S;
     double gbs;
-    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req, &layout,
-                       &cpt, &nt, &pad, &gbs) == 11) {
+    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req, &layout,
+                       &cpt, &nt, &pad, &bx, &gbs) == 12) {
         Entry e;
         e.shape.layout = layout;
         e.shape.cpt = cpt;
         e.shape.nt = nt;
         e.shape.pad = pad;
+        e.shape.bx = bx;
         e.gbs = gbs;
         g_cache[Key(prec, geom, nx, ny, (int64_t)S, lay_req)] = e;
     }
@@ -67,9 +68,9 @@ void store_locked(const Key &k, const Entry &e) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
                  std::get<3>(k), (long long)std::get<4>(k), std::get<5>(k), e.shape.layout, e.shape.cpt, e.shape.nt,
-                 e.shape.pad, e.gbs);
+                 e.shape.pad, e.shape.bx, e.gbs);
     std::fclose(f);
 }
 
@@ -99,17 +100,20 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
     std::vector<StepShape> cands;
     for (int layout : {UQ_LAYOUT_AA, UQ_LAYOUT_AB}) {
         if (p->layout != UQ_LAYOUT_AUTO && p->layout != layout) continue;
-        for (int cpt : {1, 2})
-            for (int pad : {0, 64})
-                for (int nt : {0, 1}) {
-                    if (layout == UQ_LAYOUT_AA && nt) continue;  // AA stores are in place
-                    StepShape s;
-                    s.layout = layout;
-                    s.cpt = cpt;
-                    s.pad = pad;
-                    s.nt = nt;
-                    cands.push_back(s);
-                }
+        for (int bx : {64, 128, 256})
+            for (int cpt : {1, 2})
+                for (int pad : {0, 64})
+                    for (int nt : {0, 1}) {
+                        if (layout == UQ_LAYOUT_AA && nt) continue;  // AA stores are in place
+                        if (bx > 64 && bx / 2 >= p->nx) continue;      // mostly idle lanes
+                        StepShape s;
+                        s.layout = layout;
+                        s.cpt = cpt;
+                        s.pad = pad;
+                        s.nt = nt;
+                        s.bx = bx;
+                        cands.push_back(s);
+                    }
     }
 
     const double bytes_per_node = 18.0 * (double)storage_bytes(p->precision);
@@ -156,6 +160,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
     out->cpt = best.shape.cpt;
     out->nt_store = best.shape.nt;
     out->plane_pad = best.shape.pad;
+    out->bx = best.shape.bx;
     out->gbs = best.gbs;
     out->ms_per_step = best_ms;
     out->n_candidates = tried;

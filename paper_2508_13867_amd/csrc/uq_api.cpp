@@ -450,6 +450,7 @@ extern "C" uq_status uq_job_get_info(const uq_job *j, uq_job_info *info) {
     info->cpt = j->shape.cpt;
     info->nt_store = j->shape.nt;
     info->plane_pad = j->plane_pad;
+    info->bx = j->shape.bx;
     return UQ_OK;
 }
 

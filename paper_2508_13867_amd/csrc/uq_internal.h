@@ -103,6 +103,7 @@ struct StepShape {
     int nt = 1;         // AB layout: non-temporal (cache-bypassing) stores
     int layout = UQ_LAYOUT_AA;
     int pad = 64;       // elements of padding after each population plane
+    int bx = 64;        // workgroup width along x (64, 128 or 256; height 256/bx)
 };
 
 // one stream-collide step for all samples at time t = *d_t + k; `parity`

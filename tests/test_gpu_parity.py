@@ -232,6 +232,26 @@ def test_graph_replay_equals_eager(monkeypatch, layout):
     assert np.array_equal(fa, fb) and np.array_equal(ka, kb)
 
 
+@pytest.mark.parametrize("bx", [128, 256])
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_workgroup_shapes_match_oracle(bx, layout, monkeypatch):
+    # 128 x 2 and 256 x 1 workgroups (the tuner's other shapes), ragged edges
+    monkeypatch.setenv("UQ_BX", str(bx))
+    say("case workgroup", bx, layout)
+    for spec, steps in ((TGV_RAGGED, 7), (CHANNEL_SMALL, 201)):
+        with Job(W.scaled(spec, layout=layout)) as job:
+            assert job.info().bx == bx
+            job.run(steps)
+            xi, a = job.samples()
+            p = O.sample_params(spec, xi[-1])
+            if spec["geometry"] == "tgv":
+                ref = O.tgv_run(72, 40, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+            else:
+                ref = O.channel_run(100, 41, p["nu"], p["u_peak"], steps, D=10, cx=25, cy=18, ramp=200,
+                                    want_f=True)["f"]
+            assert np.abs(job.populations(job.S - 1) - ref).max() < 1e-13
+
+
 def test_layouts_agree_fp64():
     # AA and AB perform the same per-node arithmetic (up to the compiler's
     # fused multiply-adds): results agree to rounding
@@ -269,10 +289,12 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     spec = W.scaled(TGV_4D_SMALL, steps=20)
     say("case autotune")
     r = A.autotune(spec, steps=10)
-    assert r["n_candidates"] == 12 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes idle)
+    assert r["n_candidates"] == 24 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
-        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad) == (r["layout"], r["cpt"], r["plane_pad"])
+        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx) == \
+            (r["layout"], r["cpt"], r["plane_pad"], r["bx"])
         job.run(20)
         ref = O.run_problem(spec, qois=["ke"])
         assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
