@@ -169,6 +169,41 @@ def study_precision(U, W, log, oracle_samples=8):
     return out
 
 
+def study_samplers(U, W, log):
+    """Convergence of E[K] and Var[K] (128^2 vortex, 4-D inputs, 2000 steps,
+    FP32) for Monte Carlo, Halton quasi Monte Carlo, Latin hypercube, Smolyak
+    sparse grids and tensor Gauss-Legendre collocation, against a 6^4-node
+    tensor Gauss-Legendre reference (the analogue of the paper's MC / QMC /
+    SC-gPC comparisons)."""
+    base = dict(W.TGV_MC)
+    runs = []
+
+    def run(rule, label):
+        spec = dict(base, rule=rule, name=label)
+        with U.Job(spec) as job:
+            ms = job.run_timed(spec["steps"])
+            st = job.moments("ke")
+            S = job.S
+        r = {"label": label, "rule": rule, "samples": S, "mean": st["mean"][0], "var": st["var"][0],
+             "ms": round(ms, 2)}
+        log(f"bench: samplers {r}")
+        return r
+
+    ref = run(dict(kind="gl", n=6, order=5), "gl6")
+    for N in (64, 256, 1024, 4096):
+        runs.append(run(dict(kind="mc", N=N, seed=W.SEED), f"mc{N}"))
+        runs.append(run(dict(kind="halton", N=N), f"halton{N}"))
+        runs.append(run(dict(kind="lhs", N=N, seed=W.SEED), f"lhs{N}"))
+    for lvl in (1, 2, 3, 4):
+        runs.append(run(dict(kind="smolyak", level=lvl, order=min(lvl, 3)), f"smolyak{lvl}"))
+    for n in (2, 3, 4, 5):
+        runs.append(run(dict(kind="gl", n=n, order=n - 1), f"gl{n}"))
+    for r in runs:
+        r["err_mean"] = abs(r["mean"] - ref["mean"]) / abs(ref["mean"])
+        r["err_var"] = abs(r["var"] - ref["var"]) / abs(ref["var"])
+    return {"workload": "tgv128 4-D inputs, 2000 steps, FP32", "reference": ref, "runs": runs}
+
+
 def study_cylinder(U, W, log, oracle_samples=1):
     """The cylinder workload at full size (440 x 82, 8 x 8 collocation,
     20000 steps, FP32): C_D and C_L statistics and gPC coefficients, with one
@@ -230,7 +265,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
-    ap.add_argument("--study", choices=["precision", "cylinder"], default=None,
+    ap.add_argument("--study", choices=["precision", "cylinder", "samplers"], default=None,
                     help="run a measurement study instead of the benchmark and print its JSON")
     ap.add_argument("--serving-jobs", type=int, default=24)
     ap.add_argument("--serving-load", type=float, default=1.2)
@@ -267,6 +302,9 @@ def main():
         return
     if args.study == "cylinder":
         print(json.dumps(study_cylinder(U, W, log)), flush=True)
+        return
+    if args.study == "samplers":
+        print(json.dumps(study_samplers(U, W, log)), flush=True)
         return
 
     tune = None

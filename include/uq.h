@@ -104,7 +104,25 @@ typedef enum {
     /* Monte Carlo: mc_n i.i.d. draws from SplitMix64 seeded with `seed`; draw
      * number c = j*d + k + 1 feeds sample j, input k (Sec. "Monte Carlo and
      * quasi Monte Carlo sampling"). */
-    UQ_RULE_MC = 1
+    UQ_RULE_MC = 1,
+    /* Smolyak sparse grid of nested Clenshaw-Curtis rules (Sec. "Quadrature
+     * and collocation": Clenshaw-Curtis, sparse Smolyak grids), sparse level
+     * `level` >= 0 (1-D rules of 1, 3, 5, 9, 17, ... nodes); points are the
+     * union of the tensor grids, ordered lexicographically (input 0 most
+     * significant); weights of the probability measure, some negative; gPC
+     * of total degree <= order, exact for order <= level when the response is
+     * polynomial. In d = 4 the levels 0..4 have 1, 9, 41, 137, 401 points. */
+    UQ_RULE_SMOLYAK_CC = 2,
+    /* Quasi Monte Carlo: the first mc_n points of the Halton sequence (radical
+     * inverses in the first d primes) starting at index 1; equal weights,
+     * Monte Carlo statistics (Sec. "Monte Carlo and quasi Monte Carlo
+     * sampling"). */
+    UQ_RULE_HALTON = 3,
+    /* Latin hypercube sampling of mc_n points: per input a random permutation
+     * of the mc_n strata and a uniform position inside each, drawn from
+     * SplitMix64 seeded with `seed` (Sec. "Sampling strategies"); equal
+     * weights, Monte Carlo statistics. */
+    UQ_RULE_LHS = 4
 } uq_rule;
 
 #define UQ_MAX_DIMS 8
@@ -127,10 +145,11 @@ typedef struct {
     /* sampling / collocation rule */
     int32_t rule;      /* uq_rule */
     int32_t n_per_dim; /* GL: nodes per input                               */
-    int32_t order;     /* GL: total gPC degree P (K = C(d+P, P) terms)      */
-    int64_t mc_n;      /* MC: number of samples                             */
-    uint64_t seed;     /* MC: generator seed                                */
+    int32_t order;     /* GL / SMOLYAK_CC: total gPC degree P (K = C(d+P, P)) */
+    int64_t mc_n;      /* MC / HALTON / LHS: number of samples              */
+    uint64_t seed;     /* MC / LHS: generator seed                          */
     int32_t layout;    /* uq_layout                                         */
+    int32_t level;     /* SMOLYAK_CC: sparse-grid level                     */
 } uq_problem;
 
 /* Device context. `stream` is a hipStream_t (e.g. torch's current stream,

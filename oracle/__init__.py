@@ -76,6 +76,12 @@ def _declare(L):
                                      _dp]
     L.oracle_cylinder_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     L.oracle_cylinder_nodes.restype = C.c_long
+    L.oracle_cc_points.argtypes = [C.c_int]
+    L.oracle_cc_rule.argtypes = [C.c_int, _dp, _dp]
+    L.oracle_smolyak.argtypes = [C.c_int, C.c_int, _dp, _dp]
+    L.oracle_smolyak.restype = C.c_long
+    L.oracle_halton.argtypes = [C.c_long, C.c_int, _dp, _dp]
+    L.oracle_lhs.argtypes = [C.c_uint64, C.c_long, C.c_int, _dp, _dp]
 
 
 def _p(a):
@@ -169,6 +175,32 @@ def mc_points(seed, N, d):
     return xi, a
 
 
+def cc_rule(i):
+    m = lib().oracle_cc_points(i)
+    x, w = np.zeros(m), np.zeros(m)
+    lib().oracle_cc_rule(i, _p(x), _p(w))
+    return x, w
+
+
+def smolyak(d, level):
+    S = lib().oracle_smolyak(d, level, None, None)
+    xi, a = np.zeros((S, d)), np.zeros(S)
+    lib().oracle_smolyak(d, level, _p(xi), _p(a))
+    return xi, a
+
+
+def halton(N, d):
+    xi, a = np.zeros((N, d)), np.zeros(N)
+    lib().oracle_halton(N, d, _p(xi), _p(a))
+    return xi, a
+
+
+def lhs(seed, N, d):
+    xi, a = np.zeros((N, d)), np.zeros(N)
+    lib().oracle_lhs(C.c_uint64(seed), N, d, _p(xi), _p(a))
+    return xi, a
+
+
 # --------------------------------------------------------------------------
 # statistics
 
@@ -248,6 +280,12 @@ def sample_set(problem):
         return gl_tensor(d, r["n"])
     if r["kind"] == "mc":
         return mc_points(r.get("seed", 123456), r["N"], d)
+    if r["kind"] == "smolyak":
+        return smolyak(d, r["level"])
+    if r["kind"] == "halton":
+        return halton(r["N"], d)
+    if r["kind"] == "lhs":
+        return lhs(r.get("seed", 123456), r["N"], d)
     raise ValueError(r["kind"])
 
 
@@ -291,7 +329,8 @@ def run_problem(problem, samples=None, qois=None, steps=None):
     (nu, u0, phase_x, phase_y for the vortex; u_peak, D, cx, cy, ramp, xbc for
     the channel), dists = [(target, lo, hi), ...] with target in nu, u0,
     phase_x, phase_y, re, u_peak, and rule = {'kind': 'gl', 'n': points per
-    dimension, 'order': P} or {'kind': 'mc', 'N': samples, 'seed': s}.
+    dimension, 'order': P}, {'kind': 'smolyak', 'level': l, 'order': P},
+    {'kind': 'mc' | 'halton' | 'lhs', 'N': samples, 'seed': s}.
 
     samples: optional subset of sample indices to solve (statistics are then
     not computed). Returns per-sample QoIs and, for the full set, statistics.
@@ -307,7 +346,7 @@ def run_problem(problem, samples=None, qois=None, steps=None):
     d = xi.shape[1]
     r = problem["rule"]
     stats = {}
-    if r["kind"] == "gl":
+    if r["kind"] in ("gl", "smolyak"):
         alpha = multi_indices(d, r["order"])
         phi = phi_table(xi, alpha)
         out["alpha"], out["phi"] = alpha, phi

@@ -631,3 +631,195 @@ long oracle_cylinder_nodes(int nx, int ny, int D, int cx, int cy) {
         for (int x = 0; x < nx; ++x) s += ch_cyl(&c, x, y);
     return s;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse-grid collocation (Sec. "Quadrature and collocation": Clenshaw-
+ * Curtis rules combined into sparse Smolyak grids).                         */
+
+/* nested 1-D Clenshaw-Curtis rule of level i >= 1: 1 node (x = 0) at level 1,
+ * else m = 2^(i-1) + 1 nodes x_j = -cos(pi j/(m-1)).                        */
+int oracle_cc_points(int i) { return i <= 1 ? 1 : (1 << (i - 1)) + 1; }
+
+/* Weights for the probability measure dx/2: the unique weights that
+ * integrate the Chebyshev polynomials T_0..T_{m-1} exactly, found by solving
+ * sum_j w_j T_k(x_j) = int T_k dx/2 (= 1/(1-k^2) for even k, 0 for odd k)
+ * with Gaussian elimination and partial pivoting.                           */
+int oracle_cc_rule(int i, double *x, double *w) {
+    int m = oracle_cc_points(i);
+    const double pi = acos(-1.0);
+    if (m == 1) {
+        x[0] = 0.0;
+        w[0] = 1.0;
+        return 1;
+    }
+    for (int j = 0; j < m; ++j) x[j] = -cos(pi * j / (m - 1));
+    x[(m - 1) / 2] = 0.0;
+    double *A = malloc(sizeof(double) * m * (m + 1));
+    for (int k = 0; k < m; ++k) {
+        for (int j = 0; j < m; ++j) A[k * (m + 1) + j] = cos(k * acos(x[j])); /* T_k(x_j) */
+        A[k * (m + 1) + m] = (k % 2) ? 0.0 : 1.0 / (1.0 - (double)k * k);
+    }
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (fabs(A[r * (m + 1) + c]) > fabs(A[piv * (m + 1) + c])) piv = r;
+        for (int t = 0; t <= m; ++t) {
+            double tmp = A[c * (m + 1) + t];
+            A[c * (m + 1) + t] = A[piv * (m + 1) + t];
+            A[piv * (m + 1) + t] = tmp;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            double f = A[r * (m + 1) + c] / A[c * (m + 1) + c];
+            for (int t = c; t <= m; ++t) A[r * (m + 1) + t] -= f * A[c * (m + 1) + t];
+        }
+    }
+    for (int j = 0; j < m; ++j) w[j] = A[j * (m + 1) + m] / A[j * (m + 1) + j];
+    free(A);
+    return m;
+}
+
+/* Smolyak grid of level l in d dimensions by the difference formula
+ *   A(l, d) = sum_{|i| <= l + d} D^{i_1} x ... x D^{i_d},
+ *   D^1 = U^1, D^i = U^i - U^{i-1} (a signed rule on the nested nodes).
+ * Nodes are keyed by their index on the finest grid (level l+1); the union of
+ * all tensor grids is returned in lexicographic key order (input 0 first),
+ * with the summed weights. Returns the number of nodes; xi/a may be NULL to
+ * query it. Plain arrays: a dense table over the finest tensor grid.        */
+long oracle_smolyak(int d, int l, double *xi, double *a) {
+    int L = l + 1;
+    int mf = oracle_cc_points(L);
+    long cells = 1;
+    for (int k = 0; k < d; ++k) cells *= mf;
+    double *acc = calloc((size_t)cells, sizeof(double));
+    unsigned char *used = calloc((size_t)cells, 1);
+    /* difference rules on the finest index grid: D[i][idx] */
+    double **D = malloc(sizeof(double *) * (L + 1));
+    double *xs = malloc(sizeof(double) * mf), *ws = malloc(sizeof(double) * mf);
+    for (int i = 1; i <= L; ++i) {
+        D[i] = calloc((size_t)mf, sizeof(double));
+        int m = oracle_cc_rule(i, xs, ws);
+        for (int j = 0; j < m; ++j) {
+            int key = m == 1 ? (mf - 1) / 2 : j * ((mf - 1) / (m - 1));
+            D[i][key] += ws[j];
+        }
+        if (i > 1) {
+            int mp = oracle_cc_rule(i - 1, xs, ws);
+            for (int j = 0; j < mp; ++j) {
+                int key = mp == 1 ? (mf - 1) / 2 : j * ((mf - 1) / (mp - 1));
+                D[i][key] -= ws[j];
+            }
+        }
+    }
+    int *lev = malloc(sizeof(int) * d), *idx = malloc(sizeof(int) * d);
+    for (int k = 0; k < d; ++k) lev[k] = 1;
+    for (;;) {
+        int s = 0;
+        for (int k = 0; k < d; ++k) s += lev[k];
+        if (s <= l + d) {
+            /* every node of the finest grid that belongs to level lev[k] in
+             * each input: D^{lev} is supported on the level-lev nodes        */
+            for (int k = 0; k < d; ++k) idx[k] = 0;
+            for (;;) {
+                double w = 1.0;
+                int member = 1;
+                long flat = 0;
+                for (int k = 0; k < d; ++k) {
+                    int m = oracle_cc_points(lev[k]);
+                    int step = m == 1 ? 0 : (mf - 1) / (m - 1);
+                    int on = m == 1 ? (idx[k] == (mf - 1) / 2) : (idx[k] % step == 0);
+                    if (!on) member = 0;
+                    w *= D[lev[k]][idx[k]];
+                    flat = flat * mf + idx[k];
+                }
+                if (member) {
+                    acc[flat] += w;
+                    used[flat] = 1;
+                }
+                int k = d - 1;
+                while (k >= 0 && ++idx[k] == mf) idx[k--] = 0;
+                if (k < 0) break;
+            }
+        }
+        int k = d - 1;
+        while (k >= 0 && ++lev[k] > L) lev[k--] = 1;
+        if (k < 0) break;
+    }
+    const double pi = acos(-1.0);
+    long S = 0;
+    for (long c = 0; c < cells; ++c) {
+        if (!used[c]) continue;
+        if (xi) {
+            long rem = c;
+            for (int k = d - 1; k >= 0; --k) {
+                int id = (int)(rem % mf);
+                rem /= mf;
+                double v = mf == 1 ? 0.0 : -cos(pi * id / (mf - 1));
+                if (mf > 1 && 2 * id == mf - 1) v = 0.0;
+                xi[S * d + k] = v;
+            }
+        }
+        if (a) a[S] = acc[c];
+        ++S;
+    }
+    for (int i = 1; i <= L; ++i) free(D[i]);
+    free(D);
+    free(xs);
+    free(ws);
+    free(lev);
+    free(idx);
+    free(acc);
+    free(used);
+    return S;
+}
+
+/* Quasi Monte Carlo (Sec. "Monte Carlo and quasi Monte Carlo sampling"):
+ * Halton points with indices 1..N, input k in base = k-th prime: the base-p
+ * digits of the index mirrored about the radix point, computed as an integer
+ * digit reversal divided once by p^ndigits.                                 */
+void oracle_halton(long N, int d, double *xi, double *a) {
+    static const int primes[8] = {2, 3, 5, 7, 11, 13, 17, 19};
+    for (long j = 0; j < N; ++j) {
+        for (int k = 0; k < d; ++k) {
+            unsigned long long n = (unsigned long long)(j + 1), rev = 0, den = 1, p = (unsigned long long)primes[k];
+            while (n > 0) {
+                rev = rev * p + n % p;
+                den *= p;
+                n /= p;
+            }
+            xi[j * d + k] = 2.0 * ((double)rev / (double)den) - 1.0;
+        }
+        a[j] = 1.0 / (double)N;
+    }
+}
+
+/* Latin hypercube sampling (Sec. "Sampling strategies"): for input k the N
+ * strata are shuffled by Fisher-Yates, exchanging position i (i = N-1 .. 1)
+ * with position floor(r (i+1) / 2^64), r the SplitMix64 output number
+ * c = k*2N + i + 1 of the generator seeded with `seed`; sample j then lies in
+ * stratum perm[j] at fraction u = (output k*2N + N + j + 1 >> 11) 2^-53.     */
+void oracle_lhs(uint64_t seed, long N, int d, double *xi, double *a) {
+    long *perm = malloc(sizeof(long) * N);
+    for (int k = 0; k < d; ++k) {
+        for (long i = 0; i < N; ++i) perm[i] = i;
+        uint64_t s = seed;
+        /* run the generator to output number k*2N, then draw in order */
+        for (long c = 0; c < (long)k * 2 * N; ++c) splitmix_next(&s);
+        uint64_t *draws = malloc(sizeof(uint64_t) * 2 * N);
+        for (long c = 0; c < 2 * N; ++c) draws[c] = splitmix_next(&s);
+        for (long i = N - 1; i >= 1; --i) {
+            uint64_t r = draws[i];
+            long t = (long)(((unsigned __int128)r * (unsigned __int128)(i + 1)) >> 64);
+            long tmp = perm[i];
+            perm[i] = perm[t];
+            perm[t] = tmp;
+        }
+        for (long j = 0; j < N; ++j) {
+            double u = (double)(draws[N + j] >> 11) * (1.0 / 9007199254740992.0);
+            xi[j * d + k] = 2.0 * (((double)perm[j] + u) / (double)N) - 1.0;
+        }
+        free(draws);
+    }
+    for (long j = 0; j < N; ++j) a[j] = 1.0 / (double)N;
+    free(perm);
+}

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}
 GEOMETRY = {"tgv": 0, "channel": 1}
 XBC = {0: 0, 1: 1, 2: 2, "zouhe": 0, "walls": 1, "periodic": 2}
 TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5}
-RULE = {"gl": 0, "mc": 1}
+RULE = {"gl": 0, "mc": 1, "smolyak": 2, "halton": 3, "lhs": 4}
 LAYOUT = {"auto": 0, "aa": 1, "ab": 2}
 QOI = {"ke": 0, "vel": 1, "cd": 2, "cl": 3, "rho": 4}
 MAX_DIMS = 8
@@ -45,7 +45,7 @@ class Problem(C.Structure):
         ("u_peak", C.c_double), ("D", C.c_int32), ("cx", C.c_int32), ("cy", C.c_int32), ("xbc", C.c_int32),
         ("ramp", C.c_int64), ("n_dists", C.c_int32), ("dists", Dist * MAX_DIMS), ("rule", C.c_int32),
         ("n_per_dim", C.c_int32), ("order", C.c_int32), ("mc_n", C.c_int64), ("seed", C.c_uint64),
-        ("layout", C.c_int32),
+        ("layout", C.c_int32), ("level", C.c_int32),
     ]
 
 
@@ -179,6 +179,7 @@ def make_problem(spec: dict) -> Problem:
     p.mc_n = int(r.get("N", 0))
     p.seed = int(r.get("seed", 123456))
     p.layout = LAYOUT[spec.get("layout", "auto")]
+    p.level = int(r.get("level", 0))
     return p
 
 

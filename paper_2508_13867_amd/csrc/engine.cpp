@@ -41,8 +41,10 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
     return s;
 }
 
+// The job's own stream is non-blocking, so it is ordered against the
+// caller's stream explicitly, also when that is the null stream.
 uq_status Job::enter() {
-    if (user_stream && user_stream != stream) {
+    if (user_stream != stream) {
         UQ_HIP_TRY(hipEventRecord(ev_in, user_stream));
         UQ_HIP_TRY(hipStreamWaitEvent(stream, ev_in, 0));
     }
@@ -50,7 +52,7 @@ uq_status Job::enter() {
 }
 
 uq_status Job::leave() {
-    if (user_stream && user_stream != stream) {
+    if (user_stream != stream) {
         UQ_HIP_TRY(hipEventRecord(ev_out, stream));
         UQ_HIP_TRY(hipStreamWaitEvent(user_stream, ev_out, 0));
     }

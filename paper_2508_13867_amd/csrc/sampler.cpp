@@ -4,7 +4,9 @@
 // "Core class design" of OpenLB-UQ, arXiv 2508.13867).
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "uq_internal.h"
 
@@ -56,9 +58,14 @@ uq_status validate_problem(const uq_problem &p) {
         if (p.order < 0 || p.order > 32) return fail(UQ_EINVAL, "order must be in [0, 32]");
         double S = std::pow((double)p.n_per_dim, p.n_dists);
         if (S > 1e7) return fail(UQ_EINVAL, "tensor rule too large");
-    } else if (p.rule == UQ_RULE_MC) {
-        if (p.n_dists < 1) return fail(UQ_EINVAL, "Monte Carlo needs at least one uncertain input");
+    } else if (p.rule == UQ_RULE_MC || p.rule == UQ_RULE_HALTON || p.rule == UQ_RULE_LHS) {
+        if (p.n_dists < 1) return fail(UQ_EINVAL, "sampling needs at least one uncertain input");
         if (p.mc_n < 2 || p.mc_n > 10000000) return fail(UQ_EINVAL, "mc_n must be in [2, 1e7]");
+    } else if (p.rule == UQ_RULE_SMOLYAK_CC) {
+        if (p.n_dists < 1) return fail(UQ_EINVAL, "collocation needs at least one uncertain input");
+        if (p.level < 0 || p.level > 8) return fail(UQ_EINVAL, "level must be in [0, 8]");
+        if (p.order < 0 || p.order > 32) return fail(UQ_EINVAL, "order must be in [0, 32]");
+        if (p.n_dists * (p.level + 1) > 64) return fail(UQ_EINVAL, "sparse grid too large");
     } else {
         return fail(UQ_EINVAL, "unknown rule");
     }
@@ -158,6 +165,106 @@ static inline uint64_t splitmix_at(uint64_t seed, uint64_t c) {
     return z ^ (z >> 31);
 }
 
+// ------------------------------------------------------------------ Clenshaw-Curtis / Smolyak
+// 1-D nested Clenshaw-Curtis rule of level i >= 1: m(1) = 1 (the midpoint),
+// m(i) = 2^(i-1) + 1 nodes x_j = -cos(pi j/(m-1)); weights of the probability
+// measure dx/2 from the closed form (Clenshaw & Curtis 1960)
+//   w_j = c_j/n (1 - sum_{k=1}^{n/2} b_k cos(2 k j pi/n)/(4k^2 - 1)),
+// n = m - 1, c_0 = c_n = 1/2 (else 1), b_{n/2} = 1 (else 2); summing to one.
+static int cc_points(int i) { return i <= 1 ? 1 : (1 << (i - 1)) + 1; }
+
+static void cc_weights(int i, std::vector<double> &w) {
+    const int m = cc_points(i);
+    w.assign(m, 0.0);
+    if (m == 1) {
+        w[0] = 1.0;
+        return;
+    }
+    const int n = m - 1;
+    for (int j = 0; j <= n; ++j) {
+        double s = 0.0;
+        for (int k = 1; k <= n / 2; ++k) {
+            const double b = (2 * k == n) ? 1.0 : 2.0;
+            s += b * std::cos(2.0 * k * j * M_PI / n) / (4.0 * k * k - 1.0);
+        }
+        const double c = (j == 0 || j == n) ? 0.5 : 1.0;
+        w[j] = c / n * (1.0 - s);
+    }
+}
+
+// Smolyak sparse grid by the combination technique:
+//   A(l, d) = sum over levels i (i_k >= 1) with l + 1 <= |i| <= l + d of
+//             (-1)^(l + d - |i|) C(d - 1, l + d - |i|) (U^{i_1} x ... x U^{i_d}).
+// Nodes are identified by their index on the finest 1-D grid (level l + 1),
+// so coinciding nodes of different tensor grids merge exactly.
+static void smolyak(int d, int l, std::vector<double> &xi, std::vector<double> &a, int64_t &S) {
+    const int imax = l + 1;
+    const int mf = cc_points(imax);  // finest 1-D grid
+    std::map<std::vector<int>, double> acc;
+    std::vector<int> lev(d, 1);
+    std::vector<std::vector<double>> W(imax + 1);
+    for (int i = 1; i <= imax; ++i) cc_weights(i, W[i]);
+    auto binom = [](int n, int k) {
+        double r = 1.0;
+        for (int t = 1; t <= k; ++t) r = r * (n - k + t) / t;
+        return r;
+    };
+    for (;;) {
+        int sum = 0;
+        for (int k = 0; k < d; ++k) sum += lev[k];
+        if (sum >= l + 1 && sum <= l + d) {
+            const int e = l + d - sum;
+            const double coef = ((e & 1) ? -1.0 : 1.0) * binom(d - 1, e);
+            // tensor grid of this level multi-index
+            std::vector<int> j(d, 0), key(d);
+            for (;;) {
+                double wt = coef;
+                for (int k = 0; k < d; ++k) {
+                    const int m = cc_points(lev[k]);
+                    key[k] = m == 1 ? (mf - 1) / 2 : j[k] * ((mf - 1) / (m - 1));
+                    wt *= W[lev[k]][j[k]];
+                }
+                acc[key] += wt;
+                int k = d - 1;
+                while (k >= 0 && ++j[k] == cc_points(lev[k])) j[k--] = 0;
+                if (k < 0) break;
+            }
+        }
+        int k = d - 1;
+        while (k >= 0 && ++lev[k] > imax) lev[k--] = 1;
+        if (k < 0) break;
+    }
+    S = (int64_t)acc.size();
+    xi.assign((size_t)S * d, 0.0);
+    a.assign((size_t)S, 0.0);
+    int64_t s = 0;
+    for (auto &kv : acc) {  // std::map order: lexicographic, input 0 first
+        for (int k = 0; k < d; ++k)
+            xi[(size_t)s * d + k] = mf == 1 ? 0.0 : -std::cos(M_PI * kv.first[k] / (mf - 1));
+        a[(size_t)s] = kv.second;
+        ++s;
+    }
+    // the middle node is exactly zero
+    for (auto &v : xi)
+        if (std::fabs(v) < 1e-15) v = 0.0;
+}
+
+// ------------------------------------------------------------------ Halton / LHS
+static double radical_inverse(uint64_t n, uint64_t base) {
+    double inv = 1.0 / (double)base, f = inv, r = 0.0;
+    while (n > 0) {
+        r += f * (double)(n % base);
+        n /= base;
+        f *= inv;
+    }
+    return r;
+}
+
+static const int kPrimes[UQ_MAX_DIMS] = {2, 3, 5, 7, 11, 13, 17, 19};
+
+// uniform integer in [0, n) from one generator output (Lemire's multiply-shift)
+static inline uint64_t bounded(uint64_t r, uint64_t n) { return (uint64_t)(((unsigned __int128)r * n) >> 64); }
+
 // ------------------------------------------------------------------ rule
 uq_status build_rule(const uq_problem &p, Rule &r) {
     uq_status st = validate_problem(p);
@@ -197,18 +304,54 @@ uq_status build_rule(const uq_problem &p, Rule &r) {
                 r.phi[j * r.K + t] = v;
             }
         }
+    } else if (p.rule == UQ_RULE_SMOLYAK_CC) {
+        smolyak(d, p.level, r.xi, r.a, r.S);
+        multi_indices(d, p.order, r.alpha);
+        r.K = (int)(r.alpha.size() / d);
+        r.phi.resize(r.S * r.K);
+        std::vector<double> pv((size_t)d * (p.order + 1));
+        for (int64_t j = 0; j < r.S; ++j) {
+            for (int k = 0; k < d; ++k) ortho_legendre_all(p.order, r.xi[j * d + k], &pv[(size_t)k * (p.order + 1)]);
+            for (int t = 0; t < r.K; ++t) {
+                double v = 1.0;
+                for (int k = 0; k < d; ++k) v *= pv[(size_t)k * (p.order + 1) + r.alpha[(size_t)t * d + k]];
+                r.phi[j * r.K + t] = v;
+            }
+        }
     } else {
         const int64_t N = p.mc_n;
         r.S = N;
         r.K = 0;
         r.xi.resize(N * d);
         r.a.assign(N, 1.0 / (double)N);
-        for (int64_t j = 0; j < N; ++j)
+        if (p.rule == UQ_RULE_HALTON) {
+            for (int64_t j = 0; j < N; ++j)
+                for (int k = 0; k < d; ++k) r.xi[j * d + k] = 2.0 * radical_inverse((uint64_t)j + 1, kPrimes[k]) - 1.0;
+        } else if (p.rule == UQ_RULE_LHS) {
+            // input k: Fisher-Yates shuffle of the strata 0..N-1 driven by draws
+            // c = k*2N + i + 1 (i = N-1 .. 1), then the position inside stratum
+            // s of sample j from draw c = k*2N + N + j + 1
+            std::vector<int64_t> perm((size_t)N);
             for (int k = 0; k < d; ++k) {
-                uint64_t bits = splitmix_at(p.seed, (uint64_t)(j * d + k + 1));
-                double u = (double)(bits >> 11) * 0x1.0p-53;
-                r.xi[j * d + k] = 2.0 * u - 1.0;
+                for (int64_t i = 0; i < N; ++i) perm[(size_t)i] = i;
+                const uint64_t base = (uint64_t)k * 2 * (uint64_t)N;
+                for (int64_t i = N - 1; i >= 1; --i) {
+                    const uint64_t t = bounded(splitmix_at(p.seed, base + (uint64_t)i + 1), (uint64_t)i + 1);
+                    std::swap(perm[(size_t)i], perm[(size_t)t]);
+                }
+                for (int64_t j = 0; j < N; ++j) {
+                    const double u = (double)(splitmix_at(p.seed, base + (uint64_t)N + (uint64_t)j + 1) >> 11) * 0x1.0p-53;
+                    r.xi[j * d + k] = 2.0 * (((double)perm[(size_t)j] + u) / (double)N) - 1.0;
+                }
             }
+        } else {
+            for (int64_t j = 0; j < N; ++j)
+                for (int k = 0; k < d; ++k) {
+                    uint64_t bits = splitmix_at(p.seed, (uint64_t)(j * d + k + 1));
+                    double u = (double)(bits >> 11) * 0x1.0p-53;
+                    r.xi[j * d + k] = 2.0 * u - 1.0;
+                }
+        }
     }
     return UQ_OK;
 }

@@ -327,7 +327,7 @@ extern "C" uq_status uq_sync(uq_job *j) {
     if (!j) return fail(UQ_EINVAL, "null job");
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
     UQ_HIP_TRY(hipStreamSynchronize(j->stream));
-    if (j->user_stream) UQ_HIP_TRY(hipStreamSynchronize(j->user_stream));
+    UQ_HIP_TRY(hipStreamSynchronize(j->user_stream));
     return UQ_OK;
 }
 

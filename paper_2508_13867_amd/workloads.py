@@ -103,3 +103,12 @@ def serving_trace(n_jobs=16, seed=SEED, load=1.2, rate_nodes_per_s=5.0e10, max_S
     gaps = rng.exponential(mean_service / load, size=n_jobs)
     t = np.cumsum(gaps) - gaps[0]
     return [(float(a), j) for a, j in zip(t, jobs)]
+
+
+# 128^2 vortex, 4-D inputs, level-3 Smolyak sparse grid of nested
+# Clenshaw-Curtis rules (137 points, the paper's sparse-grid size), order 3
+TGV_SMOLYAK = dict(
+    name="tgv128_smolyak_l3", geometry="tgv", precision="fp32", nx=128, ny=128, steps=2000,
+    u0=0.02, nu=0.005, dists=FOUR_D_INPUTS, rule=dict(kind="smolyak", level=3, order=3),
+)
+WORKLOADS[TGV_SMOLYAK["name"]] = TGV_SMOLYAK

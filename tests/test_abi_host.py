@@ -67,6 +67,24 @@ def test_collocation_rule_matches_oracle(spec):
     assert np.abs(phi - O.phi_table(xo, alpha)).max() < 1e-12
 
 
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4])
+def test_smolyak_rule_matches_oracle(level):
+    spec = W.scaled(W.TGV_BATCHED_FP32, rule=dict(kind="smolyak", level=level, order=min(level, 3)))
+    xi, a, alpha, phi = A.rule_points(spec)
+    xo, ao = O.smolyak(4, level)
+    assert xi.shape == xo.shape and np.abs(xi - xo).max() < 1e-15 and np.abs(a - ao).max() < 1e-13
+    assert np.abs(phi - O.phi_table(xo, alpha)).max() < 1e-12
+
+
+def test_halton_and_lhs_match_oracle():
+    xi, a, _, _ = A.rule_points(W.scaled(W.TGV_MC, rule=dict(kind="halton", N=1000)))
+    xo, ao = O.halton(1000, 4)
+    assert np.abs(xi - xo).max() < 1e-15 and np.array_equal(a, ao)
+    xi, a, _, _ = A.rule_points(W.scaled(W.TGV_MC, rule=dict(kind="lhs", N=777, seed=9)))
+    xo, ao = O.lhs(9, 777, 4)
+    assert np.array_equal(xi, xo) and np.array_equal(a, ao)
+
+
 def test_monte_carlo_points_bit_exact_with_oracle():
     xi, a, alpha, phi = A.rule_points(W.TGV_MC)
     xo, ao = O.mc_points(W.SEED, 4096, 4)

@@ -319,3 +319,20 @@ def test_mc4096_full_size_precisions_vs_fp64_and_oracle():
         for k in ("mean", "var"):
             assert rel_l2(st[prec][k], st["fp64"][k]) < TOL[prec], (prec, k, rel_l2(st[prec][k], st["fp64"][k]))
         assert rel_l2(ke[prec], ke["fp64"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("rule", [dict(kind="smolyak", level=2, order=2), dict(kind="halton", N=40),
+                                  dict(kind="lhs", N=40, seed=77)])
+def test_sparse_grid_qmc_lhs_rules_fp64(rule):
+    spec = dict(name="tgv48x40_rules", geometry="tgv", precision="fp64", nx=48, ny=40, steps=61, u0=0.02,
+                nu=0.005, dists=W.FOUR_D_INPUTS, rule=rule)
+    say("case rule", rule)
+    ref = O.run_problem(spec, qois=["ke", "vel"])
+    with Job(spec) as job:
+        xi, a = job.samples()
+        assert np.abs(xi - ref["xi"]).max() < 1e-15 and np.abs(a - ref["a"]).max() < 1e-13
+        job.run(spec["steps"])
+        for q in ("ke", "vel"):
+            st = job.moments(q)
+            for k in ("mean", "var", "var_alt") + (("coeffs",) if rule["kind"] == "smolyak" else ()):
+                assert rel_l2(st[k], ref["stats"][q][k]) < TOL["fp64"], (q, k)

@@ -381,3 +381,84 @@ def test_symmetric_cylinder_has_no_lift_and_quiescent_no_force():
     assert r["cd"] > 0 and abs(r["cl"]) < 1e-10 * r["cd"]
     q = O.channel_run(40, 21, 0.05, 0.0, 100, D=8, cx=12, cy=10)
     assert np.abs(q["force"]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- sparse grids, QMC, LHS
+
+def test_clenshaw_curtis_closed_forms_and_exactness():
+    x, w = O.cc_rule(2)  # Simpson's rule on [-1, 1], probability weights
+    assert np.allclose(x, [-1, 0, 1], atol=1e-16) and np.allclose(w, [1 / 6, 2 / 3, 1 / 6], atol=1e-15)
+    x, w = O.cc_rule(3)
+    assert np.allclose(w, [1 / 30, 4 / 15, 2 / 5, 4 / 15, 1 / 30], atol=1e-15)
+    for i in (2, 3, 4, 5):
+        x, w = O.cc_rule(i)
+        m = len(x)
+        assert m == 2 ** (i - 1) + 1
+        for k in range(m):  # exact up to degree m - 1 (and m, by symmetry)
+            exact = 0.0 if k % 2 else 1.0 / (k + 1)
+            assert abs((w * x ** k).sum() - exact) < 1e-13
+
+
+def test_smolyak_point_counts_include_the_papers_137():
+    # Sec. "Performance results": the four-dimensional TGV runs use a sparse
+    # grid of 137 points; it is the level-3 nested Clenshaw-Curtis grid in d = 4
+    assert [len(O.smolyak(4, l)[1]) for l in range(5)] == [1, 9, 41, 137, 401]
+    assert [len(O.smolyak(2, l)[1]) for l in range(5)] == [1, 5, 13, 29, 65]
+    assert [len(O.smolyak(1, l)[1]) for l in range(5)] == [1, 3, 5, 9, 17]
+
+
+@pytest.mark.parametrize("d,l", [(2, 1), (2, 3), (3, 2), (4, 3)])
+def test_smolyak_exact_to_total_degree_2l_plus_1(d, l):
+    xi, a = O.smolyak(d, l)
+    assert abs(a.sum() - 1.0) < 1e-13
+    import itertools
+    for e in itertools.product(range(2 * l + 2), repeat=d):
+        if sum(e) > 2 * l + 1:
+            continue
+        exact = 1.0
+        for ek in e:
+            exact *= 0.0 if ek % 2 else 1.0 / (ek + 1)
+        got = (a * np.prod(xi ** np.array(e), axis=1)).sum()
+        assert abs(got - exact) < 1e-12, (e, got, exact)
+
+
+def test_smolyak_gpc_projection_recovers_degree_l_expansion():
+    rng = np.random.default_rng(2)
+    d, l = 4, 3
+    xi, a = O.smolyak(d, l)
+    al = O.multi_indices(d, l)
+    coef = rng.standard_normal(al.shape[0])
+    phi = O.phi_table(xi, al)
+    st = O.gpc_stats(phi @ coef, a, phi)
+    assert np.allclose(st["coeffs"][:, 0], coef, atol=1e-11)
+
+
+def test_halton_closed_form_points():
+    xi, a = O.halton(7, 2)
+    u = (xi + 1) / 2
+    assert np.allclose(u[:, 0], [1 / 2, 1 / 4, 3 / 4, 1 / 8, 5 / 8, 3 / 8, 7 / 8], atol=1e-16)
+    assert np.allclose(u[:, 1], [1 / 3, 2 / 3, 1 / 9, 4 / 9, 7 / 9, 2 / 9, 5 / 9], atol=1e-16)
+    assert np.all(a == 1 / 7)
+
+
+def test_qmc_and_lhs_rates():
+    # a smooth integrand in d = 2: Halton error ~ N^-1 (log terms aside),
+    # MC ~ N^-1/2; LHS removes the additive part of the MC error
+    g = lambda z: np.exp(0.5 * z[:, 0] + 0.25 * z[:, 1])
+    exact = (np.sinh(0.5) / 0.5) * (np.sinh(0.25) / 0.25)
+    Ns = [128, 512, 2048, 8192]
+    err = [abs(O.mc_stats(g(O.halton(N, 2)[0]))["mean"][0] - exact) for N in Ns]
+    slope = np.polyfit(np.log(Ns), np.log(err), 1)[0]
+    assert slope < -0.8, slope
+    rms_mc = np.sqrt(np.mean([(O.mc_stats(g(O.mc_points(s, 256, 2)[0]))["mean"][0] - exact) ** 2 for s in range(32)]))
+    rms_lhs = np.sqrt(np.mean([(O.mc_stats(g(O.lhs(s, 256, 2)[0]))["mean"][0] - exact) ** 2 for s in range(32)]))
+    assert rms_lhs < rms_mc / 3, (rms_lhs, rms_mc)
+
+
+def test_lhs_strata_are_a_permutation():
+    N, d = 97, 3
+    xi, a = O.lhs(11, N, d)
+    for k in range(d):
+        strata = np.floor((xi[:, k] + 1) / 2 * N).astype(int)
+        assert sorted(strata.tolist()) == list(range(N))
+    assert not np.array_equal(O.lhs(11, N, d)[0], O.lhs(12, N, d)[0])
