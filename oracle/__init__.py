@@ -76,6 +76,8 @@ def _declare(L):
                                      _dp]
     L.oracle_cylinder_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     L.oracle_cylinder_nodes.restype = C.c_long
+    L.oracle_tgv_harmonic_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_long, C.c_double,
+                                          _dp, _dp, _dp, _dp, _dp, _dp]
     L.oracle_cc_points.argtypes = [C.c_int]
     L.oracle_cc_rule.argtypes = [C.c_int, _dp, _dp]
     L.oracle_smolyak.argtypes = [C.c_int, C.c_int, _dp, _dp]
@@ -246,6 +248,40 @@ def tgv_run(nx, ny, nu, u0, steps, phase_x=0.0, phase_y=0.0, ke_u0=None, want_f=
     return out
 
 
+def tgv_harmonic_run(nx, ny, nu, u0, zeta, steps, ke_u0=None, want_f=False):
+    n = nx * ny
+    rho, ux, uy, sp = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    f = np.zeros(9 * n) if want_f else None
+    z = np.ascontiguousarray(zeta, dtype=np.float64)
+    ke = C.c_double()
+    rc = lib().oracle_tgv_harmonic_run(nx, ny, nu, u0, _p(z), steps, u0 if ke_u0 is None else ke_u0, _p(f),
+                                       _p(rho), _p(ux), _p(uy), _p(sp), C.byref(ke))
+    if rc != 0:
+        raise ValueError("invalid TGV parameters (tau must exceed 1/2)")
+    out = {"ke": ke.value, "rho": rho.reshape(ny, nx), "ux": ux.reshape(ny, nx), "uy": uy.reshape(ny, nx),
+           "speed": sp.reshape(ny, nx)}
+    if want_f:
+        out["f"] = f.reshape(9, ny, nx)
+    return out
+
+
+def wasserstein1(xa, wa, xb, wb):
+    """W_1 between two weighted empirical measures on the real line, as the
+    integral over p in [0, 1] of |Q_a(p) - Q_b(p)| (Q the quantile functions):
+    sort each, walk both piecewise-constant quantile functions together."""
+    xa, wa, xb, wb = (np.asarray(v, dtype=np.float64).ravel() for v in (xa, wa, xb, wb))
+    ia, ib = np.argsort(xa, kind="stable"), np.argsort(xb, kind="stable")
+    xa, wa, xb, wb = xa[ia], wa[ia] / wa.sum(), xb[ib], wb[ib] / wb.sum()
+    Pa, Pb = np.cumsum(wa), np.cumsum(wb)
+    Pa[-1] = Pb[-1] = 1.0
+    edges = np.union1d(Pa, Pb)
+    lo = np.concatenate([[0.0], edges[:-1]])
+    mid = 0.5 * (lo + edges)
+    qa = xa[np.minimum(np.searchsorted(Pa, mid, side="left"), len(xa) - 1)]
+    qb = xb[np.minimum(np.searchsorted(Pb, mid, side="left"), len(xb) - 1)]
+    return float(np.sum(np.abs(qa - qb) * (edges - lo)))
+
+
 def channel_run(nx, ny, nu, u_peak, steps, D=0, cx=0, cy=0, ramp=0, xbc=0, want_f=False, ux_init=0.0):
     n = nx * ny
     rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -269,7 +305,7 @@ def cylinder_nodes(nx, ny, D, cx, cy):
 # --------------------------------------------------------------------------
 # the non-intrusive UQ algorithm, one sample after the other
 
-_TARGETS = ("nu", "u0", "phase_x", "phase_y", "re", "u_peak")
+_TARGETS = ("nu", "u0", "phase_x", "phase_y", "re", "u_peak", "zeta00", "zeta01", "zeta10", "zeta11")
 
 
 def sample_set(problem):
@@ -309,16 +345,21 @@ def solve_sample(problem, params, steps=None):
     """One deterministic LBM run of the given sample; returns its QoIs."""
     steps = problem["steps"] if steps is None else steps
     nx, ny = problem["nx"], problem["ny"]
+    if problem["geometry"] == "tgv" and problem.get("init", "tgv") == "harmonic":
+        zeta = [params["zeta00"], params["zeta01"], params["zeta10"], params["zeta11"]]
+        r = tgv_harmonic_run(nx, ny, params["nu"], params["u0"], zeta, steps, ke_u0=problem["u0"])
+        return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"], "speed": r["speed"]}
     if problem["geometry"] == "tgv":
         r = tgv_run(nx, ny, params["nu"], params["u0"], steps, params["phase_x"], params["phase_y"],
                     ke_u0=problem["u0"])
-        return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
+        return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"],
+                "speed": np.sqrt(r["ux"] ** 2 + r["uy"] ** 2)}
     if problem["geometry"] == "channel":
         xbc = {"zouhe": 0, "walls": 1, "periodic": 2}.get(problem.get("xbc", 0), problem.get("xbc", 0))
         r = channel_run(nx, ny, params["nu"], params["u_peak"], steps, D=problem.get("D", 0),
                         cx=problem.get("cx", 0), cy=problem.get("cy", 0), ramp=problem.get("ramp", 0), xbc=xbc)
         return {"cd": r["cd"], "cl": r["cl"], "fx": r["force"][0], "fy": r["force"][1],
-                "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"]}
+                "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"], "speed": np.sqrt(r["ux"] ** 2 + r["uy"] ** 2)}
     raise ValueError(problem["geometry"])
 
 

@@ -462,3 +462,70 @@ def test_lhs_strata_are_a_permutation():
         strata = np.floor((xi[:, k] + 1) / 2 * N).astype(int)
         assert sorted(strata.tolist()) == list(range(N))
     assert not np.array_equal(O.lhs(11, N, d)[0], O.lhs(12, N, d)[0])
+
+
+# ------------------------------------------- four-dimensional perturbed vortex
+
+def test_harmonic_vortex_without_perturbation_is_the_tiled_vortex():
+    # Eq. taylorGreen has wavenumber 2 on [0, 2 pi): with every zeta = 0 it is
+    # the one-period vortex of half the lattice repeated 2 x 2, and the
+    # periodic dynamics keep that tiling (up to the rounding of the two
+    # ways of evaluating the initial trigonometric terms).
+    n, nu, u0, T = 24, 0.015, 0.04, 90
+    h = O.tgv_harmonic_run(n, n, nu, u0, [0, 0, 0, 0], T)
+    t = O.tgv_run(n // 2, n // 2, nu, u0, T)
+    for k in ("ux", "uy", "rho"):
+        assert np.allclose(h[k], np.tile(t[k], (2, 2)), rtol=0, atol=1e-14), k
+    assert abs(h["ke"] - t["ke"]) < 1e-13
+
+
+def test_harmonic_vortex_point_values_isolate_each_amplitude():
+    # On n = 32 nodes, X = pi x / 16: at the nodes below 4X and 4Y are
+    # multiples of pi/2, so eps_d reduces to +-zeta_ij / 4 for a single (i, j)
+    # and the velocity to closed values (sin 4X = k_0, cos 4X = k_1).
+    n, u0 = 32, 0.05
+    z = np.array([0.31, -0.23, 0.47, 0.71])  # zeta_00, zeta_01, zeta_10, zeta_11
+    r = O.tgv_harmonic_run(n, n, 0.01, u0, z, 0)
+    s = np.sqrt(0.5)
+    # (x, y) = (2, 2): sin 4X = sin 4Y = 1 -> zeta_00 / 4; ux = -uR s s
+    assert abs(r["ux"][2, 2] - (-u0 * (1 + z[0] / 4) * 0.5)) < 1e-16
+    # (2, 4): sin 4X = 1, cos 4Y = -1 -> -zeta_01 / 4; ux = -uR s 1
+    assert abs(r["ux"][4, 2] - (-u0 * (1 - z[1] / 4) * s)) < 1e-16
+    # (4, 2): cos 4X = -1, sin 4Y = 1 -> -zeta_10 / 4; uy = uR 1 s
+    assert abs(r["uy"][2, 4] - (u0 * (1 - z[2] / 4) * s)) < 1e-16
+    # (4, 0): cos 4X = -1, cos 4Y = 1 -> -zeta_11 / 4; uy = uR
+    assert abs(r["uy"][0, 4] - (u0 * (1 - z[3] / 4))) < 1e-16
+    # pressure through rho = 1 + 3 p at (4, 0): cos 4X + cos 4Y = 0
+    assert abs(r["rho"][0, 4] - 1.0) < 1e-15
+    assert np.allclose(r["speed"], np.hypot(r["ux"], r["uy"]), rtol=0, atol=1e-17)
+
+
+def test_harmonic_vortex_transpose_swaps_the_mixed_amplitudes():
+    # swapping x and y maps amplitude u0 onto -u0 (as for the plain vortex)
+    # and exchanges the two mixed harmonics zeta_01 <-> zeta_10
+    n, T = 16, 80
+    z = [0.02, -0.015, 0.024, -0.01]
+    A = O.tgv_harmonic_run(n, n, 0.02, 0.05, z, T)
+    B = O.tgv_harmonic_run(n, n, 0.02, -0.05, [z[0], z[2], z[1], z[3]], T)
+    assert np.allclose(B["ux"], A["uy"].T, rtol=0, atol=2e-15)
+    assert np.allclose(B["uy"], A["ux"].T, rtol=0, atol=2e-15)
+    # and the perturbation matters at all
+    C0 = O.tgv_harmonic_run(n, n, 0.02, 0.05, [0, 0, 0, 0], T)
+    assert np.abs(C0["ux"] - A["ux"]).max() > 1e-6
+
+
+def test_wasserstein1_vs_scipy_and_closed_forms():
+    from scipy.stats import wasserstein_distance as wd
+    rng = np.random.default_rng(11)
+    for na, nb in ((1, 1), (7, 13), (200, 50)):
+        xa, xb = rng.normal(size=na), rng.normal(0.3, 2.0, size=nb)
+        wa, wb = rng.random(na) + 0.1, rng.random(nb) + 0.1
+        assert abs(O.wasserstein1(xa, wa, xb, wb) - wd(xa, xb, wa, wb)) < 1e-13
+        assert abs(O.wasserstein1(xa, np.ones(na), xb, np.ones(nb)) - wd(xa, xb)) < 1e-13
+    x = rng.random(40)
+    # shift by c: |c|; with itself: 0; two point masses: |a - b|
+    assert abs(O.wasserstein1(x, np.ones(40), x + 0.37, np.ones(40)) - 0.37) < 1e-14
+    assert O.wasserstein1(x, np.ones(40), x[::-1], np.ones(40)) == 0.0
+    assert abs(O.wasserstein1([2.0], [1.0], [-1.5], [3.0]) - 3.5) < 1e-15
+    # ties and repeated values: a mass of 1/2 at 0 and 1/2 at 1 against U{0, 0, 1, 1, 1, 1}
+    assert abs(O.wasserstein1([0, 1], [1, 1], [0, 0, 1, 1, 1, 1], np.ones(6)) - 1 / 6) < 1e-15
