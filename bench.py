@@ -236,6 +236,79 @@ def study_cylinder(U, W, log, oracle_samples=1):
     return out
 
 
+def study_wasserstein(U, W, log, prec="fp32", ns=(8, 16, 32, 64, 128), n_ref=256, fracs=(0.2, 0.4, 0.6, 0.8, 1.0),
+                      chunk=40000):
+    """Wasserstein convergence of the numerical statistical solutions of the
+    four-dimensional perturbed vortex: for each resolution n (N = n samples,
+    Table tab:simulation_parameters units, FP32) and each checkpoint t =
+    frac T_max, W_1 between the law of |u| (all nodes of all samples, in
+    physical units |u| / u_lat) at n and at the reference resolution, with
+    the observed rate of decay in n. A re-run of n = 128 in the other
+    precision measures what the storage precision alone moves the statistic
+    by. The initial field is invariant under a shift by half the period in
+    x; `asym` is the largest departure from that symmetry, max |u(x + n/2, y)
+    - u(x, y)| / u_lat over all samples: exact arithmetic keeps it at zero,
+    so its growth is symmetry breaking seeded by rounding."""
+    import numpy as np
+
+    def asym(job, n, u_lat):
+        v = job.qoi_samples("vel").reshape(job.S, 2, n, n)
+        return float(np.abs(np.roll(v, -(n // 2), axis=3) - v).max() / u_lat)
+
+    res = {}
+    for n in ns + (n_ref,):
+        u = U.tgv_units(n, 1.6 / n, 40.0 * n)
+        res[n] = {"units": u, "job": U.Job(W.tgv4d(n, u, precision=prec)), "done": 0, "ms": 0.0}
+    out = {"workload": f"tgv4d, n = 8..128 against 256, N = n MC samples, T_max = 100, {prec.upper()}",
+           "precision": prec, "units": {n: r["units"] for n, r in res.items()}, "checkpoints": []}
+    try:
+        for f in fracs:
+            t = f * W.TGV4D_T_MAX
+            for n, r in res.items():
+                target = int(round(t / r["units"]["dt"]))
+                while r["done"] < target:
+                    k = min(chunk, target - r["done"])
+                    r["ms"] += r["job"].run_timed(k)
+                    r["done"] += k
+                    if n == n_ref:
+                        log(f"bench: tgv4d n={n} step {r['done']} of {target} (t = {t:g})")
+            ref = res[n_ref]
+            cp = {"t": t, "frac": f, "steps": {n: r["done"] for n, r in res.items()}, "w1": {}}
+            for n in ns:
+                cp["w1"][n] = U.wasserstein1(res[n]["job"], ref["job"], "speed", 1.0 / res[n]["units"]["u_lat"],
+                                             1.0 / ref["units"]["u_lat"])
+            cp["mean_speed_ref"] = float(np.mean(ref["job"].moments("speed")["mean"]) / ref["units"]["u_lat"])
+            cp["asym"] = {n: asym(r["job"], n, r["units"]["u_lat"]) for n, r in res.items()}
+            x, y = np.log(np.array(ns, float)), np.log(np.array([cp["w1"][n] for n in ns]))
+            cp["rate_all"] = float(-np.polyfit(x, y, 1)[0])
+            cp["rate_last3"] = float(-np.polyfit(x[-3:], y[-3:], 1)[0])
+            log(f"bench: tgv4d t={t:g} W1 {cp['w1']} rate {cp['rate_all']:.2f} (last three {cp['rate_last3']:.2f})")
+            out["checkpoints"].append(cp)
+        for n, r in res.items():
+            nodes = r["job"].S * n * n
+            out.setdefault("mlups", {})[n] = round(nodes * r["done"] / (r["ms"] * 1e-3) / 1e6, 1)
+        # what the storage precision alone changes at n = 128, T_max
+        n = 128
+        r = res[n]
+        other = "fp64" if prec != "fp64" else "fp32"
+        with U.Job(W.tgv4d(n, r["units"], precision=other)) as jo:
+            done = 0
+            while done < r["done"]:
+                k = min(chunk, r["done"] - done)
+                jo.run(k)
+                done += k
+                log(f"bench: tgv4d n={n} {other} step {done} of {r['done']}")
+            out["fp32_vs_fp64_w1_n128"] = U.wasserstein1(r["job"], jo, "speed", 1.0 / r["units"]["u_lat"],
+                                                         1.0 / r["units"]["u_lat"])
+            out[f"asym_n128_{other}"] = asym(jo, n, r["units"]["u_lat"])
+    finally:
+        for r in res.values():
+            r["job"].close()
+        for r in res.values():
+            del r["job"]
+    return out
+
+
 def cpu_baseline(spec, n_samples=4, lbm_steps=300):
     """The FP64 oracle, single-threaded, on the full lattice of the workload
     for a few samples and steps (about 10 s of CPU work)."""
@@ -265,8 +338,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
-    ap.add_argument("--study", choices=["precision", "cylinder", "samplers"], default=None,
+    ap.add_argument("--study", choices=["precision", "cylinder", "samplers", "wasserstein"], default=None,
                     help="run a measurement study instead of the benchmark and print its JSON")
+    ap.add_argument("--study-precision", default="fp32", choices=["fp64", "fp32"],
+                    help="storage precision of the wasserstein study")
     ap.add_argument("--serving-jobs", type=int, default=24)
     ap.add_argument("--serving-load", type=float, default=1.2)
     ap.add_argument("--no-tune", action="store_true",
@@ -305,6 +380,9 @@ def main():
         return
     if args.study == "samplers":
         print(json.dumps(study_samplers(U, W, log)), flush=True)
+        return
+    if args.study == "wasserstein":
+        print(json.dumps(study_wasserstein(U, W, log, prec=args.study_precision)), flush=True)
         return
 
     tune = None

@@ -84,8 +84,30 @@ typedef enum {
     UQ_T_PHASE_X = 2, /* TGV phase shift in x (radians)                    */
     UQ_T_PHASE_Y = 3, /* TGV phase shift in y                              */
     UQ_T_RE = 4,      /* channel Reynolds number; nu = u_peak_nominal D/Re */
-    UQ_T_U_PEAK = 5   /* channel peak inflow velocity                      */
+    UQ_T_U_PEAK = 5,  /* channel peak inflow velocity                      */
+    /* amplitudes zeta_{ij} of the harmonic perturbation of the TGV with
+     * init = UQ_INIT_TGV_HARMONIC (i, j in {0, 1}) */
+    UQ_T_ZETA00 = 6,
+    UQ_T_ZETA01 = 7,
+    UQ_T_ZETA10 = 8,
+    UQ_T_ZETA11 = 9
 } uq_target;
+
+/* Initial field of the vortex. */
+typedef enum {
+    /* u = u0(-cos(kx+px) sin(ky+py), sin(kx+px) cos(ky+py)), k = 2 pi/n */
+    UQ_INIT_TGV = 0,
+    /* the four-dimensional perturbed vortex (Sec. "Taylor--Green vortex flow
+     * with four-dimensional uncertain initial velocity perturbation", Eq.
+     * taylorGreen): two periods over the lattice, kappa = 4 pi/n,
+     *   u = u0^R (-cos(kappa x) sin(kappa y), sin(kappa x) cos(kappa y)),
+     *   p = -(u0^R)^2/4 (cos(2 kappa x) + cos(2 kappa y)), rho = 1 + 3p,
+     *   u0^R = u0 (1 + eps), eps = 1/4 sum_{i,j in {0,1}} zeta_ij
+     *          k_i(2 kappa x) k_j(2 kappa y), k_0 = sin, k_1 = cos
+     * (the paper's physical amplitude is 1, so its additive perturbation is
+     * relative to u0 here). */
+    UQ_INIT_TGV_HARMONIC = 1
+} uq_init;
 
 /* One independent uniform input U(lo, hi) (Sec. "Distribution and
  * polynomial basis"); its reference variable xi on [-1, 1] maps to
@@ -150,6 +172,7 @@ typedef struct {
     uint64_t seed;     /* MC / LHS: generator seed                          */
     int32_t layout;    /* uq_layout                                         */
     int32_t level;     /* SMOLYAK_CC: sparse-grid level                     */
+    int32_t init;      /* uq_init (vortex only)                             */
 } uq_problem;
 
 /* Device context. `stream` is a hipStream_t (e.g. torch's current stream,
@@ -182,7 +205,9 @@ typedef enum {
     UQ_QOI_CD = 2,
     UQ_QOI_CL = 3,
     /* density field [ny][nx], 0 at solid nodes */
-    UQ_QOI_RHO = 4
+    UQ_QOI_RHO = 4,
+    /* speed field |u| [ny][nx], 0 at solid nodes */
+    UQ_QOI_SPEED = 5
 } uq_qoi;
 
 /* Statistics of one QoI over the samples, caller-owned host buffers; any
@@ -351,6 +376,25 @@ uq_status uq_server_wait(uq_server *s, uint64_t ticket, double timeout_s, uq_res
 uq_status uq_server_get_stats(uq_server *s, uq_server_stats *out);
 /* Stop the loop, abandon queued and live jobs, release all device memory. */
 void uq_server_destroy(uq_server *s);
+
+/* 1-Wasserstein distance between the numerical statistical solutions of two
+ * jobs at their current steps (Sec. "Taylor--Green vortex flow with
+ * four-dimensional uncertain initial velocity perturbation", Eq. of W_1):
+ * the law of a field QoI of job a (every value of every sample, value o of
+ * sample j carrying weight a_j / n_out, each value multiplied by scale_a)
+ * against the same for job b, W_1 = integral |F_a - F_b|. Both jobs must be
+ * on the same device; the result is computed there (sort, prefix sums,
+ * quantile overlap, compensated sum) on job a's stream. qoi must be a field
+ * (VEL, RHO or SPEED). Blocking. */
+uq_status uq_wasserstein1(uq_job *a, uq_job *b, int32_t qoi, double scale_a, double scale_b, double *w1);
+
+/* Lattice units of the paper's four-dimensional vortex case (Table
+ * tab:simulation_parameters): for n nodes per side, Mach number Ma and
+ * Reynolds number Re (physical velocity 1, viscosity 1/Re, domain 2 pi):
+ * dx = 2 pi/(n-1), u_lat = Ma/sqrt(3), dt = dx u_lat, nu_lat = dt/(Re dx^2),
+ * tau = 3 nu_lat + 1/2. Host only. */
+uq_status uq_tgv_units(int32_t n, double Ma, double Re, double *nu_lat, double *u_lat, double *dx, double *dt,
+                       double *tau);
 
 /* Host-only helpers (no device needed): the job's sample set and basis,
  * for callers that want the rule without creating a job.

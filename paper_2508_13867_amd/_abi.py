@@ -21,10 +21,12 @@ STATUS_NAMES = {0: "UQ_OK", 1: "UQ_EINVAL", 2: "UQ_ENOMEM", 3: "UQ_EAGAIN", 4: "
 PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}
 GEOMETRY = {"tgv": 0, "channel": 1}
 XBC = {0: 0, 1: 1, 2: 2, "zouhe": 0, "walls": 1, "periodic": 2}
-TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5}
+TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5, "zeta00": 6, "zeta01": 7,
+          "zeta10": 8, "zeta11": 9}
+INIT = {"tgv": 0, "harmonic": 1}
 RULE = {"gl": 0, "mc": 1, "smolyak": 2, "halton": 3, "lhs": 4}
 LAYOUT = {"auto": 0, "aa": 1, "ab": 2}
-QOI = {"ke": 0, "vel": 1, "cd": 2, "cl": 3, "rho": 4}
+QOI = {"ke": 0, "vel": 1, "cd": 2, "cl": 3, "rho": 4, "speed": 5}
 MAX_DIMS = 8
 
 
@@ -45,7 +47,7 @@ class Problem(C.Structure):
         ("u_peak", C.c_double), ("D", C.c_int32), ("cx", C.c_int32), ("cy", C.c_int32), ("xbc", C.c_int32),
         ("ramp", C.c_int64), ("n_dists", C.c_int32), ("dists", Dist * MAX_DIMS), ("rule", C.c_int32),
         ("n_per_dim", C.c_int32), ("order", C.c_int32), ("mc_n", C.c_int64), ("seed", C.c_uint64),
-        ("layout", C.c_int32), ("level", C.c_int32),
+        ("layout", C.c_int32), ("level", C.c_int32), ("init", C.c_int32),
     ]
 
 
@@ -120,6 +122,8 @@ SIGNATURES = {
     "uq_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
     "uq_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
     "uq_server_destroy": (None, [_P]),
+    "uq_wasserstein1": (C.c_int, [_P, _P, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double)]),
+    "uq_tgv_units": (C.c_int, [C.c_int32, C.c_double, C.c_double] + [C.POINTER(C.c_double)] * 5),
     "uq_rule_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "uq_rule_points": (C.c_int, [C.POINTER(Problem), _P, _P, _P, _P]),
 }
@@ -180,6 +184,7 @@ def make_problem(spec: dict) -> Problem:
     p.seed = int(r.get("seed", 123456))
     p.layout = LAYOUT[spec.get("layout", "auto")]
     p.level = int(r.get("level", 0))
+    p.init = INIT[spec.get("init", "tgv")]
     return p
 
 
@@ -242,6 +247,20 @@ def torch_device(device: int = 0, stream=None, allocator=True):
         dev.free = FREE_FN()
     dev.ctx = None
     return dev, keep
+
+
+def tgv_units(n: int, Ma: float, Re: float) -> dict:
+    """Lattice units of the four-dimensional vortex case (uq_tgv_units)."""
+    v = [C.c_double() for _ in range(5)]
+    check(lib().uq_tgv_units(int(n), float(Ma), float(Re), *[C.byref(x) for x in v]))
+    return dict(zip(("nu", "u_lat", "dx", "dt", "tau"), (x.value for x in v)))
+
+
+def wasserstein1(a: "Job", b: "Job", qoi: str = "speed", scale_a: float = 1.0, scale_b: float = 1.0) -> float:
+    """uq_wasserstein1: W_1 between the laws of a field QoI of two jobs."""
+    w = C.c_double()
+    check(lib().uq_wasserstein1(a.h, b.h, QOI[qoi], float(scale_a), float(scale_b), C.byref(w)))
+    return w.value
 
 
 def autotune(spec: dict, steps: int = 40, device: int = 0) -> dict:

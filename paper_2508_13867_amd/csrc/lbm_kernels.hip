@@ -425,13 +425,28 @@ __global__ __launch_bounds__(256) void k_init(JobDev j) {
             double f[9];
             for (int i = 0; i < 9; ++i) f[i] = 0.0;
             if (x < j.nx && j.geom == 0) {
-                // Taylor-Green vortex (Eqs. TGV_vel, TGV_press at t = 0), rho = 1 + 3p
-                const double kx = 2.0 * M_PI / j.nx, ky = 2.0 * M_PI / j.ny;
-                const double ax = kx * x + sd.phase_x, ay = ky * y + sd.phase_y;
-                const double ux = -sd.u0 * cos(ax) * sin(ay);
-                const double uy = sd.u0 * sin(ax) * cos(ay);
-                const double p = -0.25 * sd.u0 * sd.u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
-                const double drho = 3.0 * p, rho = 1.0 + drho;
+                double ux, uy, p;
+                if (j.init == UQ_INIT_TGV_HARMONIC) {
+                    // perturbed vortex (Eq. taylorGreen), two periods per side,
+                    // amplitude u0 (1 + eps) with first-order harmonics of 2 kappa
+                    const double kx = 4.0 * M_PI / j.nx, ky = 4.0 * M_PI / j.ny;
+                    const double ax = kx * x, ay = ky * y;
+                    const double sx = sin(2.0 * ax), cx = cos(2.0 * ax), sy = sin(2.0 * ay), cy = cos(2.0 * ay);
+                    const double eps = 0.25 * (sd.zeta[0] * sx * sy + sd.zeta[1] * sx * cy + sd.zeta[2] * cx * sy +
+                                               sd.zeta[3] * cx * cy);
+                    const double uR = sd.u0 * (1.0 + eps);
+                    ux = -uR * cos(ax) * sin(ay);
+                    uy = uR * sin(ax) * cos(ay);
+                    p = -0.25 * uR * uR * (cos(2.0 * ax) + cos(2.0 * ay));
+                } else {
+                    // Taylor-Green vortex (Eqs. TGV_vel, TGV_press at t = 0)
+                    const double kx = 2.0 * M_PI / j.nx, ky = 2.0 * M_PI / j.ny;
+                    const double ax = kx * x + sd.phase_x, ay = ky * y + sd.phase_y;
+                    ux = -sd.u0 * cos(ax) * sin(ay);
+                    uy = sd.u0 * sin(ax) * cos(ay);
+                    p = -0.25 * sd.u0 * sd.u0 * (cos(2.0 * ax) + (kx / ky) * (kx / ky) * cos(2.0 * ay));
+                }
+                const double drho = 3.0 * p, rho = 1.0 + drho;  // rho = 1 + p/cs2
                 const double uu = 1.5 * (ux * ux + uy * uy);
                 for (int i = 0; i < 9; ++i) {
                     const double cu = CXd[i] * ux + CYd[i] * uy;
@@ -516,7 +531,7 @@ __global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
     }
 }
 
-// Per-sample fields: out[s][3][ny][nx] = ux, uy, rho (0 at solid nodes).
+// Per-sample fields: out[s][4][ny][nx] = ux, uy, rho, |u| (0 at solid nodes).
 template <int P, bool CHANNEL, int MODE>
 __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out) {
     using PR = Prec<P>;
@@ -526,7 +541,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
     for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
     const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
     const double u_peak = j.smp[smp].u_peak;
-    double *o = out + smp * 3 * cells;
+    double *o = out + smp * 4 * cells;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
         uint32_t m = 0;
@@ -536,6 +551,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
                 o[c] = 0.0;
                 o[cells + c] = 0.0;
                 o[2 * cells + c] = 0.0;
+                o[3 * cells + c] = 0.0;
                 continue;
             }
         }
@@ -546,6 +562,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
         o[c] = (double)ux;
         o[cells + c] = (double)uy;
         o[2 * cells + c] = 1.0 + (double)drho;
+        o[3 * cells + c] = sqrt((double)ux * (double)ux + (double)uy * (double)uy);
     }
     }
 }

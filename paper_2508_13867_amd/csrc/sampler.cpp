@@ -34,6 +34,9 @@ uq_status validate_problem(const uq_problem &p) {
     if (p.geometry == UQ_GEOM_CHANNEL && p.ny < 3) return fail(UQ_EINVAL, "channel needs ny >= 3");
     if ((int64_t)p.nx * p.ny > (int64_t)1 << 30) return fail(UQ_EINVAL, "lattice too large");
     if (p.n_dists < 0 || p.n_dists > UQ_MAX_DIMS) return fail(UQ_EINVAL, "n_dists out of range");
+    if (p.init != UQ_INIT_TGV && p.init != UQ_INIT_TGV_HARMONIC) return fail(UQ_EINVAL, "unknown init");
+    if (p.init == UQ_INIT_TGV_HARMONIC && p.geometry != UQ_GEOM_TGV)
+        return fail(UQ_EINVAL, "the harmonic initial field is a vortex option");
     if (p.geometry == UQ_GEOM_CHANNEL) {
         if (p.xbc < UQ_XBC_ZOUHE || p.xbc > UQ_XBC_PERIODIC) return fail(UQ_EINVAL, "unknown xbc");
         if (p.D < 0) return fail(UQ_EINVAL, "D must be >= 0");
@@ -41,7 +44,9 @@ uq_status validate_problem(const uq_problem &p) {
     }
     for (int k = 0; k < p.n_dists; ++k) {
         const uq_dist &q = p.dists[k];
-        if (q.target < UQ_T_NU || q.target > UQ_T_U_PEAK) return fail(UQ_EINVAL, "unknown target");
+        if (q.target < UQ_T_NU || q.target > UQ_T_ZETA11) return fail(UQ_EINVAL, "unknown target");
+        if (q.target >= UQ_T_ZETA00 && !(p.geometry == UQ_GEOM_TGV && p.init == UQ_INIT_TGV_HARMONIC))
+            return fail(UQ_EINVAL, "perturbation amplitudes apply to the harmonic vortex only");
         if (!(q.hi >= q.lo) || !std::isfinite(q.lo) || !std::isfinite(q.hi))
             return fail(UQ_EINVAL, "distribution needs finite lo <= hi");
         bool tgv_only = q.target == UQ_T_U0 || q.target == UQ_T_PHASE_X || q.target == UQ_T_PHASE_Y;
@@ -362,6 +367,7 @@ void map_inputs(const uq_problem &p, const double *xi, SampleInputs &o) {
     o.phase_x = p.phase_x;
     o.phase_y = p.phase_y;
     o.u_peak = p.u_peak;
+    for (int k = 0; k < 4; ++k) o.zeta[k] = 0.0;
     bool has_re = false;
     double re = 0.0;
     for (int k = 0; k < p.n_dists; ++k) {
@@ -374,6 +380,10 @@ void map_inputs(const uq_problem &p, const double *xi, SampleInputs &o) {
             case UQ_T_PHASE_Y: o.phase_y = v; break;
             case UQ_T_RE: has_re = true; re = v; break;
             case UQ_T_U_PEAK: o.u_peak = v; break;
+            case UQ_T_ZETA00: o.zeta[0] = v; break;
+            case UQ_T_ZETA01: o.zeta[1] = v; break;
+            case UQ_T_ZETA10: o.zeta[2] = v; break;
+            case UQ_T_ZETA11: o.zeta[3] = v; break;
         }
     }
     // Re from the peak inflow velocity and the diameter (cylinder section)
@@ -401,5 +411,21 @@ extern "C" uq_status uq_rule_points(const uq_problem *p, double *xi, double *a, 
     if (a) std::memcpy(a, r.a.data(), sizeof(double) * r.a.size());
     if (alpha) std::memcpy(alpha, r.alpha.data(), sizeof(int32_t) * r.alpha.size());
     if (phi) std::memcpy(phi, r.phi.data(), sizeof(double) * r.phi.size());
+    return UQ_OK;
+}
+
+extern "C" uq_status uq_tgv_units(int32_t n, double Ma, double Re, double *nu_lat, double *u_lat, double *dx,
+                                  double *dt, double *tau) {
+    if (n < 2 || !(Ma > 0) || !(Re > 0)) return uqi::fail(UQ_EINVAL, "need n >= 2, Ma > 0, Re > 0");
+    // physical box of side 2 pi resolved by n nodes (Table tab:simulation_parameters)
+    const double h = 2.0 * M_PI / (double)(n - 1);
+    const double ul = Ma / std::sqrt(3.0);
+    const double k = h * ul;                 // time step: dx times the lattice velocity
+    const double nl = (1.0 / Re) * k / (h * h);
+    if (nu_lat) *nu_lat = nl;
+    if (u_lat) *u_lat = ul;
+    if (dx) *dx = h;
+    if (dt) *dt = k;
+    if (tau) *tau = 3.0 * nl + 0.5;
     return UQ_OK;
 }

@@ -34,6 +34,18 @@ void *Job::dalloc(size_t bytes) {
     return p;
 }
 
+void Job::dfree(void *p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+        if (allocs[i] == p) {
+            if (dev.free)
+                dev.free(p, dev.ctx);
+            else
+                (void)hipFree(p);
+            allocs.erase(allocs.begin() + (long)i);
+            return;
+        }
+}
+
 void Job::dfree_all() {
     for (void *p : allocs) {
         if (dev.free)
@@ -120,7 +132,7 @@ uq_status Job::ensure_stats_buffers(int64_t n_out_max) {
 uq_status Job::ensure_fields() {
     if (!d_fields) {
         const int64_t cells = (int64_t)p.nx * p.ny;
-        d_fields = (double *)dalloc(sizeof(double) * 3 * cells * S);
+        d_fields = (double *)dalloc(sizeof(double) * 4 * cells * S);
         if (!d_fields) return fail(UQ_ENOMEM, "out of device memory for per-sample fields");
     }
     return UQ_OK;
@@ -170,6 +182,7 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
         d.phase_x = in.phase_x;
         d.phase_y = in.phase_y;
         d.u_peak = in.u_peak;
+        for (int k = 0; k < 4; ++k) d.zeta[k] = in.zeta[k];
         smp[(size_t)s] = d;
         const double uc = P.geometry == UQ_GEOM_TGV ? std::fabs(in.u0) : 1.5 * std::fabs(in.u_peak);
         umax = std::max(umax, uc);
@@ -261,6 +274,7 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
     const double uref = P.geometry == UQ_GEOM_TGV ? P.u0 : P.u_peak;
     jd.ke_norm = uref != 0.0 ? 2.0 / ((double)P.nx * P.ny * uref * uref) : 1.0;
     jd.D = P.D;
+    jd.init = P.init;
     j->plane_pad = (int)pad;
 
     UQ_HIP_TRY(launch_init(jd, j->stream));
@@ -338,7 +352,8 @@ namespace uqi {
 uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld) {
     const uq_problem &P = p;
     const int64_t cells = (int64_t)P.nx * P.ny;
-    uq_status st = ensure_stats_buffers(qoi == UQ_QOI_VEL ? 2 * cells : (qoi == UQ_QOI_RHO ? cells : 1));
+    const bool field1 = qoi == UQ_QOI_RHO || qoi == UQ_QOI_SPEED;
+    uq_status st = ensure_stats_buffers(qoi == UQ_QOI_VEL ? 2 * cells : (field1 ? cells : 1));
     if (st != UQ_OK) return st;
     UQ_HIP_TRY(launch_qoi_scalars(jd, t, d_qoi, stream));
     std::vector<double> h((size_t)(4 * S));
@@ -356,13 +371,13 @@ uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t 
         *ld = 1;
         return UQ_OK;
     }
-    if (qoi == UQ_QOI_VEL || qoi == UQ_QOI_RHO) {
+    if (qoi == UQ_QOI_VEL || field1) {
         st = ensure_fields();
         if (st != UQ_OK) return st;
         UQ_HIP_TRY(launch_fields(jd, t, d_fields, stream));
-        *M = qoi == UQ_QOI_VEL ? d_fields : d_fields + 2 * cells;
+        *M = qoi == UQ_QOI_VEL ? d_fields : d_fields + (qoi == UQ_QOI_RHO ? 2 : 3) * cells;
         *n_out = qoi == UQ_QOI_VEL ? 2 * cells : cells;
-        *ld = 3 * cells;
+        *ld = 4 * cells;
         return UQ_OK;
     }
     return fail(UQ_EINVAL, "unknown QoI");
@@ -374,8 +389,8 @@ extern "C" uq_status uq_qoi_samples(uq_job *j, int32_t qoi, double *out, int64_t
     if (!j) return fail(UQ_EINVAL, "null job");
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
     const int64_t cells = (int64_t)j->p.nx * j->p.ny;
-    int64_t n = qoi == UQ_QOI_VEL ? 2 * cells : (qoi == UQ_QOI_RHO ? cells : 1);
-    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_RHO) return fail(UQ_EINVAL, "unknown QoI");
+    int64_t n = qoi == UQ_QOI_VEL ? 2 * cells : ((qoi == UQ_QOI_RHO || qoi == UQ_QOI_SPEED) ? cells : 1);
+    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_SPEED) return fail(UQ_EINVAL, "unknown QoI");
     if (n_out) *n_out = n;
     if (!out) return UQ_OK;
     const double *M;
@@ -393,7 +408,7 @@ extern "C" uq_status uq_qoi_samples(uq_job *j, int32_t qoi, double *out, int64_t
 extern "C" uq_status uq_moments(uq_job *j, int32_t qoi, uq_moments_out *out) {
     if (!j || !out) return fail(UQ_EINVAL, "null argument");
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
-    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_RHO) return fail(UQ_EINVAL, "unknown QoI");
+    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_SPEED) return fail(UQ_EINVAL, "unknown QoI");
     const double *M;
     int64_t n, ld;
     uq_status st = j->enter();

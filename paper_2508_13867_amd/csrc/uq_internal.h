@@ -39,18 +39,20 @@ uq_status build_rule(const uq_problem &p, Rule &r);
 // Per-sample solver inputs after mapping the reference variables.
 struct SampleInputs {
     double nu, u0, phase_x, phase_y, u_peak;
+    double zeta[4];
 };
 void map_inputs(const uq_problem &p, const double *xi_row, SampleInputs &out);
 
 // ------------------------------------------------------------------ device-side layout
-// Per-sample parameters read by the kernels (one 64-byte record per sample).
+// Per-sample parameters read by the kernels (one 128-byte record per sample).
 struct alignas(64) SampleDev {
     double omega;   // 1/tau
     double u0;      // TGV amplitude
     double phase_x; // TGV phases
     double phase_y;
     double u_peak;  // channel peak inflow
-    double pad[3];
+    double zeta[4]; // harmonic perturbation amplitudes (UQ_INIT_TGV_HARMONIC)
+    double pad[7];
 };
 
 // Per-node boundary mask of the channel (one 32-bit word per node).
@@ -85,6 +87,8 @@ struct JobDev {
     double ke_norm;         // 2/(nx ny u0^2)
     int32_t D;
     int32_t layout;         // UQ_LAYOUT_AA or UQ_LAYOUT_AB
+    int32_t init;           // uq_init (vortex)
+    int32_t pad1;
 };
 
 // A job in the continuous-batching table (device memory).
@@ -122,7 +126,7 @@ hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s);
 hipError_t launch_qoi_scalars(const JobDev &j, int64_t t, double *out, hipStream_t s);
 // M[s] = KE, C_D or C_L of sample s from the scalars above
 hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s);
-// per-sample fields at time t: out[S][3][ny][nx] = {ux, uy, rho}
+// per-sample fields at time t: out[S][4][ny][nx] = {ux, uy, rho, |u|}
 hipError_t launch_fields(const JobDev &j, int64_t t, double *out, hipStream_t s);
 // unshifted double populations of one sample in natural order
 hipError_t launch_export(const JobDev &j, int64_t t, int64_t sample, double *out, hipStream_t s);

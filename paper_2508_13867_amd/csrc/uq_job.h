@@ -51,6 +51,7 @@ struct Job {
 
     ~Job();
     void *dalloc(size_t bytes);
+    void dfree(void *p);  // release one block from dalloc
     void dfree_all();
     uq_status ensure_stats_buffers(int64_t n_out_max);
     uq_status ensure_fields();

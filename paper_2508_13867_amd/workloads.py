@@ -112,3 +112,19 @@ TGV_SMOLYAK = dict(
     u0=0.02, nu=0.005, dists=FOUR_D_INPUTS, rule=dict(kind="smolyak", level=3, order=3),
 )
 WORKLOADS[TGV_SMOLYAK["name"]] = TGV_SMOLYAK
+
+
+# Four-dimensional perturbed vortex (Sec. "Taylor--Green vortex flow with
+# four-dimensional uncertain initial velocity perturbation"): zeta_ij ~
+# U(-0.025, 0.025) i.i.d., N = n Monte Carlo samples, Ma = 1.6 / n,
+# Re = 40 n, lattice units of Table tab:simulation_parameters, T_max = 100.
+ZETA_INPUTS = [("zeta00", -0.025, 0.025), ("zeta01", -0.025, 0.025), ("zeta10", -0.025, 0.025),
+               ("zeta11", -0.025, 0.025)]
+TGV4D_T_MAX = 100.0
+
+
+def tgv4d(n, units, precision="fp32", seed=SEED):
+    """The perturbed-vortex problem at resolution n; units is the result of
+    tgv_units(n, 1.6 / n, 40 n) (lattice viscosity and velocity)."""
+    return dict(name=f"tgv4d_{n}", geometry="tgv", init="harmonic", precision=precision, nx=n, ny=n, steps=0,
+                u0=units["u_lat"], nu=units["nu"], dists=ZETA_INPUTS, rule=dict(kind="mc", N=n, seed=seed + n))

@@ -103,3 +103,15 @@ def test_invalid_problems_are_rejected(bad):
         A.rule_points(spec)
     assert e.value.status == A.UQ_EINVAL
     assert A.lib().uq_last_error().decode()
+
+
+def test_tgv_units_match_the_papers_table():
+    # Table tab:simulation_parameters (values as printed, 6 decimals)
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table1_tgv_units.txt"), comments="#")
+    for N, n, Ma, Re, tau, dx, dt in rows:
+        u = A.tgv_units(int(n), Ma, Re)
+        assert abs(u["tau"] - tau) < 1e-6 and abs(u["dx"] - dx) < 1e-6 and abs(u["dt"] - dt) < 1e-6, n
+        assert abs(u["u_lat"] - Ma / np.sqrt(3.0)) < 1e-16
+        assert abs(u["tau"] - (3 * u["nu"] + 0.5)) < 1e-15
+    with pytest.raises(A.UQError):
+        A.tgv_units(1, 0.1, 100)
