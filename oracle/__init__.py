@@ -74,6 +74,7 @@ def _declare(L):
     L.oracle_channel_run.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                      C.c_double, C.c_long, C.c_long, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
                                      _dp]
+    L.oracle_channel_run_opts.argtypes = [C.POINTER(ChannelOpts), _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.oracle_cylinder_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
     L.oracle_cylinder_nodes.restype = C.c_long
     L.oracle_tgv_harmonic_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_long, C.c_double,
@@ -298,6 +299,41 @@ def channel_run(nx, ny, nu, u_peak, steps, D=0, cx=0, cy=0, ramp=0, xbc=0, want_
     return out
 
 
+class ChannelOpts(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("xbc", C.c_int), ("cyl", C.c_int), ("D", C.c_int),
+                ("cx", C.c_int), ("cy", C.c_int), ("ccx", C.c_double), ("ccy", C.c_double), ("R", C.c_double),
+                ("q_lo", C.c_double), ("q_hi", C.c_double), ("q_fix", C.c_double), ("nu", C.c_double),
+                ("u_peak", C.c_double), ("ramp", C.c_long), ("steps", C.c_long), ("ux_init", C.c_double),
+                ("force_ref", C.c_int)]
+
+
+def channel_run_opts(nx, ny, nu, u_peak, steps, xbc=0, cyl=0, D=0, cx=0, cy=0, ccx=0.0, ccy=0.0, R=0.0,
+                     q_lo=-1.0, q_hi=-1.0, q_fix=-1.0, ramp=0, ux_init=0.0, force_ref=0, want_f=False, want_q=False):
+    """Channel run with every option of the oracle: cyl = 1 is the exact
+    circle (ccx, ccy, R) with interpolated bounce-back; q_lo / q_hi >= 0
+    place the straight walls at y = -q_lo and y = ny - 1 + q_hi with the
+    same interpolated rule; xbc = 3 is the finite-difference inlet/outlet."""
+    o = ChannelOpts(nx=nx, ny=ny, xbc=xbc, cyl=cyl, D=D, cx=cx, cy=cy, ccx=ccx, ccy=ccy, R=R, q_lo=q_lo,
+                    q_hi=q_hi, q_fix=q_fix, nu=nu, u_peak=u_peak, ramp=ramp, steps=steps, ux_init=ux_init,
+                    force_ref=force_ref)
+    n = nx * ny
+    rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
+    f = np.zeros(9 * n) if want_f else None
+    q = np.zeros(9 * n) if want_q else None
+    force, cdcl, wall = np.zeros(2), np.zeros(2), np.zeros(2)
+    rc = lib().oracle_channel_run_opts(C.byref(o), _p(f), _p(rho), _p(ux), _p(uy), _p(force), _p(cdcl), _p(wall),
+                                       _p(q))
+    if rc != 0:
+        raise ValueError("invalid channel parameters")
+    out = {"rho": rho.reshape(ny, nx), "ux": ux.reshape(ny, nx), "uy": uy.reshape(ny, nx),
+           "force": force, "cd": cdcl[0], "cl": cdcl[1], "wall_force": wall}
+    if want_f:
+        out["f"] = f.reshape(9, ny, nx)
+    if want_q:
+        out["q"] = q.reshape(9, ny, nx)
+    return out
+
+
 def cylinder_nodes(nx, ny, D, cx, cy):
     return lib().oracle_cylinder_nodes(nx, ny, D, cx, cy)
 
@@ -328,8 +364,9 @@ def sample_set(problem):
 def sample_params(problem, xi_row):
     """Deterministic inputs of one sample: each uncertain input is the affine
     image (lo+hi)/2 + (hi-lo)/2 xi of its reference variable; a Reynolds-number
-    input sets nu = u_peak_nominal D / Re (the cylinder section's definition
-    of Re with the peak inflow velocity)."""
+    input sets nu = U D / Re (the cylinder section's definition of Re), U the
+    nominal peak inflow velocity or, with force_ref 'mean', its mean 2/3 of
+    it, D the diameter."""
     p = {k: problem.get(k, 0.0) for k in _TARGETS}
     p["u_peak"] = problem.get("u_peak", 0.0)
     for (target, lo, hi), z in zip(problem["dists"], xi_row):
@@ -337,7 +374,9 @@ def sample_params(problem, xi_row):
             raise ValueError(target)
         p[target] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * z
     if any(t == "re" for t, _, _ in problem["dists"]):
-        p["nu"] = problem["u_peak"] * problem["D"] / p["re"]
+        U = problem["u_peak"] * (2.0 / 3.0 if problem.get("force_ref", "peak") == "mean" else 1.0)
+        dia = problem["cyl_d"] if problem.get("cyl_bc", "halfway") == "bouzidi" else problem["D"]
+        p["nu"] = U * dia / p["re"]
     return p
 
 
@@ -355,9 +394,16 @@ def solve_sample(problem, params, steps=None):
         return {"ke": r["ke"], "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"],
                 "speed": np.sqrt(r["ux"] ** 2 + r["uy"] ** 2)}
     if problem["geometry"] == "channel":
-        xbc = {"zouhe": 0, "walls": 1, "periodic": 2}.get(problem.get("xbc", 0), problem.get("xbc", 0))
-        r = channel_run(nx, ny, params["nu"], params["u_peak"], steps, D=problem.get("D", 0),
-                        cx=problem.get("cx", 0), cy=problem.get("cy", 0), ramp=problem.get("ramp", 0), xbc=xbc)
+        xbc = {"zouhe": 0, "walls": 1, "periodic": 2, "interp": 3}.get(problem.get("xbc", 0), problem.get("xbc", 0))
+        fref = 1 if problem.get("force_ref", "peak") == "mean" else 0
+        if problem.get("cyl_bc", "halfway") == "bouzidi":
+            r = channel_run_opts(nx, ny, params["nu"], params["u_peak"], steps, xbc=xbc, cyl=1,
+                                 ccx=problem["cyl_x"], ccy=problem["cyl_y"], R=0.5 * problem["cyl_d"],
+                                 ramp=problem.get("ramp", 0), force_ref=fref)
+        else:
+            r = channel_run_opts(nx, ny, params["nu"], params["u_peak"], steps, xbc=xbc, D=problem.get("D", 0),
+                                 cx=problem.get("cx", 0), cy=problem.get("cy", 0), ramp=problem.get("ramp", 0),
+                                 force_ref=fref)
         return {"cd": r["cd"], "cl": r["cl"], "fx": r["force"][0], "fy": r["force"][1],
                 "vel": np.stack([r["ux"], r["uy"]]), "rho": r["rho"], "speed": np.sqrt(r["ux"] ** 2 + r["uy"] ** 2)}
     raise ValueError(problem["geometry"])

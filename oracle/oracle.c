@@ -461,45 +461,103 @@ int oracle_tgv_harmonic_run(int nx, int ny, double nu, double u0, const double *
 }
 
 /* ------------------------------------------------------------------------ */
-/* Channel flow past a cylinder, one deterministic sample. The paper's own
- * set-up (Sec. "Flow past a circular cylinder with uncertain inlet
- * velocity") uses interpolated and curved boundaries; this is the simpler
- * variant with the same structure:
- *   - channel of nx x ny nodes, walls half-way at y = -1/2 and y = ny - 1/2
- *     (so H = ny), no-slip by half-way bounce-back;
- *   - solid cylinder nodes: 4((x-cx)^2 + (y-cy)^2) <= D^2 (integer test);
- *     half-way bounce-back on every link into it;
+/* Channel flow past a cylinder, one deterministic sample (Sec. "Flow past a
+ * circular cylinder with uncertain inlet velocity").
+ *   - channel of nx x ny nodes; no-slip walls below row 0 and above row
+ *     ny-1. By default half-way (walls at y = -1/2 and y = ny - 1/2, so
+ *     H = ny) with half-way bounce-back; optionally at y = -q_lo and
+ *     y = ny - 1 + q_hi with the interpolated bounce-back below (used by
+ *     tests of that scheme on a straight wall);
+ *   - cylinder, two variants: (0) solid nodes 4((x-cx)^2 + (y-cy)^2) <= D^2
+ *     (integer test) with half-way bounce-back on every link into it; (1)
+ *     the exact circle of centre (ccx, ccy) and radius R (solid iff
+ *     (x-ccx)^2 + (y-ccy)^2 <= R^2) with the linear interpolated
+ *     bounce-back of Bouzidi, Firdaouss and Lallemand (Phys. Fluids 13,
+ *     3452, 2001), the second-order curved-wall scheme the paper uses;
  *   - x boundary mode xbc: 0 = velocity inlet at x = 0 and pressure outlet
- *     (rho = 1) at x = nx-1, both by Zou & He (Phys. Fluids 9, 1591, 1997)
- *     on every row of the open columns; at the two corner nodes of a column
- *     the populations arriving from beyond the wall are filled by
- *     bounce-back first, and Zou-He then completes the rest;
- *     1 = solid walls half-way at x = -1/2 and x = nx - 1/2; 2 = periodic;
- *   - parabolic inlet u_x(y) = s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2, u_y = 0,
- *     with the start-up ramp s(t) = sin^2(pi t/(2 T_r)) for t < T_r, else 1
- *     (the paper ramps the inflow without giving the form);
+ *     (rho = 1) at x = nx-1 by Zou & He (Phys. Fluids 9, 1591, 1997) on every
+ *     row of the open columns (at the corner nodes the populations arriving
+ *     from beyond the wall come from the wall rule first, and Zou-He
+ *     completes the rest); 1 = solid walls half-way at x = -1/2 and
+ *     x = nx - 1/2; 2 = periodic; 3 = the same inlet and outlet by the
+ *     finite-difference velocity-gradient reconstruction of Latt et al.
+ *     (Phys. Rev. E 77, 056703, 2008), the paper's interpolated boundaries:
+ *     every population of an open-column node is rebuilt as equilibrium plus
+ *     the first-order non-equilibrium part -w_i rho tau/cs2 Q_i : grad u,
+ *     Q_i = c_i c_i - cs2 I, with grad u from second-order finite
+ *     differences (one-sided into the fluid across the column, central along
+ *     it, one-sided at its ends); the inlet takes the prescribed velocity
+ *     and rho from the known populations, the outlet rho = 1, u_y = 0 and
+ *     u_x from the known populations;
+ *   - parabolic inlet u_x(y) = s(t) 4 u_peak (y - y_lo)(y_hi - y)/H^2,
+ *     u_y = 0, between the wall positions y_lo, y_hi (H = y_hi - y_lo), with
+ *     the start-up ramp s(t) = sin^2(pi t/(2 T_r)) for t < T_r, else 1 (the
+ *     paper ramps the inflow without giving the form);
  *   - initial state: equilibrium at rho = 1, u = 0 (Sec. cylinder,
  *     equilibrium initialisation; s(0) = 0); tests may start from a uniform
  *     u = (ux_init, 0) instead;
- *   - forces by momentum exchange on the cylinder links,
- *     F = sum_{fluid x, i: x + c_i in cylinder} 2 c_i f*_i(x, t), from the
- *     post-collision populations of step t (Ladd 1994), a lattice evaluation
- *     of the surface integrals Eqs. dragForce/liftForce;
- *   - C_D = 2 F_x/(rho0 u_peak^2 D), C_L = 2 F_y/(rho0 u_peak^2 D) with
- *     rho0 = 1 and the sample's peak inlet velocity.                        */
+ *   - forces by momentum exchange on the cylinder links (Ladd 1994; for
+ *     interpolated links Mei et al., J. Comput. Phys. 175, 2002):
+ *     F = sum_{fluid x, k: x + c_k in cylinder} c_k (f*_k(x, t) +
+ *     f_opp(k)(x, t+1)), with f* the collision of the final state and
+ *     f_opp(k)(x, t+1) what the wall rule returns from it (half-way:
+ *     f*_k(x, t), so F = sum 2 c_k f*_k), a lattice evaluation of the surface
+ *     integrals Eqs. dragForce/liftForce;
+ *   - C_D = 2 F_x/(rho0 U^2 D), C_L = 2 F_y/(rho0 U^2 D), rho0 = 1, U the
+ *     sample's peak inlet velocity (force_ref 0) or its mean 2/3 u_peak
+ *     (force_ref 1), D the diameter (2R for the circle).                     */
 
 typedef struct {
     int nx, ny, xbc;
-    int D, cx, cy;
-    double tau, u_peak;
-    long ramp;
-    unsigned char *solid; /* [ny][nx] cylinder mask */
+    int cyl;            /* 0: integer mask; 1: exact circle, interpolated */
+    int D, cx, cy;      /* integer cylinder (D = 0: none)                 */
+    double ccx, ccy, R; /* exact circle                                   */
+    double q_lo, q_hi;  /* < 0: half-way walls                            */
+    double q_fix;       /* >= 0: every link fraction replaced (tests)     */
+    double nu, u_peak;
+    long ramp, steps;
+    double ux_init;
+    int force_ref;
+} oracle_channel_opts;
+
+typedef struct {
+    oracle_channel_opts o;
+    int nx, ny;
+    double tau, y_lo, y_hi;
+    unsigned char *solid; /* [ny][nx] */
+    double *q;            /* [9][ny][nx] link fraction of pull direction i, 0 = none */
 } channel;
 
-static int ch_cyl(const channel *c, int x, int y) {
-    if (c->D <= 0) return 0;
-    long dx = x - c->cx, dy = y - c->cy;
-    return 4 * (dx * dx + dy * dy) <= (long)c->D * c->D;
+static int in_cylinder(const channel *c, double x, double y) {
+    if (c->o.cyl == 1) {
+        double dx = x - c->o.ccx, dy = y - c->o.ccy;
+        return dx * dx + dy * dy <= c->o.R * c->o.R;
+    }
+    if (c->o.D <= 0) return 0;
+    long dx = (long)x - c->o.cx, dy = (long)y - c->o.cy;
+    return 4 * (dx * dx + dy * dy) <= (long)c->o.D * c->o.D;
+}
+
+/* point inside the solid of the interpolated geometry (circle or walls)  */
+static int in_solid_exact(const channel *c, double x, double y) {
+    if (c->o.q_lo >= 0.0 && (y < c->y_lo || y > c->y_hi)) return 1;
+    return c->o.cyl == 1 && in_cylinder(c, x, y);
+}
+
+/* fraction q in (0, 1] of the link from fluid node (x, y) towards
+ * (x - CX[i], y - CY[i]) at which it enters the solid, by bisection on the
+ * segment (one crossing: the solid pieces are convex).                      */
+static double link_fraction(const channel *c, int x, int y, int i) {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (in_solid_exact(c, x - mid * CX[i], y - mid * CY[i]))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 static double ramp_factor(long t, long T) {
@@ -510,30 +568,47 @@ static double ramp_factor(long t, long T) {
 }
 
 static double inlet_ux(const channel *c, int y, long t) {
-    double H = (double)c->ny;
-    double yy = y + 0.5;
-    return ramp_factor(t, c->ramp) * 4.0 * c->u_peak * yy * (H - yy) / (H * H);
+    double H = c->y_hi - c->y_lo;
+    return ramp_factor(t, c->o.ramp) * 4.0 * c->o.u_peak * (y - c->y_lo) * (c->y_hi - y) / (H * H);
 }
 
 /* classify the source node x - c_i of a pull for node (x, y):
- * 0 = fluid node inside (coordinates returned), 1 = bounce-back (solid,
- * or wall), 2 = open boundary (Zou-He fills it).                           */
+ * 0 = fluid node inside (coordinates returned), 1 = half-way bounce-back
+ * (cylinder or wall), 2 = open boundary, 3 = interpolated wall link.        */
 static int ch_source(const channel *c, int x, int y, int i, int *xs, int *ys) {
     int sx = x - CX[i], sy = y - CY[i];
-    if (sy < 0 || sy >= c->ny) return 1;
+    if (sy < 0 || sy >= c->ny) return c->o.q_lo >= 0.0 ? 3 : 1;
     if (sx < 0 || sx >= c->nx) {
-        if (c->xbc == 2) {
+        if (c->o.xbc == 2) {
             sx = (sx + c->nx) % c->nx;
-        } else if (c->xbc == 1) {
+        } else if (c->o.xbc == 1) {
             return 1;
         } else {
             return 2;
         }
     }
-    if (c->solid[(long)sy * c->nx + sx]) return 1;
+    if (c->solid[(long)sy * c->nx + sx]) return c->o.cyl == 1 ? 3 : 1;
     *xs = sx;
     *ys = sy;
     return 0;
+}
+
+/* What the wall returns for pull direction i at fluid node (x, y), from the
+ * post-collision field fs: half-way bounce-back f*_k(x), k = opp(i), or the
+ * linear interpolation of Bouzidi et al. with link fraction q,
+ *   q <  1/2: 2q f*_k(x) + (1 - 2q) f*_k(x - c_k)
+ *   q >= 1/2: f*_k(x)/(2q) + (1 - 1/(2q)) f*_i(x)
+ * (x - c_k = x + c_i; where that node is not fluid the half-way rule is
+ * used).                                                                    */
+static double wall_return(const channel *c, const double *fs, int x, int y, int i, int kind) {
+    int nx = c->nx, ny = c->ny, k = OPP(i);
+    double fk = fs[idx(k, y, x, nx, ny)];
+    if (kind != 3) return fk;
+    double q = c->q[idx(i, y, x, nx, ny)];
+    if (q >= 0.5) return fk / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fs[idx(i, y, x, nx, ny)];
+    int xb = x + CX[i], yb = y + CY[i];
+    if (xb < 0 || xb >= nx || yb < 0 || yb >= ny || c->solid[(long)yb * nx + xb]) return fk;
+    return 2.0 * q * fk + (1.0 - 2.0 * q) * fs[idx(k, yb, xb, nx, ny)];
 }
 
 /* Zou-He completion of the unknown populations at an open-column node. */
@@ -552,6 +627,78 @@ static void zou_he_outlet(double *f) {
     f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * rho * ux;
 }
 
+/* Velocity and density imposed at open-column node (x, y) of the streamed
+ * field f: inlet prescribed u and rho from the known populations, outlet
+ * rho = 1, u_y = 0, u_x from the known populations (the Zou-He relations).  */
+static void open_state(const channel *c, const double *f, int x, int y, long t, double *rho, double *ux,
+                       double *uy) {
+    int nx = c->nx, ny = c->ny;
+    double g[9];
+    for (int i = 0; i < 9; ++i) g[i] = f[idx(i, y, x, nx, ny)];
+    if (x == 0) {
+        *ux = inlet_ux(c, y, t);
+        *uy = 0.0;
+        *rho = (g[0] + g[2] + g[4] + 2.0 * (g[3] + g[6] + g[7])) / (1.0 - *ux);
+    } else {
+        *rho = 1.0;
+        *ux = -1.0 + (g[0] + g[2] + g[4] + 2.0 * (g[1] + g[5] + g[8]));
+        *uy = 0.0;
+    }
+}
+
+/* finite-difference reconstruction of both open columns (xbc 3) on the
+ * streamed field f, at time t                                               */
+static void fd_open_columns(const channel *c, double *f, long t) {
+    int nx = c->nx, ny = c->ny;
+    double *U = malloc(sizeof(double) * 3 * ny * 2); /* rho, ux, uy per column node */
+    for (int side = 0; side < 2; ++side) {
+        int x = side == 0 ? 0 : nx - 1;
+        for (int y = 0; y < ny; ++y) {
+            double *u = U + 3 * (side * ny + y);
+            open_state(c, f, x, y, t, &u[0], &u[1], &u[2]);
+        }
+    }
+    for (int side = 0; side < 2; ++side) {
+        int x = side == 0 ? 0 : nx - 1, s = side == 0 ? 1 : -1;
+        for (int y = 0; y < ny; ++y) {
+            const double *u = U + 3 * (side * ny + y);
+            /* across the column: u at x, x + s, x + 2s (interior moments) */
+            double r1, u1x, u1y, r2, u2x, u2y, g[9];
+            for (int i = 0; i < 9; ++i) g[i] = f[idx(i, y, x + s, nx, ny)];
+            moments(g, &r1, &u1x, &u1y);
+            for (int i = 0; i < 9; ++i) g[i] = f[idx(i, y, x + 2 * s, nx, ny)];
+            moments(g, &r2, &u2x, &u2y);
+            double dxux = s * (-3.0 * u[1] + 4.0 * u1x - u2x) / 2.0;
+            double dxuy = s * (-3.0 * u[2] + 4.0 * u1y - u2y) / 2.0;
+            /* along the column: central, one-sided at the ends */
+            const double *um, *uc = u, *up;
+            double dyux, dyuy;
+            if (y == 0) {
+                up = U + 3 * (side * ny + 1);
+                um = U + 3 * (side * ny + 2);
+                dyux = (-3.0 * uc[1] + 4.0 * up[1] - um[1]) / 2.0;
+                dyuy = (-3.0 * uc[2] + 4.0 * up[2] - um[2]) / 2.0;
+            } else if (y == ny - 1) {
+                um = U + 3 * (side * ny + ny - 2);
+                up = U + 3 * (side * ny + ny - 3);
+                dyux = (3.0 * uc[1] - 4.0 * um[1] + up[1]) / 2.0;
+                dyuy = (3.0 * uc[2] - 4.0 * um[2] + up[2]) / 2.0;
+            } else {
+                um = U + 3 * (side * ny + y - 1);
+                up = U + 3 * (side * ny + y + 1);
+                dyux = (up[1] - um[1]) / 2.0;
+                dyuy = (up[2] - um[2]) / 2.0;
+            }
+            for (int i = 0; i < 9; ++i) {
+                double Qxx = CX[i] * CX[i] - CS2, Qyy = CY[i] * CY[i] - CS2, Qxy = CX[i] * CY[i];
+                double QS = Qxx * dxux + Qyy * dyuy + Qxy * (dxuy + dyux);
+                f[idx(i, y, x, nx, ny)] = feq(i, u[0], u[1], u[2]) - W(i) * u[0] * c->tau / CS2 * QS;
+            }
+        }
+    }
+    free(U);
+}
+
 static void channel_step(const channel *c, long t, double *f, double *fs) {
     int nx = c->nx, ny = c->ny;
     /* collision at every fluid node */
@@ -563,8 +710,8 @@ static void channel_step(const channel *c, long t, double *f, double *fs) {
             collide(a, c->tau, b);
             for (int i = 0; i < 9; ++i) fs[idx(i, y, x, nx, ny)] = b[i];
         }
-    /* streaming by pull, bounce-back where the source is not fluid, then
-     * Zou-He on the open columns with the inflow of time t+1              */
+    /* streaming by pull, the wall rule where the source is not fluid, then
+     * the open columns with the inflow of time t+1                         */
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (c->solid[(long)y * nx + x]) continue;
@@ -575,14 +722,13 @@ static void channel_step(const channel *c, long t, double *f, double *fs) {
                 int k = ch_source(c, x, y, i, &xs, &ys);
                 if (k == 0)
                     g[i] = fs[idx(i, ys, xs, nx, ny)];
-                else if (k == 1)
-                    g[i] = fs[idx(OPP(i), y, x, nx, ny)];
-                else {
+                else if (k == 2) {
                     g[i] = 0.0;
                     open = 1;
-                }
+                } else
+                    g[i] = wall_return(c, fs, x, y, i, k);
             }
-            if (open) {
+            if (open && c->o.xbc == 0) {
                 if (x == 0)
                     zou_he_inlet(g, inlet_ux(c, y, t + 1));
                 else
@@ -590,39 +736,77 @@ static void channel_step(const channel *c, long t, double *f, double *fs) {
             }
             for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = g[i];
         }
+    if (c->o.xbc == 3) fd_open_columns(c, f, t + 1);
+}
+
+static int channel_setup(channel *c, const oracle_channel_opts *o) {
+    memset(c, 0, sizeof *c);
+    c->o = *o;
+    c->nx = o->nx;
+    c->ny = o->ny;
+    c->tau = o->nu / CS2 + 0.5;
+    if (!(c->tau > 0.5) || o->nx < 2 || o->ny < 3) return -1;
+    if (o->xbc == 3 && (o->nx < 4 || o->ny < 3)) return -1;
+    c->y_lo = o->q_lo >= 0.0 ? -o->q_lo : -0.5;
+    c->y_hi = o->q_hi >= 0.0 ? (o->ny - 1) + o->q_hi : o->ny - 0.5;
+    long n = (long)o->nx * o->ny;
+    c->solid = calloc((size_t)n, 1);
+    c->q = calloc((size_t)(9 * n), sizeof(double));
+    for (int y = 0; y < o->ny; ++y)
+        for (int x = 0; x < o->nx; ++x) c->solid[(long)y * o->nx + x] = (unsigned char)in_cylinder(c, x, y);
+    for (int y = 0; y < o->ny; ++y)
+        for (int x = 0; x < o->nx; ++x) {
+            if (c->solid[(long)y * o->nx + x]) continue;
+            for (int i = 1; i < 9; ++i) {
+                int xs, ys;
+                if (ch_source(c, x, y, i, &xs, &ys) != 3) continue;
+                c->q[idx(i, y, x, o->nx, o->ny)] = o->q_fix >= 0.0 ? o->q_fix : link_fraction(c, x, y, i);
+            }
+        }
+    return 0;
+}
+
+static void channel_free(channel *c) {
+    free(c->solid);
+    free(c->q);
 }
 
 /* Run one channel sample. Outputs (each may be NULL): f_out [9][ny][nx]
  * (solid nodes hold 0), rho/ux/uy [ny][nx] (0 at solid nodes), force[2]
- * = (F_x, F_y) at the final step, cd_cl[2], and wall_force[2], the same
- * momentum-exchange sum over the links into the channel walls (not a
- * quantity of interest: it closes the global momentum balance in tests).  */
-int oracle_channel_run(int nx, int ny, int xbc, int D, int cx, int cy, double nu, double u_peak, long ramp,
-                       long steps, double ux_init, double *f_out, double *rho_out, double *ux_out, double *uy_out,
-                       double *force, double *cd_cl, double *wall_force) {
+ * = (F_x, F_y) at the final step, cd_cl[2], wall_force[2] (the same
+ * momentum-exchange sum over the links into the channel walls: not a
+ * quantity of interest, it closes the global momentum balance in tests),
+ * q_out [9][ny][nx] (the link fractions).                                    */
+int oracle_channel_run_opts(const oracle_channel_opts *o, double *f_out, double *rho_out, double *ux_out,
+                            double *uy_out, double *force, double *cd_cl, double *wall_force, double *q_out) {
     channel c;
-    c.nx = nx;
-    c.ny = ny;
-    c.xbc = xbc;
-    c.D = D;
-    c.cx = cx;
-    c.cy = cy;
-    c.tau = nu / CS2 + 0.5;
-    c.u_peak = u_peak;
-    c.ramp = ramp;
-    if (!(c.tau > 0.5) || nx < 2 || ny < 3) return -1;
+    if (channel_setup(&c, o) != 0) {
+        channel_free(&c);
+        return -1;
+    }
+    int nx = c.nx, ny = c.ny;
     long n = (long)nx * ny;
-    c.solid = calloc((size_t)n, 1);
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) c.solid[(long)y * nx + x] = (unsigned char)ch_cyl(&c, x, y);
     double *f = calloc((size_t)(9 * n), sizeof(double)), *fs = calloc((size_t)(9 * n), sizeof(double));
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (c.solid[(long)y * nx + x]) continue;
-            for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = feq(i, 1.0, ux_init, 0.0);
+            for (int i = 0; i < 9; ++i) f[idx(i, y, x, nx, ny)] = feq(i, 1.0, o->ux_init, 0.0);
         }
-    for (long t = 0; t < steps; ++t) channel_step(&c, t, f, fs);
+    for (long t = 0; t < o->steps; ++t) channel_step(&c, t, f, fs);
 
+    /* collide the final state everywhere, then exchange momentum */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long cc = (long)y * nx + x;
+            if (c.solid[cc]) {
+                for (int i = 0; i < 9; ++i) fs[idx(i, y, x, nx, ny)] = 0.0;
+                continue;
+            }
+            double a[9], b[9];
+            for (int i = 0; i < 9; ++i) a[i] = f[idx(i, y, x, nx, ny)];
+            collide(a, c.tau, b);
+            for (int i = 0; i < 9; ++i) fs[idx(i, y, x, nx, ny)] = b[i];
+        }
     nsum Fx = {0, 0}, Fy = {0, 0}, Wx = {0, 0}, Wy = {0, 0};
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -633,26 +817,27 @@ int oracle_channel_run(int nx, int ny, int xbc, int D, int cx, int cy, double nu
                 if (uy_out) uy_out[cc] = 0.0;
                 continue;
             }
-            double a[9], b[9], rho, ux, uy;
+            double a[9], rho, ux, uy;
             for (int i = 0; i < 9; ++i) a[i] = f[idx(i, y, x, nx, ny)];
             moments(a, &rho, &ux, &uy);
             if (rho_out) rho_out[cc] = rho;
             if (ux_out) ux_out[cc] = ux;
             if (uy_out) uy_out[cc] = uy;
-            collide(a, c.tau, b);
-            for (int i = 1; i < 9; ++i) {
-                /* link x -> x + c_i is a bounce-back link iff the pull of
-                 * direction opp(i) at x has its source there                */
-                int xs = 0, ys = 0;
-                if (ch_source(&c, x, y, OPP(i), &xs, &ys) != 1) continue;
-                int xn = x + CX[i], yn = y + CY[i];
+            for (int k = 1; k < 9; ++k) {
+                /* link x -> x + c_k meets a wall iff the pull of direction
+                 * opp(k) at x has its source there                          */
+                int xs = 0, ys = 0, i = OPP(k);
+                int kind = ch_source(&c, x, y, i, &xs, &ys);
+                if (kind != 1 && kind != 3) continue;
+                double ex = fs[idx(k, y, x, nx, ny)] + wall_return(&c, fs, x, y, i, kind);
+                int xn = x + CX[k], yn = y + CY[k];
                 int into_cyl = xn >= 0 && xn < nx && yn >= 0 && yn < ny && c.solid[(long)yn * nx + xn];
                 if (into_cyl) {
-                    nadd(&Fx, 2.0 * CX[i] * b[i]);
-                    nadd(&Fy, 2.0 * CY[i] * b[i]);
+                    nadd(&Fx, CX[k] * ex);
+                    nadd(&Fy, CY[k] * ex);
                 } else {
-                    nadd(&Wx, 2.0 * CX[i] * b[i]);
-                    nadd(&Wy, 2.0 * CY[i] * b[i]);
+                    nadd(&Wx, CX[k] * ex);
+                    nadd(&Wy, CY[k] * ex);
                 }
             }
         }
@@ -666,27 +851,53 @@ int oracle_channel_run(int nx, int ny, int xbc, int D, int cx, int cy, double nu
         wall_force[1] = nval(&Wy);
     }
     if (cd_cl) {
-        double q = 1.0 * u_peak * u_peak * (double)D;
+        double D = o->cyl == 1 ? 2.0 * o->R : (double)o->D;
+        double U = o->force_ref == 1 ? (2.0 / 3.0) * o->u_peak : o->u_peak;
+        double q = 1.0 * U * U * D;
         cd_cl[0] = D > 0 ? 2.0 * fx / q : 0.0;
         cd_cl[1] = D > 0 ? 2.0 * fy / q : 0.0;
     }
     if (f_out) memcpy(f_out, f, sizeof(double) * 9 * n);
-    free(c.solid);
+    if (q_out) memcpy(q_out, c.q, sizeof(double) * 9 * n);
+    channel_free(&c);
     free(f);
     free(fs);
     return 0;
+}
+
+/* The half-way variant with the integer cylinder (the argument list of the
+ * first channel interface).                                                 */
+int oracle_channel_run(int nx, int ny, int xbc, int D, int cx, int cy, double nu, double u_peak, long ramp,
+                       long steps, double ux_init, double *f_out, double *rho_out, double *ux_out, double *uy_out,
+                       double *force, double *cd_cl, double *wall_force) {
+    oracle_channel_opts o;
+    memset(&o, 0, sizeof o);
+    o.nx = nx;
+    o.ny = ny;
+    o.xbc = xbc;
+    o.cyl = 0;
+    o.D = D;
+    o.cx = cx;
+    o.cy = cy;
+    o.q_lo = o.q_hi = o.q_fix = -1.0;
+    o.nu = nu;
+    o.u_peak = u_peak;
+    o.ramp = ramp;
+    o.steps = steps;
+    o.ux_init = ux_init;
+    return oracle_channel_run_opts(&o, f_out, rho_out, ux_out, uy_out, force, cd_cl, wall_force, NULL);
 }
 
 /* Count of solid cylinder nodes, for geometry checks. */
 long oracle_cylinder_nodes(int nx, int ny, int D, int cx, int cy) {
     channel c;
     memset(&c, 0, sizeof c);
-    c.D = D;
-    c.cx = cx;
-    c.cy = cy;
+    c.o.D = D;
+    c.o.cx = cx;
+    c.o.cy = cy;
     long s = 0;
     for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) s += ch_cyl(&c, x, y);
+        for (int x = 0; x < nx; ++x) s += in_cylinder(&c, x, y);
     return s;
 }
 

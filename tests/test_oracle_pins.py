@@ -529,3 +529,94 @@ def test_wasserstein1_vs_scipy_and_closed_forms():
     assert abs(O.wasserstein1([2.0], [1.0], [-1.5], [3.0]) - 3.5) < 1e-15
     # ties and repeated values: a mass of 1/2 at 0 and 1/2 at 1 against U{0, 0, 1, 1, 1, 1}
     assert abs(O.wasserstein1([0, 1], [1, 1], [0, 0, 1, 1, 1, 1], np.ones(6)) - 1 / 6) < 1e-15
+
+
+# ------------------------------------- interpolated walls and open boundaries
+
+C9X = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+C9Y = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def test_interpolated_bounce_back_at_one_half_is_half_way():
+    # with every link fraction 1/2 both branches of the interpolation return
+    # f*_k(x): the scheme (and its momentum exchange) is half-way bounce-back
+    a = O.channel_run(60, 24, 0.05, 0.04, 150, D=8, cx=15, cy=11, ramp=50, want_f=True)
+    b = O.channel_run_opts(60, 24, 0.05, 0.04, 150, cyl=1, ccx=15, ccy=11, R=4.0, q_fix=0.5, ramp=50,
+                           want_f=True)
+    assert np.array_equal(a["f"], b["f"])
+    assert np.array_equal(a["force"], b["force"])
+
+
+def test_circle_link_fractions_lie_on_the_circle():
+    cx, cy, R = 15.3, 11.7, 4.4
+    r = O.channel_run_opts(60, 24, 0.05, 0.04, 0, cyl=1, ccx=cx, ccy=cy, R=R, want_q=True)
+    q = r["q"]
+    i, y, x = np.nonzero(q)
+    assert len(i) > 20
+    assert np.all((q[i, y, x] > 0) & (q[i, y, x] <= 1))
+    # the crossing point x - q c_i is on the circle; the node is outside it
+    # and the link's far end inside
+    px, py = x - q[i, y, x] * C9X[i], y - q[i, y, x] * C9Y[i]
+    assert np.abs(np.hypot(px - cx, py - cy) - R).max() < 1e-12
+    assert np.all(np.hypot(x - cx, y - cy) > R)
+    assert np.all(np.hypot(x - C9X[i] - cx, y - C9Y[i] - cy) <= R)
+
+
+def _poiseuille_shape_error(ny, q_lo, q_hi, xbc=0, nu=1 / 6, geometry=None):
+    nx = 2 * ny
+    r = O.channel_run_opts(nx, ny, nu, 0.02, int(4 * ny * ny / nu), xbc=xbc, q_lo=q_lo, q_hi=q_hi)
+    lo, hi = geometry or ((-q_lo if q_lo >= 0 else -0.5), ((ny - 1) + q_hi if q_hi >= 0 else ny - 0.5))
+    y = np.arange(ny)
+    ex = (y - lo) * (hi - y)
+    col = r["ux"][:, nx // 2]
+    return np.abs(col / col.sum() - ex / ex.sum()).max() * ny, r
+
+
+@pytest.mark.parametrize("q_lo, q_hi", [(0.1, 0.9), (0.7, 0.2)])
+def test_interpolated_straight_walls_give_second_order_poiseuille(q_lo, q_hi):
+    # Walls at y = -q_lo and ny - 1 + q_hi, treated by the interpolated
+    # bounce-back (both branches q < 1/2 and q >= 1/2 occur): the steady
+    # profile shape converges to the parabola between the true wall
+    # positions at second order. Half-way bounce-back on the same lattice
+    # places the walls at -1/2, ny - 1/2 and is only first order there.
+    e = [_poiseuille_shape_error(ny, q_lo, q_hi)[0] for ny in (8, 16, 32)]
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(orders > 1.8), (e, orders)
+    assert e[-1] < 5e-3
+    geom = (-q_lo, 31 + q_hi)
+    hw = _poiseuille_shape_error(32, -1, -1, geometry=geom)[0]
+    assert hw > 5 * e[-1]
+
+
+def test_finite_difference_inlet_outlet_poiseuille():
+    # Latt et al.'s reconstruction: the inlet carries the prescribed velocity
+    # and the outlet rho = 1 exactly; the steady channel has no transverse
+    # velocity and no kink at the open columns up to O(dx^2). (A dropped or
+    # sign-flipped non-equilibrium part, or tau - 1/2 for tau, leaves
+    # |u_y| ~ 1e-2 u and kinks ~ 1e-2 u that do not shrink with ny.)
+    res = {}
+    for ny in (8, 16):
+        nx = 2 * ny
+        _, r = _poiseuille_shape_error(ny, -1, -1, xbc=3, nu=0.1)
+        y = np.arange(ny)
+        ex = 4 * 0.02 * (y + 0.5) * (ny - y - 0.5) / ny ** 2
+        assert np.abs(r["ux"][:, 0] - ex).max() < 1e-15
+        assert np.abs(r["uy"][:, 0]).max() < 1e-17
+        assert np.abs(r["rho"][:, -1] - 1).max() < 1e-15
+        kink = max(np.abs(r["ux"][:, 0] - 2 * r["ux"][:, 1] + r["ux"][:, 2]).max(),
+                   np.abs(r["ux"][:, -1] - 2 * r["ux"][:, -2] + r["ux"][:, -3]).max()) / 0.02
+        res[ny] = (np.abs(r["uy"]).max() / 0.02, kink)
+    assert res[8][0] < 3e-3 and res[16][0] < 1e-3 and res[8][0] / res[16][0] > 3, res
+    assert res[16][1] < 1e-3, res
+
+
+def test_interpolated_cylinder_symmetric_and_drag_converges_in_time():
+    # the circle centred between the walls: mirror symmetry leaves no lift;
+    # the drag is positive and settles
+    D = 8
+    nx, ny = 22 * D, 4 * D
+    kw = dict(cyl=1, ccx=2 * D, ccy=(ny - 1) / 2, R=D / 2, xbc=3, ramp=500, force_ref=1)
+    a = O.channel_run_opts(nx, ny, 0.04, 0.06, 3000, **kw)
+    assert abs(a["cl"]) < 1e-10 and a["cd"] > 1.0
+    assert np.allclose(a["ux"], a["ux"][::-1], rtol=0, atol=1e-13)
+    assert np.allclose(a["uy"], -a["uy"][::-1], rtol=0, atol=1e-13)
