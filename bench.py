@@ -309,6 +309,65 @@ def study_wasserstein(U, W, log, prec="fp32", ns=(8, 16, 32, 64, 128), n_ref=256
     return out
 
 
+def study_cylinder_paper(U, W, log, steps=40000, n_mc=1000):
+    """The paper's cylinder set-up (22D x 4D, D = 20, interpolated circle,
+    finite-difference inlet/outlet, u_in = u(1 + 0.2 xi), Re = 20 on the mean
+    inflow, FP32): mean and standard deviation of C_D by Monte Carlo, Halton
+    quasi Monte Carlo and Gauss-Legendre SC-gPC, and the deterministic value,
+    next to the paper's Table tab:uq_results; the drag history of the
+    deterministic run; a resolution study (D = 10, 20, 40) of the
+    deterministic drag for the interpolated and the half-way/Zou-He
+    boundaries; and the literal reading (peak velocity in Re and C_D)."""
+    import numpy as np
+
+    base = dict(W.CYLINDER_PAPER_FP32, steps=steps)
+    paper = {"mc": (5.66731, 0.34896), "qmc": (5.67270, 0.34890), "sc": (5.67261, 0.34888),
+             "deterministic": (5.63208, None)}
+    out = {"workload": base["name"] + f", {steps} steps", "paper_table": paper, "runs": {}}
+
+    def run(spec, label, checkpoints=()):
+        with U.Job(spec) as job:
+            hist, done, ms = [], 0, 0.0
+            for c in list(checkpoints) + [spec["steps"]]:
+                if c > done:
+                    ms += job.run_timed(c - done)
+                    done = c
+                if c in checkpoints:
+                    hist.append((c, float(job.qoi_samples("cd")[:, 0].mean())))
+            st = job.moments("cd")
+            cd = job.qoi_samples("cd")[:, 0]
+            cl = job.qoi_samples("cl")[:, 0]
+            nodes = job.S * spec["nx"] * spec["ny"]
+        r = {"samples": int(cd.size), "mean": float(st["mean"][0]), "std": float(np.sqrt(st["var"][0])),
+             "cl_max_abs": float(np.abs(cl).max()), "ms": round(ms, 1),
+             "mlups": round(nodes * spec["steps"] / (ms * 1e-3) / 1e6, 1)}
+        if hist:
+            r["history"] = hist
+        log(f"bench: cylinder paper {label} {r}")
+        out["runs"][label] = r
+        return r
+
+    run(W.scaled(base, rule=dict(kind="gl", n=1, order=0)), "deterministic",
+        checkpoints=(5000, 10000, 20000, 30000))
+    run(base, "sc")
+    run(W.scaled(base, rule=dict(kind="mc", N=n_mc, seed=W.SEED)), "mc")
+    run(W.scaled(base, rule=dict(kind="halton", N=n_mc)), "qmc")
+    # resolution study of the deterministic drag (lattice velocity fixed, so
+    # nu and the step count scale with D)
+    for D in (10, 20, 40):
+        for scheme in ("interp", "halfway"):
+            f = D / 20
+            spec = W.scaled(base, name=f"cyl_D{D}_{scheme}", nx=22 * D, ny=4 * D, cyl_x=2.0 * D,
+                            cyl_y=(4 * D - 1) / 2, cyl_d=float(D), nu=0.04 * f, steps=int(steps * f),
+                            ramp=int(base["ramp"] * f), rule=dict(kind="gl", n=1, order=0))
+            if scheme == "halfway":
+                spec = W.scaled(spec, cyl_bc="halfway", xbc="zouhe", D=D, cx=2 * D, cy=2 * D)
+            run(spec, f"resolution_D{D}_{scheme}")
+    # the literal reading: peak inflow in Re and in C_D
+    run(W.scaled(base, nu=0.06, force_ref="peak", rule=dict(kind="gl", n=1, order=0)), "literal_peak_reading")
+    return out
+
+
 def cpu_baseline(spec, n_samples=4, lbm_steps=300):
     """The FP64 oracle, single-threaded, on the full lattice of the workload
     for a few samples and steps (about 10 s of CPU work)."""
@@ -338,7 +397,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
-    ap.add_argument("--study", choices=["precision", "cylinder", "samplers", "wasserstein"], default=None,
+    ap.add_argument("--study", choices=["precision", "cylinder", "samplers", "wasserstein", "cylinder_paper"], default=None,
                     help="run a measurement study instead of the benchmark and print its JSON")
     ap.add_argument("--study-precision", default="fp32", choices=["fp64", "fp32"],
                     help="storage precision of the wasserstein study")
@@ -380,6 +439,9 @@ def main():
         return
     if args.study == "samplers":
         print(json.dumps(study_samplers(U, W, log)), flush=True)
+        return
+    if args.study == "cylinder_paper":
+        print(json.dumps(study_cylinder_paper(U, W, log)), flush=True)
         return
     if args.study == "wasserstein":
         print(json.dumps(study_wasserstein(U, W, log, prec=args.study_precision)), flush=True)

@@ -74,8 +74,45 @@ typedef enum {
     UQ_XBC_ZOUHE = 0,   /* Zou-He parabolic velocity inlet at x = 0 and Zou-He
                            pressure outlet (rho = 1) at x = nx-1            */
     UQ_XBC_WALLS = 1,   /* half-way bounce-back walls at x = -1/2, nx - 1/2 */
-    UQ_XBC_PERIODIC = 2 /* periodic in x                                    */
+    UQ_XBC_PERIODIC = 2, /* periodic in x                                   */
+    /* the paper's interpolated inlet and outlet (Sec. "Flow past a circular
+     * cylinder with uncertain inlet velocity", after Latt et al., Phys. Rev.
+     * E 77, 056703, 2008): every population of an open-column node is
+     * rebuilt as equilibrium plus the first-order non-equilibrium part
+     * -w_i rho tau/cs^2 Q_i : grad u, Q_i = c_i c_i - cs^2 I, with grad u by
+     * second-order finite differences (one-sided into the fluid across the
+     * column, central along it, one-sided at its two ends). Inlet: the
+     * parabolic velocity, rho from the known populations; outlet: rho = 1,
+     * u_y = 0, u_x from the known populations. Needs the AB layout, nx >= 4,
+     * and the cylinder at least 3 nodes away from both columns. */
+    UQ_XBC_INTERP = 3
 } uq_xbc;
+
+/* Cylinder wall treatment (channel). */
+typedef enum {
+    /* solid nodes 4((x-cx)^2 + (y-cy)^2) <= D^2 on the integer centre (cx,
+     * cy); half-way bounce-back on every link into them */
+    UQ_CYL_HALFWAY = 0,
+    /* the exact circle of centre (cyl_x, cyl_y) and diameter cyl_d (solid
+     * iff (x-cyl_x)^2 + (y-cyl_y)^2 <= (cyl_d/2)^2) with the linear
+     * interpolated bounce-back of Bouzidi, Firdaouss and Lallemand (Phys.
+     * Fluids 13, 3452, 2001), the paper's second-order curved wall: for the
+     * link from fluid node x along c_k that meets the circle at fraction q,
+     *   q <  1/2: f_opp(k)(x, t+1) = 2q f*_k(x) + (1-2q) f*_k(x - c_k)
+     *   q >= 1/2: f_opp(k)(x, t+1) = f*_k(x)/(2q) + (1 - 1/(2q)) f*_opp(k)(x).
+     * Forces by momentum exchange over the same links, F = sum c_k (f*_k(x)
+     * + f_opp(k)(x, t+1)) (Mei et al., J. Comput. Phys. 175, 2002). Needs
+     * the AB layout and the circle at least 2 nodes inside the walls and 3
+     * nodes away from the x ends. */
+    UQ_CYL_BOUZIDI = 1
+} uq_cyl_bc;
+
+/* Velocity that normalises C_D, C_L and that a Reynolds-number input uses
+ * (nu = U D/Re with the nominal peak): */
+typedef enum {
+    UQ_FORCE_REF_PEAK = 0, /* U = the sample's peak inflow u_peak           */
+    UQ_FORCE_REF_MEAN = 1  /* U = the mean of the parabola, 2/3 u_peak       */
+} uq_force_ref;
 
 /* Input that an uncertain variable drives. */
 typedef enum {
@@ -173,6 +210,9 @@ typedef struct {
     int32_t layout;    /* uq_layout                                         */
     int32_t level;     /* SMOLYAK_CC: sparse-grid level                     */
     int32_t init;      /* uq_init (vortex only)                             */
+    int32_t cyl_bc;    /* uq_cyl_bc (channel)                               */
+    int32_t force_ref; /* uq_force_ref (channel)                            */
+    double cyl_x, cyl_y, cyl_d; /* exact circle of UQ_CYL_BOUZIDI          */
 } uq_problem;
 
 /* Device context. `stream` is a hipStream_t (e.g. torch's current stream,
@@ -199,9 +239,11 @@ typedef enum {
     /* velocity field, n_out = 2 nx ny: all u_x in row-major [ny][nx], then
      * all u_y; 0 at solid nodes (Fig. velocity_stats statistics).        */
     UQ_QOI_VEL = 1,
-    /* drag / lift coefficient 2F/(u_peak^2 D) from momentum exchange on the
-     * cylinder links, F = sum 2 c_i f*_i over links into the cylinder, with
-     * the sample's u_peak (Eqs. dragForce, liftForce, C_D, C_L).         */
+    /* drag / lift coefficient 2F/(U^2 D) from momentum exchange on the
+     * cylinder links of the final state (half-way: F = sum 2 c_i f*_i over
+     * links into the cylinder; interpolated links as under uq_cyl_bc), U
+     * the sample's peak inflow or its mean (uq_force_ref), D the diameter
+     * (Eqs. dragForce, liftForce and the C_D, C_L definitions).         */
     UQ_QOI_CD = 2,
     UQ_QOI_CL = 3,
     /* density field [ny][nx], 0 at solid nodes */

@@ -20,7 +20,9 @@ STATUS_NAMES = {0: "UQ_OK", 1: "UQ_EINVAL", 2: "UQ_ENOMEM", 3: "UQ_EAGAIN", 4: "
                 5: "UQ_EDEVICE", 6: "UQ_ESTATE"}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}
 GEOMETRY = {"tgv": 0, "channel": 1}
-XBC = {0: 0, 1: 1, 2: 2, "zouhe": 0, "walls": 1, "periodic": 2}
+XBC = {0: 0, 1: 1, 2: 2, 3: 3, "zouhe": 0, "walls": 1, "periodic": 2, "interp": 3}
+CYL_BC = {"halfway": 0, "bouzidi": 1}
+FORCE_REF = {"peak": 0, "mean": 1}
 TARGET = {"nu": 0, "u0": 1, "phase_x": 2, "phase_y": 3, "re": 4, "u_peak": 5, "zeta00": 6, "zeta01": 7,
           "zeta10": 8, "zeta11": 9}
 INIT = {"tgv": 0, "harmonic": 1}
@@ -48,6 +50,8 @@ class Problem(C.Structure):
         ("ramp", C.c_int64), ("n_dists", C.c_int32), ("dists", Dist * MAX_DIMS), ("rule", C.c_int32),
         ("n_per_dim", C.c_int32), ("order", C.c_int32), ("mc_n", C.c_int64), ("seed", C.c_uint64),
         ("layout", C.c_int32), ("level", C.c_int32), ("init", C.c_int32),
+        ("cyl_bc", C.c_int32), ("force_ref", C.c_int32),
+        ("cyl_x", C.c_double), ("cyl_y", C.c_double), ("cyl_d", C.c_double),
     ]
 
 
@@ -185,6 +189,11 @@ def make_problem(spec: dict) -> Problem:
     p.layout = LAYOUT[spec.get("layout", "auto")]
     p.level = int(r.get("level", 0))
     p.init = INIT[spec.get("init", "tgv")]
+    p.cyl_bc = CYL_BC[spec.get("cyl_bc", "halfway")]
+    p.force_ref = FORCE_REF[spec.get("force_ref", "peak")]
+    p.cyl_x = float(spec.get("cyl_x", 0.0))
+    p.cyl_y = float(spec.get("cyl_y", 0.0))
+    p.cyl_d = float(spec.get("cyl_d", 0.0))
     return p
 
 

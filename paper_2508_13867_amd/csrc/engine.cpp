@@ -17,15 +17,16 @@ static int env_int(const char *name, int dflt) {
     return std::atoi(v);
 }
 
-// Launch shape and layout of a job: the problem's explicit layout, else the
-// UQ_LAYOUT environment override ("aa" / "ab"), else AA.
 // Launch shape and layout of a job. Order of precedence: a shape measured by
 // uq_autotune for this problem class (when the problem leaves the layout to
 // AUTO, or fixes the same layout), then the UQ_* environment overrides, then
 // the defaults (AA, one row per thread, 64 elements of plane padding).
 StepShape choose_shape(const uq_problem &p, int64_t S) {
     StepShape s;
-    if (tuned_shape(p, S, &s)) return s;
+    if (tuned_shape(p, S, &s)) {
+        if (needs_ab(p)) s.layout = UQ_LAYOUT_AB;
+        return s;
+    }
     s.cpt = env_int("UQ_CPT", 1);
     s.persistent = env_int("UQ_PERSISTENT", 0);
     s.nt = env_int("UQ_NT_STORE", 1);
@@ -38,6 +39,7 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
         const char *v = std::getenv("UQ_LAYOUT");
         if (v && (v[0] == 'a' || v[0] == 'A') && (v[1] == 'b' || v[1] == 'B')) s.layout = UQ_LAYOUT_AB;
     }
+    if (needs_ab(p)) s.layout = UQ_LAYOUT_AB;
     return s;
 }
 

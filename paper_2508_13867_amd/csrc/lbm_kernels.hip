@@ -231,10 +231,123 @@ struct ModeOf {
     static constexpr int value = LAYOUT == UQ_LAYOUT_AB ? AB_PULL : (PARITY ? AA_ODD : AA_EVEN);
 };
 
-// Gather f~(x, t) of one node, with bounce-back and Zou-He.
-template <int P, bool CHANNEL, int MODE>
+// Interpolated bounce-back (Bouzidi, Firdaouss & Lallemand 2001) for pull
+// direction i of a node whose link x -> x - c_i meets the cylinder at
+// fraction q; AB layout, where the source slab holds every node's f* of the
+// previous step. With k = opp(i):
+//   q <  1/2: f_i(x) = 2q f*_k(x) + (1 - 2q) f*_k(x + c_i)
+//   q >= 1/2: f_i(x) = f*_k(x)/(2q) + (1 - 1/(2q)) f*_i(x)
+// (x + c_i is fluid: the circle keeps clear of the walls, and by convexity
+// the node behind a fluid node on a link into the circle is outside it). The
+// weights of the shifted populations cancel (the coefficients sum to 1).
+template <int P>
+__device__ inline typename Prec<P>::C wall_return(const JobDev &j, const typename Prec<P>::T *base, const Site &s,
+                                                  int64_t own, int i) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    const int k = OPPd[i];
+    const C fk = PR::ld(base + k * j.plane + own, j.inv_scale);
+    const double q = j.q[(int64_t)i * j.ny * j.pitch + own];
+    if (!(q > 0.0)) return fk;  // a half-way link (channel wall)
+    if (q >= 0.5) {
+        const C fi = PR::ld(base + i * j.plane + own, j.inv_scale);
+        const double a = 1.0 / (2.0 * q);
+        return (C)a * fk + (C)(1.0 - a) * fi;
+    }
+    const int xb = sx_of(s, CXd[i]), yb = sy_of(s, CYd[i]);
+    const C fb = PR::ld(base + k * j.plane + (int64_t)yb * j.pitch + xb, j.inv_scale);
+    return (C)(2.0 * q) * fk + (C)(1.0 - 2.0 * q) * fb;
+}
+
+template <int P, bool CHANNEL, int MODE, bool FD = true, bool QL = true>
 __device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
-                              int64_t t, double u_peak, typename Prec<P>::C f[9]) {
+                              int64_t t, double u_peak, double omega, typename Prec<P>::C f[9]);
+
+// inflow profile u_x at row y, time t: s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2
+__device__ inline double inlet_ux(const JobDev &j, int y, int64_t t, double u_peak) {
+    const double H = (double)j.ny, yy = (double)y + 0.5;
+    return ramp_factor(t, j.ramp) * 4.0 * u_peak * yy * (H - yy) / (H * H);
+}
+
+// velocity of an outlet-column node from its known populations (rho = 1)
+template <int P>
+__device__ inline double outlet_ux(const JobDev &j, const typename Prec<P>::T *base, int x, int y, int64_t t,
+                                   double u_peak, double omega) {
+    typename Prec<P>::C g[9];
+    gather<P, true, AB_PULL, false>(j, base, site(j, x, y), j.mask[(int64_t)y * j.pitch + x], t, u_peak, omega, g);
+    return (double)((g[0] + g[2] + g[4]) + (g[1] + g[5] + g[8]) + (g[1] + g[5] + g[8]));
+}
+
+// velocity of an interior node from its streamed populations
+template <int P>
+__device__ inline void node_u(const JobDev &j, const typename Prec<P>::T *base, int x, int y, int64_t t,
+                              double u_peak, double omega, double &ux, double &uy) {
+    using C = typename Prec<P>::C;
+    C g[9], drho, gx, gy;
+    gather<P, true, AB_PULL, false>(j, base, site(j, x, y), j.mask[(int64_t)y * j.pitch + x], t, u_peak, omega, g);
+    moments(g, drho, gx, gy);
+    ux = (double)gx;
+    uy = (double)gy;
+}
+
+// Finite-difference reconstruction of an open-column node (the paper's
+// interpolated inlet / outlet after Latt et al. 2008): f_i = f_i^eq(rho, u)
+// + f_i^neq, f_i^neq = -3 w_i rho tau Q_i : grad u, Q_i = c_i c_i - I/3.
+// grad u: across the column the one-sided second-order difference
+// (-3 u_0 + 4 u_1 - u_2)/2 into the fluid; along it the central difference,
+// one-sided at the two end rows. Inlet: u prescribed, rho from the known
+// populations; outlet: rho = 1, u_y = 0, u_x from the known populations.
+template <int P>
+__device__ inline void fd_column(const JobDev &j, const typename Prec<P>::T *base, const Site &s, int64_t t,
+                                 double u_peak, double omega, typename Prec<P>::C f[9]) {
+    using C = typename Prec<P>::C;
+    const int x = s.x, y = s.y, ny = j.ny;
+    const bool inlet = x == 0;
+    const int sd = inlet ? 1 : -1;
+    double rho, ux, uy = 0.0;
+    if (inlet) {
+        ux = inlet_ux(j, y, t, u_peak);
+        const double S = (double)((f[0] + f[2] + f[4]) + (f[3] + f[6] + f[7]) + (f[3] + f[6] + f[7]));
+        rho = 1.0 + (S + ux) / (1.0 - ux);
+    } else {
+        rho = 1.0;
+        ux = (double)((f[0] + f[2] + f[4]) + (f[1] + f[5] + f[8]) + (f[1] + f[5] + f[8]));
+    }
+    // across the column
+    double u1x, u1y, u2x, u2y;
+    node_u<P>(j, base, x + sd, y, t, u_peak, omega, u1x, u1y);
+    node_u<P>(j, base, x + 2 * sd, y, t, u_peak, omega, u2x, u2y);
+    const double dxux = sd * (-3.0 * ux + 4.0 * u1x - u2x) * 0.5;
+    const double dxuy = sd * (-3.0 * uy + 4.0 * u1y - u2y) * 0.5;
+    // along the column (u_y = 0 on both columns)
+    auto col_ux = [&](int yy) {
+        return inlet ? inlet_ux(j, yy, t, u_peak) : outlet_ux<P>(j, base, x, yy, t, u_peak, omega);
+    };
+    double dyux;
+    if (y == 0)
+        dyux = (-3.0 * ux + 4.0 * col_ux(1) - col_ux(2)) * 0.5;
+    else if (y == ny - 1)
+        dyux = (3.0 * ux - 4.0 * col_ux(ny - 2) + col_ux(ny - 3)) * 0.5;
+    else
+        dyux = (col_ux(y + 1) - col_ux(y - 1)) * 0.5;
+    const double dyuy = 0.0;
+    const double tau = 1.0 / omega, drho = rho - 1.0, uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double cx = CXd[i], cy = CYd[i], w = wgt<double>(i);
+        const double cu = cx * ux + cy * uy;
+        const double QS = (cx * cx - 1.0 / 3.0) * dxux + (cy * cy - 1.0 / 3.0) * dyuy + cx * cy * (dxuy + dyux);
+        f[i] = (C)(w * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)) - 3.0 * w * rho * tau * QS);
+    }
+}
+
+// Gather f~(x, t) of one node, with the wall rules and the open columns
+// (FD = false leaves the open-column populations of a finite-difference job
+// unset: the reconstruction reads its neighbours that way; QL = false omits
+// the interpolated links: the bulk step kernel never meets those nodes).
+template <int P, bool CHANNEL, int MODE, bool FD, bool QL>
+__device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
+                              int64_t t, double u_peak, double omega, typename Prec<P>::C f[9]) {
     using PR = Prec<P>;
     const float inv = j.inv_scale;
     const int64_t pitch = j.pitch, plane = j.plane;
@@ -245,16 +358,25 @@ __device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, 
             f[i] = PR::ld(base + i * plane + own, inv);
         } else if (CHANNEL && (m & (1u << (M_BB + i)))) {
             // bounce-back: f_i(x,t) = f*_opp(i)(x,t-1), stored at this node
-            // (AA odd: in slot i; AB: in slot opp(i))
-            f[i] = PR::ld(base + (MODE == AA_ODD ? i : OPPd[i]) * plane + own, inv);
+            // (AA odd: in slot i; AB: in slot opp(i)); interpolated links
+            // (AB only) combine it with a second value
+            if (MODE == AB_PULL && QL && (m & M_QLINK))
+                f[i] = wall_return<P>(j, base, s, own, i);
+            else
+                f[i] = PR::ld(base + (MODE == AA_ODD ? i : OPPd[i]) * plane + own, inv);
         } else if (CHANNEL && (m & (1u << (M_OPEN + i)))) {
-            f[i] = 0;  // rest state at t = 0, else filled by Zou-He below
+            f[i] = 0;  // rest state at t = 0, else filled below
         } else {
             const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
             f[i] = PR::ld(base + (MODE == AA_ODD ? OPPd[i] : i) * plane + (int64_t)ys * pitch + xs, inv);
         }
     }
-    if (CHANNEL && (m & (0x1FFu << M_OPEN)) && t > 0) zou_he(f, j, s.x, s.y, t, u_peak);
+    if (CHANNEL && (m & (0x1FFu << M_OPEN)) && t > 0) {
+        if (j.xbc != UQ_XBC_INTERP)
+            zou_he(f, j, s.x, s.y, t, u_peak);
+        else if (MODE == AB_PULL && FD)
+            fd_column<P>(j, base, s, t, u_peak, omega, f);
+    }
 }
 
 // Scatter post-collision f*(x, t) to where step t+1 reads it.
@@ -323,7 +445,8 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
     if (x >= j.nx) return;
     T *src_all = (T *)(LAYOUT == UQ_LAYOUT_AB && PARITY ? j.f2 : j.f);
     T *dst_all = (T *)(LAYOUT == UQ_LAYOUT_AB && !PARITY ? j.f2 : j.f);
-    const C omega = (C)j.smp[smp].omega;
+    const double omega_d = j.smp[smp].omega;
+    const C omega = (C)omega_d;
     const double u_peak = CHANNEL ? j.smp[smp].u_peak : 0.0;
     const T *src = src_all + smp * 9 * j.plane;
     T *dst = dst_all + smp * 9 * j.plane;
@@ -339,9 +462,12 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
         m[r] = 0;
         if (CHANNEL && live[r]) {
             m[r] = j.mask[(int64_t)y * j.pitch + x];
-            live[r] = !(m[r] & M_SOLID);
+            // solid nodes, and the boundary nodes that k_special updates
+            // (interpolated links, finite-difference open columns), are not
+            // stepped here
+            live[r] = !(m[r] & (M_SOLID | M_SPECIAL));
         }
-        if (live[r]) gather<P, CHANNEL, MODE>(j, src, site(j, x, y), m[r], t, u_peak, f[r]);
+        if (live[r]) gather<P, CHANNEL, MODE, false, false>(j, src, site(j, x, y), m[r], t, u_peak, omega_d, f[r]);
     }
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
@@ -364,6 +490,36 @@ __global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int 
         const int64_t rem = tile - smp * per_sample;
         const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
         tile_update<P, CHANNEL, PARITY, CPT, LAYOUT, NT>(j, t, smp, tx, ty);
+    }
+}
+
+// The boundary nodes of a job with interpolated boundaries (AB layout):
+// nodes with interpolated cylinder links and the open columns of a
+// finite-difference inlet/outlet, listed in j.special; one thread per
+// (listed node, sample): gather with those rules, collide, store. It reads
+// only the source slab and writes only listed nodes of the destination slab,
+// so it and k_step of the same step are independent; keeping these rules
+// out of k_step keeps the bulk kernel's registers and occupancy unchanged.
+template <int P, int PARITY>
+__global__ __launch_bounds__(64) void k_special(JobDev j, const int64_t *d_t, int k) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    const int64_t t = *d_t + k;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= j.n_special) return;
+    const int64_t node = j.special[e];
+    const int y = (int)(node / j.pitch), x = (int)(node - (int64_t)y * j.pitch);
+    const uint32_t m = j.mask[node];
+    const T *src_all = (const T *)(PARITY ? j.f2 : j.f);
+    T *dst_all = (T *)(PARITY ? j.f : j.f2);
+    const Site st = site(j, x, y);
+    for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
+        const SampleDev &sd = j.smp[smp];
+        C f[9], drho, ux, uy;
+        gather<P, true, AB_PULL, true, true>(j, src_all + smp * 9 * j.plane, st, m, t, sd.u_peak, sd.omega, f);
+        bgk(f, (C)sd.omega, drho, ux, uy);
+        scatter<P, true, AB_PULL, false>(j, dst_all + smp * 9 * j.plane, st, m, f);
     }
 }
 
@@ -499,14 +655,33 @@ __global__ __launch_bounds__(256) void k_qoi(JobDev j, int64_t t, double *out) {
         }
         const Site s = site(j, x, y);
         C f[9], drho, ux, uy;
-        gather<P, CHANNEL, MODE>(j, base, s, m, t, sd.u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, sd.u_peak, sd.omega, f);
         if (CHANNEL && (m & (0x1FFu << M_CYL))) {
             bgk(f, (C)sd.omega, drho, ux, uy);
-            for (int i = 1; i < 9; ++i)
-                if (m & (1u << (M_CYL + i))) {
-                    const double fs = (double)f[i] + wgt<double>(i);
-                    fx.add(2.0 * CXd[i] * fs);
-                    fy.add(2.0 * CYd[i] * fs);
+            for (int k = 1; k < 9; ++k)
+                if (m & (1u << (M_CYL + k))) {
+                    // exchange on link k: c_k (f*_k(x) + what the wall returns
+                    // at t+1), both unshifted; half-way: 2 c_k f*_k(x)
+                    const double fk = (double)f[k] + wgt<double>(k);
+                    double back = fk;
+                    if (MODE == AB_PULL && (m & M_QLINK)) {
+                        const int i = OPPd[k];
+                        const double q = j.q[(int64_t)i * j.ny * j.pitch + (int64_t)y * j.pitch + x];
+                        if (q >= 0.5) {
+                            const double a = 1.0 / (2.0 * q);
+                            back = a * fk + (1.0 - a) * ((double)f[i] + wgt<double>(i));
+                        } else if (q > 0.0) {
+                            // f*_k of the node behind, x - c_k = x + c_i
+                            const int xb = sx_of(s, CXd[i]), yb = sy_of(s, CYd[i]);
+                            C g[9], gr, gx, gy;
+                            gather<P, CHANNEL, MODE>(j, base, site(j, xb, yb), j.mask[(int64_t)yb * j.pitch + xb], t,
+                                                     sd.u_peak, sd.omega, g);
+                            bgk(g, (C)sd.omega, gr, gx, gy);
+                            back = 2.0 * q * fk + (1.0 - 2.0 * q) * ((double)g[k] + wgt<double>(k));
+                        }
+                    }
+                    fx.add(CXd[k] * (fk + back));
+                    fy.add(CYd[k] * (fk + back));
                 }
         } else {
             moments(f, drho, ux, uy);
@@ -540,7 +715,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
     const int64_t cells = (int64_t)j.nx * j.ny;
     for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
     const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
-    const double u_peak = j.smp[smp].u_peak;
+    const double u_peak = j.smp[smp].u_peak, omega = j.smp[smp].omega;
     double *o = out + smp * 4 * cells;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
@@ -557,7 +732,7 @@ __global__ __launch_bounds__(256) void k_fields(JobDev j, int64_t t, double *out
         }
         const Site s = site(j, x, y);
         C f[9], drho, ux, uy;
-        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, omega, f);
         moments(f, drho, ux, uy);
         o[c] = (double)ux;
         o[cells + c] = (double)uy;
@@ -575,7 +750,7 @@ __global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp
     using T = typename PR::T;
     const int64_t cells = (int64_t)j.nx * j.ny;
     const T *base = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f) + smp * 9 * j.plane;
-    const double u_peak = j.smp[smp].u_peak;
+    const double u_peak = j.smp[smp].u_peak, omega = j.smp[smp].omega;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
         uint32_t m = 0;
@@ -588,7 +763,7 @@ __global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp
         }
         const Site s = site(j, x, y);
         C f[9];
-        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, f);
+        gather<P, CHANNEL, MODE>(j, base, s, m, t, u_peak, omega, f);
         for (int i = 0; i < 9; ++i) out[i * cells + c] = (double)f[i] + wgt<double>(i);
     }
 }
@@ -680,15 +855,16 @@ __global__ void k_advance(int64_t *d_t, int64_t n) {
 
 // which: UQ_QOI_KE -> KE; UQ_QOI_CD / UQ_QOI_CL -> 2 F/(u_peak^2 D) with the
 // sample's peak inflow velocity and rho0 = 1
-__global__ void k_select(const double *qoi, const SampleDev *smp, int64_t S, int which, int D, double *M) {
+__global__ void k_select(const double *qoi, const SampleDev *smp, int64_t S, int which, double dia, double u_fac,
+                         double *M) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     if (which == UQ_QOI_KE) {
         M[s] = qoi[4 * s];
     } else {
-        const double u = smp[s].u_peak;
+        const double u = u_fac * smp[s].u_peak;
         const double F = which == UQ_QOI_CD ? qoi[4 * s + 1] : qoi[4 * s + 2];
-        M[s] = 2.0 * F / (u * u * (double)D);
+        M[s] = 2.0 * F / (u * u * dia);
     }
 }
 
@@ -796,6 +972,24 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
     dim3 block(bx, by);
     dim3 grid((unsigned)G);
     const bool nt = shape.nt != 0;
+    if (j.n_special > 0) {
+        dim3 og((unsigned)((j.n_special + 63) / 64), (unsigned)std::min<int64_t>(j.S, 65535));
+        const bool odd = parity & 1;
+#define UQ_SPECIAL(PP)                                                       \
+    do {                                                                     \
+        if (odd) k_special<PP, 1><<<og, 64, 0, s>>>(j, d_t, k);              \
+        else k_special<PP, 0><<<og, 64, 0, s>>>(j, d_t, k);                  \
+    } while (0)
+        switch (j.prec) {
+            case UQ_FP64: UQ_SPECIAL(UQ_FP64); break;
+            case UQ_FP32: UQ_SPECIAL(UQ_FP32); break;
+            case UQ_FP16S: UQ_SPECIAL(UQ_FP16S); break;
+            default: UQ_SPECIAL(UQ_BF16S); break;
+        }
+#undef UQ_SPECIAL
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
     else step_cpt<2>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
     return hipGetLastError();
@@ -831,7 +1025,7 @@ hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s) {
-    k_select<<<(unsigned)((j.S + 255) / 256), 256, 0, s>>>(qoi, j.smp, j.S, which, j.D, M);
+    k_select<<<(unsigned)((j.S + 255) / 256), 256, 0, s>>>(qoi, j.smp, j.S, which, j.dia, j.u_fac, M);
     return hipGetLastError();
 }
 

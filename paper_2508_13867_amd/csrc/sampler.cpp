@@ -38,9 +38,32 @@ uq_status validate_problem(const uq_problem &p) {
     if (p.init == UQ_INIT_TGV_HARMONIC && p.geometry != UQ_GEOM_TGV)
         return fail(UQ_EINVAL, "the harmonic initial field is a vortex option");
     if (p.geometry == UQ_GEOM_CHANNEL) {
-        if (p.xbc < UQ_XBC_ZOUHE || p.xbc > UQ_XBC_PERIODIC) return fail(UQ_EINVAL, "unknown xbc");
+        if (p.xbc < UQ_XBC_ZOUHE || p.xbc > UQ_XBC_INTERP) return fail(UQ_EINVAL, "unknown xbc");
         if (p.D < 0) return fail(UQ_EINVAL, "D must be >= 0");
         if (p.ramp < 0) return fail(UQ_EINVAL, "ramp must be >= 0");
+        if (p.cyl_bc != UQ_CYL_HALFWAY && p.cyl_bc != UQ_CYL_BOUZIDI) return fail(UQ_EINVAL, "unknown cyl_bc");
+        if (p.force_ref != UQ_FORCE_REF_PEAK && p.force_ref != UQ_FORCE_REF_MEAN)
+            return fail(UQ_EINVAL, "unknown force_ref");
+        const bool interp = p.xbc == UQ_XBC_INTERP || p.cyl_bc == UQ_CYL_BOUZIDI;
+        if (interp && p.layout == UQ_LAYOUT_AA)
+            return fail(UQ_EINVAL, "interpolated boundaries read neighbours' previous state: they need the AB layout");
+        if (p.xbc == UQ_XBC_INTERP && p.nx < 4) return fail(UQ_EINVAL, "the interpolated inlet/outlet needs nx >= 4");
+        // extent of the cylinder's solid nodes
+        double x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+        if (p.cyl_bc == UQ_CYL_BOUZIDI) {
+            if (!(p.cyl_d > 0) || !std::isfinite(p.cyl_x) || !std::isfinite(p.cyl_y))
+                return fail(UQ_EINVAL, "the interpolated cylinder needs a finite centre and cyl_d > 0");
+            const double r = 0.5 * p.cyl_d;
+            x0 = p.cyl_x - r, x1 = p.cyl_x + r, y0 = p.cyl_y - r, y1 = p.cyl_y + r;
+            if (y0 < 2.0 || y1 > p.ny - 3.0 || x0 < 3.0 || x1 > p.nx - 4.0)
+                return fail(UQ_EINVAL, "the interpolated cylinder must stay 2 nodes inside the walls and 3 nodes "
+                                       "from the x ends");
+        } else if (p.D > 0) {
+            const double r = 0.5 * p.D;
+            x0 = p.cx - r, x1 = p.cx + r, y0 = p.cy - r, y1 = p.cy + r;
+        }
+        if (p.xbc == UQ_XBC_INTERP && x1 >= x0 && (x0 < 3.0 || x1 > p.nx - 4.0))
+            return fail(UQ_EINVAL, "the interpolated inlet/outlet needs the cylinder 3 nodes away from both columns");
     }
     for (int k = 0; k < p.n_dists; ++k) {
         const uq_dist &q = p.dists[k];
@@ -386,8 +409,13 @@ void map_inputs(const uq_problem &p, const double *xi, SampleInputs &o) {
             case UQ_T_ZETA11: o.zeta[3] = v; break;
         }
     }
-    // Re from the peak inflow velocity and the diameter (cylinder section)
-    if (has_re) o.nu = p.u_peak * (double)p.D / re;
+    // Re from the nominal inflow velocity (peak, or the mean 2/3 of it) and
+    // the diameter (cylinder section)
+    if (has_re) {
+        const double U = p.force_ref == UQ_FORCE_REF_MEAN ? p.u_peak * (2.0 / 3.0) : p.u_peak;
+        const double dia = p.cyl_bc == UQ_CYL_BOUZIDI ? p.cyl_d : (double)p.D;
+        o.nu = U * dia / re;
+    }
 }
 
 }  // namespace uqi

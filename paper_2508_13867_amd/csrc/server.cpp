@@ -469,9 +469,12 @@ extern "C" uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t
     if (steps < 0) return fail(UQ_EINVAL, "steps must be >= 0");
     if (qoi != UQ_QOI_KE && qoi != UQ_QOI_CD && qoi != UQ_QOI_CL)
         return fail(UQ_EINVAL, "the server returns scalar QoIs (KE, CD, CL)");
-    if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (p->geometry != UQ_GEOM_CHANNEL || p->D <= 0))
+    if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) &&
+        (p->geometry != UQ_GEOM_CHANNEL || (p->D <= 0 && p->cyl_bc != UQ_CYL_BOUZIDI)))
         return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
     if (p->precision != s->cfg.precision) return fail(UQ_EINVAL, "job precision differs from the server's");
+    if (needs_ab(*p))
+        return fail(UQ_EINVAL, "the server runs the in-place AA layout; interpolated boundaries need a job of their own");
     Rule r;
     uq_status st = build_rule(*p, r);
     if (st != UQ_OK) return st;

@@ -20,6 +20,7 @@ namespace uqi {
 namespace {
 
 // problem class: precision, geometry, lattice, samples, requested layout
+// (interpolated-boundary problems count as a layout request of their own)
 using Key = std::tuple<int, int, int, int, int64_t, int>;
 
 struct Entry {
@@ -31,7 +32,9 @@ std::mutex g_mu;
 std::map<Key, Entry> g_cache;
 bool g_loaded = false;
 
-Key key_of(const uq_problem &p, int64_t S) { return Key(p.precision, p.geometry, p.nx, p.ny, S, p.layout); }
+Key key_of(const uq_problem &p, int64_t S) {
+    return Key(p.precision, p.geometry, p.nx, p.ny, S, needs_ab(p) ? 16 + p.layout : p.layout);
+}
 
 const char *cache_path() {
     const char *v = std::getenv("UQ_TUNE_CACHE");
@@ -100,6 +103,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
     std::vector<StepShape> cands;
     for (int layout : {UQ_LAYOUT_AA, UQ_LAYOUT_AB}) {
         if (p->layout != UQ_LAYOUT_AUTO && p->layout != layout) continue;
+        if (needs_ab(*p) && layout != UQ_LAYOUT_AB) continue;
         for (int bx : {64, 128, 256})
             for (int cpt : {1, 2})
                 for (int pad : {0, 64})

@@ -64,8 +64,13 @@ int64_t row_pitch(int nx) { return ((int64_t)nx + 63) / 64 * 64; }
 // Channel node classification (see M_* bits in uq_internal.h). The pull
 // source of direction i at node x is x - c_i: beyond the walls y = -1/2,
 // ny - 1/2 -> bounce-back; beyond x = -1/2 or nx - 1/2 -> per xbc; a solid
-// cylinder node -> bounce-back.
+// cylinder node -> bounce-back (interpolated for UQ_CYL_BOUZIDI, with the
+// link fraction in q[i][y][pitch]).
 static bool cyl_solid(const uq_problem &p, int x, int y) {
+    if (p.cyl_bc == UQ_CYL_BOUZIDI) {
+        const double dx = x - p.cyl_x, dy = y - p.cyl_y, r = 0.5 * p.cyl_d;
+        return dx * dx + dy * dy <= r * r;
+    }
     if (p.D <= 0) return false;
     const int64_t dx = x - p.cx, dy = y - p.cy;
     return 4 * (dx * dx + dy * dy) <= (int64_t)p.D * p.D;
@@ -74,9 +79,28 @@ static bool cyl_solid(const uq_problem &p, int x, int y) {
 static const int HCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int HCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, int &fluid) {
+// Fraction t in (0, 1] of the link from fluid node (x, y) towards
+// (x, y) - c_i at which it enters the circle: the smaller root of
+// |d - t c_i|^2 = r^2, d = (x, y) - centre, in the cancellation-free form
+// t = (|d|^2 - r^2) / (h + sqrt(h^2 - |c_i|^2 (|d|^2 - r^2))), h = c_i . d.
+static double circle_fraction(const uq_problem &p, int x, int y, int i) {
+    const double dx = x - p.cyl_x, dy = y - p.cyl_y, r = 0.5 * p.cyl_d;
+    const double a = (double)(HCX[i] * HCX[i] + HCY[i] * HCY[i]);
+    const double h = HCX[i] * dx + HCY[i] * dy;
+    const double g = dx * dx + dy * dy - r * r;
+    const double t = g / (h + std::sqrt(std::max(0.0, h * h - a * g)));
+    return std::min(1.0, std::max(t, 1e-12));
+}
+
+void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, std::vector<double> &q,
+                std::vector<int32_t> &special, int &fluid) {
     const int nx = p.nx, ny = p.ny;
+    const bool interp_cyl = p.cyl_bc == UQ_CYL_BOUZIDI;
+    const bool open_x = p.xbc == UQ_XBC_ZOUHE || p.xbc == UQ_XBC_INTERP;
     mask.assign((size_t)ny * pitch, M_SOLID);
+    q.clear();
+    special.clear();
+    if (interp_cyl) q.assign((size_t)9 * ny * pitch, 0.0);
     fluid = 0;
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -88,28 +112,36 @@ void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask,
             ++fluid;
             for (int i = 1; i < 9; ++i) {
                 int sx = x - HCX[i], sy = y - HCY[i];
-                bool bb = false, open = false;
+                bool bb = false, open = false, cyl = false;
                 if (sy < 0 || sy >= ny) {
                     bb = true;
                 } else if (sx < 0 || sx >= nx) {
                     if (p.xbc == UQ_XBC_PERIODIC) {
                         sx = (sx + nx) % nx;
-                        bb = cyl_solid(p, sx, sy);
+                        bb = cyl = cyl_solid(p, sx, sy);
                     } else if (p.xbc == UQ_XBC_WALLS) {
                         bb = true;
                     } else {
                         open = true;
                     }
                 } else {
-                    bb = cyl_solid(p, sx, sy);
+                    bb = cyl = cyl_solid(p, sx, sy);
                 }
                 if (bb) m |= 1u << (M_BB + i);
                 if (open) m |= 1u << (M_OPEN + i);
+                if (cyl && interp_cyl) {
+                    m |= M_QLINK;
+                    q[((size_t)i * ny + y) * pitch + x] = circle_fraction(p, x, y, i);
+                }
                 const int dx = x + HCX[i], dy = y + HCY[i];
                 if (dx >= 0 && dx < nx && dy >= 0 && dy < ny && cyl_solid(p, dx, dy)) m |= 1u << (M_CYL + i);
             }
-            if (p.xbc == UQ_XBC_ZOUHE && x == 0) m |= M_INLET;
-            if (p.xbc == UQ_XBC_ZOUHE && x == nx - 1) m |= M_OUTLET;
+            if (open_x && x == 0) m |= M_INLET;
+            if (open_x && x == nx - 1) m |= M_OUTLET;
+            if ((m & M_QLINK) || (p.xbc == UQ_XBC_INTERP && (m & (M_INLET | M_OUTLET)))) {
+                m |= M_SPECIAL;
+                special.push_back((int32_t)((int64_t)y * pitch + x));
+            }
             mask[(size_t)y * pitch + x] = m;
         }
 }
@@ -197,11 +229,15 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
     }
 
     std::vector<uint32_t> mask;
+    std::vector<double> qlink;
+    std::vector<int32_t> special;
     j->fluid = P.nx * P.ny;
-    if (P.geometry == UQ_GEOM_CHANNEL) build_mask(P, j->pitch, mask, j->fluid);
+    if (P.geometry == UQ_GEOM_CHANNEL) build_mask(P, j->pitch, mask, qlink, special, j->fluid);
 
     // device buffers
     j->shape = forced ? *forced : choose_shape(P, j->S);
+    if (needs_ab(P) && j->shape.layout != UQ_LAYOUT_AB)
+        return fail(UQ_EINVAL, "interpolated boundaries need the AB layout");
     // padding after each population plane (elements, multiple of 64): spreads
     // the nine plane streams of a wavefront over HBM channels
     const int64_t pad = std::max(0, j->shape.pad) / 64 * 64;
@@ -223,9 +259,13 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
         j->dfree_all();
         return fail(UQ_ENOMEM, "out of device memory for the population slab (" + std::to_string(slab_bytes) + " B)");
     }
+    double *d_q = nullptr;
+    int32_t *d_special = nullptr;
     if (!mask.empty()) {
         d_mask = (uint32_t *)j->dalloc(sizeof(uint32_t) * mask.size());
-        if (!d_mask) {
+        if (!qlink.empty()) d_q = (double *)j->dalloc(sizeof(double) * qlink.size());
+        if (!special.empty()) d_special = (int32_t *)j->dalloc(sizeof(int32_t) * special.size());
+        if (!d_mask || (!qlink.empty() && !d_q) || (!special.empty() && !d_special)) {
             j->dfree_all();
             return fail(UQ_ENOMEM, "out of device memory for the boundary mask");
         }
@@ -250,6 +290,10 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
     UQ_HIP_TRY(hipMemcpyAsync(d_smp, smp.data(), sizeof(SampleDev) * j->S, hipMemcpyHostToDevice, j->stream));
     if (d_mask)
         UQ_HIP_TRY(hipMemcpyAsync(d_mask, mask.data(), sizeof(uint32_t) * mask.size(), hipMemcpyHostToDevice, j->stream));
+    if (d_q) UQ_HIP_TRY(hipMemcpyAsync(d_q, qlink.data(), sizeof(double) * qlink.size(), hipMemcpyHostToDevice, j->stream));
+    if (d_special)
+        UQ_HIP_TRY(hipMemcpyAsync(d_special, special.data(), sizeof(int32_t) * special.size(), hipMemcpyHostToDevice,
+                                  j->stream));
     // host vectors above go out of scope: make the copies complete first
     UQ_HIP_TRY(hipStreamSynchronize(j->stream));
 
@@ -275,6 +319,11 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
     jd.ke_norm = uref != 0.0 ? 2.0 / ((double)P.nx * P.ny * uref * uref) : 1.0;
     jd.D = P.D;
     jd.init = P.init;
+    jd.q = d_q;
+    jd.dia = P.cyl_bc == UQ_CYL_BOUZIDI ? P.cyl_d : (double)P.D;
+    jd.u_fac = P.force_ref == UQ_FORCE_REF_MEAN ? 2.0 / 3.0 : 1.0;
+    jd.special = d_special;
+    jd.n_special = (int32_t)special.size();
     j->plane_pad = (int)pad;
 
     UQ_HIP_TRY(launch_init(jd, j->stream));
@@ -363,7 +412,7 @@ uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t 
         if (h[(size_t)(4 * s + 3)] != 0.0)
             return fail(UQ_EUNSTABLE, "sample " + std::to_string(s) + " holds a non-finite value at step " + std::to_string(t));
     if (qoi == UQ_QOI_KE || qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) {
-        if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (P.geometry != UQ_GEOM_CHANNEL || P.D <= 0))
+        if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (P.geometry != UQ_GEOM_CHANNEL || (P.D <= 0 && P.cyl_bc != UQ_CYL_BOUZIDI)))
             return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
         UQ_HIP_TRY(launch_select_scalar(jd, d_qoi, qoi, d_M, stream));
         *M = d_M;

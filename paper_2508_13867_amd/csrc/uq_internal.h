@@ -34,11 +34,16 @@ struct Rule {
 };
 
 uq_status validate_problem(const uq_problem &p);
+// interpolated boundaries (finite-difference inlet/outlet, interpolated
+// cylinder) read neighbours' previous state: AB layout only
+inline bool needs_ab(const uq_problem &p) {
+    return p.geometry == UQ_GEOM_CHANNEL && (p.xbc == UQ_XBC_INTERP || p.cyl_bc == UQ_CYL_BOUZIDI);
+}
 uq_status build_rule(const uq_problem &p, Rule &r);
 
 // Per-sample solver inputs after mapping the reference variables.
 struct SampleInputs {
-    double nu, u0, phase_x, phase_y, u_peak;
+    double nu, u0, phase_x, phase_y, u_peak;  // u_peak: the channel's peak inflow
     double zeta[4];
 };
 void map_inputs(const uq_problem &p, const double *xi_row, SampleInputs &out);
@@ -61,6 +66,10 @@ struct alignas(64) SampleDev {
 //  bit  18     : node is solid
 //  bit  19     : node is on the inlet column, bit 20: outlet column
 //  bits 21..29 : the link x -> x + c_i enters the cylinder (force links)
+//  bit  30     : some bounce-back link of the node is interpolated (the link
+//                fractions are in JobDev::q)
+//  bit  31     : the node is stepped by the boundary-node kernel (interpolated
+//                links, finite-difference open columns), not the bulk kernel
 enum : uint32_t {
     M_BB = 0,
     M_OPEN = 9,
@@ -68,6 +77,8 @@ enum : uint32_t {
     M_INLET = 1u << 19,
     M_OUTLET = 1u << 20,
     M_CYL = 21,
+    M_QLINK = 1u << 30,
+    M_SPECIAL = 1u << 31,
 };
 
 // A job as the kernels see it.
@@ -89,6 +100,13 @@ struct JobDev {
     int32_t layout;         // UQ_LAYOUT_AA or UQ_LAYOUT_AB
     int32_t init;           // uq_init (vortex)
     int32_t pad1;
+    const double *q;        // [9][ny][pitch] interpolated-link fraction of pull
+                            // direction i (0: none); null without such links
+    double dia;             // diameter in C_D, C_L
+    double u_fac;           // their velocity: u_fac * u_peak of the sample
+    const int32_t *special; // [n_special] nodes (y * pitch + x) with M_SPECIAL
+    int32_t n_special;
+    int32_t pad2;
 };
 
 // A job in the continuous-batching table (device memory).

@@ -12,7 +12,8 @@ namespace uqi {
 
 int64_t storage_bytes(int prec);
 int64_t row_pitch(int nx);
-void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, int &fluid);
+void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask, std::vector<double> &q,
+                std::vector<int32_t> &special, int &fluid);
 StepShape choose_shape(const uq_problem &p, int64_t S);
 // tuned shape for a problem class, if one was measured in this process
 bool tuned_shape(const uq_problem &p, int64_t S, StepShape *out);

@@ -40,7 +40,20 @@ CYLINDER_FP32 = dict(
     dists=[("re", 16.0, 24.0), ("u_peak", 0.045, 0.055)], rule=dict(kind="gl", n=8, order=7),
 )
 
-WORKLOADS = {w["name"]: w for w in (TGV_SMALL_FP64, TGV_BATCHED_FP32, TGV_MC, CYLINDER_FP32)}
+# The paper's own cylinder set-up (Sec. "Flow past a circular cylinder with
+# uncertain inlet velocity", Table tab:uq_results at n_x = 20): channel 22D x
+# 4D with D = 20 nodes (walls half-way outside rows 0 and 79), the exact
+# circle at (2D, (ny-1)/2) with interpolated bounce-back, finite-difference
+# inlet/outlet, u_in(xi) = u(1 + 0.2 xi) (0.2 +- 0.04 relative), Re = 20 at
+# the nominal inflow with nu fixed, C_D and Re on the mean inflow velocity
+# (lattice mean 0.04, peak 0.06), 11-node Gauss-Legendre collocation.
+CYLINDER_PAPER_FP32 = dict(
+    name="cyl440x80_paper_fp32", geometry="channel", precision="fp32", nx=440, ny=80, steps=40000,
+    u_peak=0.06, nu=0.04, cyl_bc="bouzidi", cyl_x=40.0, cyl_y=39.5, cyl_d=20.0, ramp=4000, xbc="interp",
+    force_ref="mean", layout="ab", dists=[("u_peak", 0.048, 0.072)], rule=dict(kind="gl", n=11, order=10),
+)
+
+WORKLOADS = {w["name"]: w for w in (TGV_SMALL_FP64, TGV_BATCHED_FP32, TGV_MC, CYLINDER_FP32, CYLINDER_PAPER_FP32)}
 
 
 def scaled(spec, **over):
