@@ -349,27 +349,40 @@ template <int P, bool CHANNEL, int MODE, bool FD, bool QL>
 __device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
                               int64_t t, double u_peak, double omega, typename Prec<P>::C f[9]) {
     using PR = Prec<P>;
+    using C = typename PR::C;
     const float inv = j.inv_scale;
     const int64_t pitch = j.pitch, plane = j.plane;
     const int64_t own = (int64_t)s.y * pitch + s.x;
+    // Every direction issues its one load unconditionally, the wall rule only
+    // selecting the address: with no branches between them all nine loads
+    // are in flight together (per-direction branches made the compiler wait
+    // for each load at the block boundaries).
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         if (MODE == AA_EVEN) {
             f[i] = PR::ld(base + i * plane + own, inv);
-        } else if (CHANNEL && (m & (1u << (M_BB + i)))) {
-            // bounce-back: f_i(x,t) = f*_opp(i)(x,t-1), stored at this node
-            // (AA odd: in slot i; AB: in slot opp(i)); interpolated links
-            // (AB only) combine it with a second value
-            if (MODE == AB_PULL && QL && (m & M_QLINK))
-                f[i] = wall_return<P>(j, base, s, own, i);
-            else
-                f[i] = PR::ld(base + (MODE == AA_ODD ? i : OPPd[i]) * plane + own, inv);
-        } else if (CHANNEL && (m & (1u << (M_OPEN + i)))) {
-            f[i] = 0;  // rest state at t = 0, else filled below
-        } else {
-            const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
-            f[i] = PR::ld(base + (MODE == AA_ODD ? OPPd[i] : i) * plane + (int64_t)ys * pitch + xs, inv);
+            continue;
         }
+        // pull: f_i(x,t) = f*_i(x - c_i, t-1) (AA odd: slot opp(i) there;
+        // AB: slot i); bounce-back: f*_opp(i)(x, t-1) at this node (AA odd:
+        // slot i; AB: slot opp(i))
+        const int xs = sx_of(s, -CXd[i]), ys = sy_of(s, -CYd[i]);
+        int64_t off = (int64_t)(MODE == AA_ODD ? OPPd[i] : i) * plane + (int64_t)ys * pitch + xs;
+        bool bb = false;
+        if (CHANNEL) {
+            bb = (m >> (M_BB + i)) & 1u;
+            const int64_t off_bb = (int64_t)(MODE == AA_ODD ? i : OPPd[i]) * plane + own;
+            off = bb ? off_bb : off;
+        }
+        C v = PR::ld(base + off, inv);
+        if (CHANNEL) {
+            // interpolated links (AB only) combine it with a second value
+            if (MODE == AB_PULL && QL && bb && (m & M_QLINK)) v = wall_return<P>(j, base, s, own, i);
+            // beyond an open column: rest state at t = 0, else filled below
+            // (the wrapped pull address is in bounds; its value is unused)
+            v = ((m >> (M_OPEN + i)) & 1u) ? C(0) : v;
+        }
+        f[i] = v;
     }
     if (CHANNEL && (m & (0x1FFu << M_OPEN)) && t > 0) {
         if (j.xbc != UQ_XBC_INTERP)
@@ -397,16 +410,19 @@ __device__ inline void scatter(const JobDev &j, typename Prec<P>::T *base, const
         } else if (MODE == AA_EVEN) {
             PR::st(base + OPPd[i] * plane + own, f[i], sc);
         } else {
+            // AA odd: f*_i goes to slot i of x + c_i; if that is a wall it
+            // returns to this node as f_opp(i) (slot opp(i) here). A value
+            // leaving through an open column is parked in that same own slot,
+            // which nothing else writes and the next gather overrides (no
+            // branch: the stores stay back to back).
             const int o = OPPd[i];
-            if (CHANNEL && (m & (1u << (M_BB + o)))) {
-                // destination is a wall: f*_i returns to this node as f_opp(i)
-                PR::st(base + o * plane + own, f[i], sc);
-            } else if (CHANNEL && (m & (1u << (M_OPEN + o)))) {
-                // leaves through an open column
-            } else {
-                const int xd = sx_of(s, CXd[i]), yd = sy_of(s, CYd[i]);
-                PR::st(base + i * plane + (int64_t)yd * pitch + xd, f[i], sc);
+            const int xd = sx_of(s, CXd[i]), yd = sy_of(s, CYd[i]);
+            int64_t off = (int64_t)i * plane + (int64_t)yd * pitch + xd;
+            if (CHANNEL) {
+                const bool back = ((m >> (M_BB + o)) | (m >> (M_OPEN + o))) & 1u;
+                off = back ? (int64_t)o * plane + own : off;
             }
+            PR::st(base + off, f[i], sc);
         }
     }
 }

@@ -53,7 +53,12 @@ CYLINDER_PAPER_FP32 = dict(
     force_ref="mean", layout="ab", dists=[("u_peak", 0.048, 0.072)], rule=dict(kind="gl", n=11, order=10),
 )
 
-WORKLOADS = {w["name"]: w for w in (TGV_SMALL_FP64, TGV_BATCHED_FP32, TGV_MC, CYLINDER_FP32, CYLINDER_PAPER_FP32)}
+# the same with 1000 Monte Carlo samples: the batched form of that study
+CYLINDER_PAPER_MC_FP32 = dict(CYLINDER_PAPER_FP32, name="cyl440x80_paper_mc1000_fp32",
+                              rule=dict(kind="mc", N=1000, seed=SEED))
+
+WORKLOADS = {w["name"]: w for w in (TGV_SMALL_FP64, TGV_BATCHED_FP32, TGV_MC, CYLINDER_FP32, CYLINDER_PAPER_FP32,
+                                    CYLINDER_PAPER_MC_FP32)}
 
 
 def scaled(spec, **over):
