@@ -73,7 +73,7 @@ uq_status Job::advance(int64_t steps) {
     const int L = env_int("UQ_GRAPH_STEPS", 64) & ~1;
     if (use_graph && L >= 2 && steps >= L + 1) {
         if (t & 1) {
-            UQ_HIP_TRY(launch_step(jd, d_t, 0, 1, shape, stream));
+            UQ_HIP_TRY(launch_step(jd, d_t, 0, 1, shape, stream, &side));
             UQ_HIP_TRY(launch_advance(d_t, 1, stream));
             t += 1;
             steps -= 1;
@@ -82,7 +82,7 @@ uq_status Job::advance(int64_t steps) {
             release_graph();
             UQ_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
-            for (int k = 0; k < L && e == hipSuccess; ++k) e = launch_step(jd, d_t, k, k & 1, shape, stream);
+            for (int k = 0; k < L && e == hipSuccess; ++k) e = launch_step(jd, d_t, k, k & 1, shape, stream, &side);
             if (e == hipSuccess) e = launch_advance(d_t, L, stream);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(stream, &g);
@@ -103,7 +103,7 @@ uq_status Job::advance(int64_t steps) {
     }
     if (steps > 0) {
         for (int64_t k = 0; k < steps; ++k)
-            UQ_HIP_TRY(launch_step(jd, d_t, (int)k, (int)((t + k) & 1), shape, stream));
+            UQ_HIP_TRY(launch_step(jd, d_t, (int)k, (int)((t + k) & 1), shape, stream, &side));
         UQ_HIP_TRY(launch_advance(d_t, steps, stream));
         t += steps;
     }
@@ -114,8 +114,12 @@ Job::~Job() {
     if (stream) (void)hipStreamSynchronize(stream);
     release_graph();
     dfree_all();
+    if (side.stream) (void)hipStreamSynchronize(side.stream);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (side.fork) (void)hipEventDestroy(side.fork);
+    if (side.join) (void)hipEventDestroy(side.join);
+    if (side.stream) (void)hipStreamDestroy(side.stream);
     if (stream) (void)hipStreamDestroy(stream);
 }
 

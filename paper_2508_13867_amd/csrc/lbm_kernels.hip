@@ -297,14 +297,12 @@ __device__ inline void node_u(const JobDev &j, const typename Prec<P>::T *base, 
 // (-3 u_0 + 4 u_1 - u_2)/2 into the fluid; along it the central difference,
 // one-sided at the two end rows. Inlet: u prescribed, rho from the known
 // populations; outlet: rho = 1, u_y = 0, u_x from the known populations.
-template <int P>
-__device__ inline void fd_column(const JobDev &j, const typename Prec<P>::T *base, const Site &s, int64_t t,
-                                 double u_peak, double omega, typename Prec<P>::C f[9]) {
-    using C = typename Prec<P>::C;
-    const int x = s.x, y = s.y, ny = j.ny;
-    const bool inlet = x == 0;
-    const int sd = inlet ? 1 : -1;
-    double rho, ux, uy = 0.0;
+
+// imposed state of an open-column node from its streamed populations
+// (unknown ones unset)
+template <typename C>
+__device__ inline void fd_state(const JobDev &j, const C f[9], bool inlet, int y, int64_t t, double u_peak,
+                                double &rho, double &ux) {
     if (inlet) {
         ux = inlet_ux(j, y, t, u_peak);
         const double S = (double)((f[0] + f[2] + f[4]) + (f[3] + f[6] + f[7]) + (f[3] + f[6] + f[7]));
@@ -313,24 +311,20 @@ __device__ inline void fd_column(const JobDev &j, const typename Prec<P>::T *bas
         rho = 1.0;
         ux = (double)((f[0] + f[2] + f[4]) + (f[1] + f[5] + f[8]) + (f[1] + f[5] + f[8]));
     }
-    // across the column
-    double u1x, u1y, u2x, u2y;
-    node_u<P>(j, base, x + sd, y, t, u_peak, omega, u1x, u1y);
-    node_u<P>(j, base, x + 2 * sd, y, t, u_peak, omega, u2x, u2y);
-    const double dxux = sd * (-3.0 * ux + 4.0 * u1x - u2x) * 0.5;
-    const double dxuy = sd * (-3.0 * uy + 4.0 * u1y - u2y) * 0.5;
-    // along the column (u_y = 0 on both columns)
-    auto col_ux = [&](int yy) {
-        return inlet ? inlet_ux(j, yy, t, u_peak) : outlet_ux<P>(j, base, x, yy, t, u_peak, omega);
-    };
-    double dyux;
-    if (y == 0)
-        dyux = (-3.0 * ux + 4.0 * col_ux(1) - col_ux(2)) * 0.5;
-    else if (y == ny - 1)
-        dyux = (3.0 * ux - 4.0 * col_ux(ny - 2) + col_ux(ny - 3)) * 0.5;
-    else
-        dyux = (col_ux(y + 1) - col_ux(y - 1)) * 0.5;
-    const double dyuy = 0.0;
+}
+
+// d(u_x)/dy along the column from the column values at y-2 .. y+2
+// (um2, um1, u0, up1, up2; only those inside the column are read)
+__device__ inline double fd_dy(int y, int ny, double um2, double um1, double u0, double up1, double up2) {
+    if (y == 0) return (-3.0 * u0 + 4.0 * up1 - up2) * 0.5;
+    if (y == ny - 1) return (3.0 * u0 - 4.0 * um1 + um2) * 0.5;
+    return (up1 - um1) * 0.5;
+}
+
+// f = f^eq + f^neq from the imposed state and the gradient (u_y = 0)
+template <typename C>
+__device__ inline void fd_rebuild(C f[9], double rho, double ux, double dxux, double dxuy, double dyux, double omega) {
+    const double uy = 0.0, dyuy = 0.0;
     const double tau = 1.0 / omega, drho = rho - 1.0, uu = ux * ux + uy * uy;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -339,6 +333,34 @@ __device__ inline void fd_column(const JobDev &j, const typename Prec<P>::T *bas
         const double QS = (cx * cx - 1.0 / 3.0) * dxux + (cy * cy - 1.0 / 3.0) * dyuy + cx * cy * (dxuy + dyux);
         f[i] = (C)(w * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)) - 3.0 * w * rho * tau * QS);
     }
+}
+
+// the whole reconstruction for one node, neighbours gathered here (QoI and
+// export kernels; the step uses k_fd_columns, which shares them in LDS)
+template <int P>
+__device__ inline void fd_column(const JobDev &j, const typename Prec<P>::T *base, const Site &s, int64_t t,
+                                 double u_peak, double omega, typename Prec<P>::C f[9]) {
+    const int x = s.x, y = s.y, ny = j.ny;
+    const bool inlet = x == 0;
+    const int sd = inlet ? 1 : -1;
+    double rho, ux;
+    fd_state(j, f, inlet, y, t, u_peak, rho, ux);
+    double u1x, u1y, u2x, u2y;
+    node_u<P>(j, base, x + sd, y, t, u_peak, omega, u1x, u1y);
+    node_u<P>(j, base, x + 2 * sd, y, t, u_peak, omega, u2x, u2y);
+    const double dxux = sd * (-3.0 * ux + 4.0 * u1x - u2x) * 0.5;
+    const double dxuy = sd * (-3.0 * 0.0 + 4.0 * u1y - u2y) * 0.5;
+    auto col_ux = [&](int yy) {
+        return inlet ? inlet_ux(j, yy, t, u_peak) : outlet_ux<P>(j, base, x, yy, t, u_peak, omega);
+    };
+    double dyux;
+    if (y == 0)
+        dyux = fd_dy(y, ny, 0.0, 0.0, ux, col_ux(1), col_ux(2));
+    else if (y == ny - 1)
+        dyux = fd_dy(y, ny, col_ux(ny - 3), col_ux(ny - 2), ux, 0.0, 0.0);
+    else
+        dyux = fd_dy(y, ny, 0.0, col_ux(y - 1), ux, col_ux(y + 1), 0.0);
+    fd_rebuild(f, rho, ux, dxux, dxuy, dyux, omega);
 }
 
 // Gather f~(x, t) of one node, with the wall rules and the open columns
@@ -478,9 +500,9 @@ __device__ inline void tile_update(const JobDev &j, int64_t t, int64_t smp, int 
         m[r] = 0;
         if (CHANNEL && live[r]) {
             m[r] = j.mask[(int64_t)y * j.pitch + x];
-            // solid nodes, and the boundary nodes that k_special updates
-            // (interpolated links, finite-difference open columns), are not
-            // stepped here
+            // solid nodes, and the boundary nodes that k_qlinks and
+            // k_fd_columns update (interpolated links, finite-difference
+            // open columns), are not stepped here
             live[r] = !(m[r] & (M_SOLID | M_SPECIAL));
         }
         if (live[r]) gather<P, CHANNEL, MODE, false, false>(j, src, site(j, x, y), m[r], t, u_peak, omega_d, f[r]);
@@ -509,15 +531,16 @@ __global__ __launch_bounds__(256) void k_step(JobDev j, const int64_t *d_t, int 
     }
 }
 
-// The boundary nodes of a job with interpolated boundaries (AB layout):
-// nodes with interpolated cylinder links and the open columns of a
-// finite-difference inlet/outlet, listed in j.special; one thread per
-// (listed node, sample): gather with those rules, collide, store. It reads
-// only the source slab and writes only listed nodes of the destination slab,
-// so it and k_step of the same step are independent; keeping these rules
-// out of k_step keeps the bulk kernel's registers and occupancy unchanged.
+// Boundary nodes of jobs with interpolated boundaries (AB layout), stepped
+// apart from k_step so that the bulk kernel keeps its registers and
+// occupancy. Both kernels below read only the source slab and write only
+// their own nodes of the destination slab, so they and k_step of the same
+// step are independent.
+//
+// Nodes with interpolated cylinder links (listed in j.special), one thread
+// per (node, sample): gather with the interpolation, collide, store.
 template <int P, int PARITY>
-__global__ __launch_bounds__(64) void k_special(JobDev j, const int64_t *d_t, int k) {
+__global__ __launch_bounds__(64) void k_qlinks(JobDev j, const int64_t *d_t, int k) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
@@ -533,9 +556,76 @@ __global__ __launch_bounds__(64) void k_special(JobDev j, const int64_t *d_t, in
     for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
         const SampleDev &sd = j.smp[smp];
         C f[9], drho, ux, uy;
-        gather<P, true, AB_PULL, true, true>(j, src_all + smp * 9 * j.plane, st, m, t, sd.u_peak, sd.omega, f);
+        gather<P, true, AB_PULL, false, true>(j, src_all + smp * 9 * j.plane, st, m, t, sd.u_peak, sd.omega, f);
         bgk(f, (C)sd.omega, drho, ux, uy);
         scatter<P, true, AB_PULL, false>(j, dst_all + smp * 9 * j.plane, st, m, f);
+    }
+}
+
+// The two open columns of a finite-difference inlet/outlet. One workgroup
+// per (column, chunk of FD_ROWS rows, sample); its threads gather, one node
+// each, the column node and the two nodes next to it into the fluid, for the
+// chunk's rows plus two halo rows on each side, and share the velocities
+// through LDS; the column threads then rebuild, collide and store.
+constexpr int FD_RB = 85, FD_HALO = 2, FD_ROWS = FD_RB - 2 * FD_HALO, FD_BLOCK = 256;
+
+template <int P, int PARITY>
+__global__ __launch_bounds__(FD_BLOCK) void k_fd_columns(JobDev j, const int64_t *d_t, int k) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    __shared__ double ub[FD_RB], u1x[FD_RB], u1y[FD_RB], u2x[FD_RB], u2y[FD_RB];
+    const int64_t t = *d_t + k;
+    const int chunks = (j.ny + FD_ROWS - 1) / FD_ROWS;
+    const bool inlet = (int)blockIdx.x < chunks;
+    const int chunk = inlet ? (int)blockIdx.x : (int)blockIdx.x - chunks;
+    const int tid = threadIdx.x;
+    const int c = tid / FD_RB, r = tid - c * FD_RB;  // c: 0 the column, 1 and 2 into the fluid
+    const int x = inlet ? c : j.nx - 1 - c;
+    const int y = chunk * FD_ROWS - FD_HALO + r;
+    const bool valid = c < 3 && y >= 0 && y < j.ny;
+    const bool own = valid && c == 0 && r >= FD_HALO && r < FD_RB - FD_HALO;
+    const uint32_t m = valid ? j.mask[(int64_t)y * j.pitch + x] : 0u;
+    const T *src_all = (const T *)(PARITY ? j.f2 : j.f);
+    T *dst_all = (T *)(PARITY ? j.f : j.f2);
+    for (int64_t smp = blockIdx.y; smp < j.S; smp += gridDim.y) {
+        const SampleDev &sd = j.smp[smp];
+        const T *src = src_all + smp * 9 * j.plane;
+        C f[9];
+        double rho = 1.0, ux = 0.0;
+        if (valid) {
+            const Site st = site(j, x, y);
+            if (c == 0) {
+                gather<P, true, AB_PULL, false, false>(j, src, st, m, t, sd.u_peak, sd.omega, f);
+                fd_state(j, f, inlet, y, t, sd.u_peak, rho, ux);
+                ub[r] = ux;
+            } else {
+                C drho, gx, gy;
+                gather<P, true, AB_PULL, false, true>(j, src, st, m, t, sd.u_peak, sd.omega, f);
+                moments(f, drho, gx, gy);
+                if (c == 1) {
+                    u1x[r] = (double)gx;
+                    u1y[r] = (double)gy;
+                } else {
+                    u2x[r] = (double)gx;
+                    u2y[r] = (double)gy;
+                }
+            }
+        }
+        __syncthreads();
+        if (own) {
+            if (t > 0) {  // the state at t = 0 is the rest state as gathered
+                const double sdx = inlet ? 1.0 : -1.0;
+                const double dyux = fd_dy(y, j.ny, ub[r - 2], ub[r - 1], ux, ub[r + 1], ub[r + 2]);
+                const double dxux = sdx * (-3.0 * ux + 4.0 * u1x[r] - u2x[r]) * 0.5;
+                const double dxuy = sdx * (-3.0 * 0.0 + 4.0 * u1y[r] - u2y[r]) * 0.5;
+                fd_rebuild(f, rho, ux, dxux, dxuy, dyux, sd.omega);
+            }
+            C drho, gx, gy;
+            bgk(f, (C)sd.omega, drho, gx, gy);
+            scatter<P, true, AB_PULL, false>(j, dst_all + smp * 9 * j.plane, site(j, x, y), m, f);
+        }
+        __syncthreads();  // the LDS rows are reused by the next sample
     }
 }
 
@@ -975,7 +1065,7 @@ static void step_cpt(const JobDev &j, const int64_t *d_t, int k, int parity, boo
 }
 
 hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
-                       hipStream_t s) {
+                       hipStream_t s_main, const SideStream *side) {
     const int cpt = shape.cpt <= 1 ? 1 : 2;
     const int bx = shape.bx == 128 || shape.bx == 256 ? shape.bx : BX;
     const int by = 256 / bx;
@@ -988,27 +1078,59 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
     dim3 block(bx, by);
     dim3 grid((unsigned)G);
     const bool nt = shape.nt != 0;
+    const bool odd = parity & 1;
+    const unsigned gs = (unsigned)std::min<int64_t>(j.S, 65535);
+    const bool fd_cols = j.geom == 1 && j.xbc == UQ_XBC_INTERP && j.layout == UQ_LAYOUT_AB;
+    // boundary-node kernels: on the side stream when there is one
+    hipStream_t s = s_main;
+    if ((j.n_special > 0 || fd_cols) && side && side->stream) {
+        hipError_t e = hipEventRecord(side->fork, s_main);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+        if (e != hipSuccess) return e;
+        s = side->stream;
+    }
     if (j.n_special > 0) {
-        dim3 og((unsigned)((j.n_special + 63) / 64), (unsigned)std::min<int64_t>(j.S, 65535));
-        const bool odd = parity & 1;
-#define UQ_SPECIAL(PP)                                                       \
-    do {                                                                     \
-        if (odd) k_special<PP, 1><<<og, 64, 0, s>>>(j, d_t, k);              \
-        else k_special<PP, 0><<<og, 64, 0, s>>>(j, d_t, k);                  \
+        dim3 og((unsigned)((j.n_special + 63) / 64), gs);
+#define UQ_QL(PP)                                                        \
+    do {                                                                 \
+        if (odd) k_qlinks<PP, 1><<<og, 64, 0, s>>>(j, d_t, k);           \
+        else k_qlinks<PP, 0><<<og, 64, 0, s>>>(j, d_t, k);               \
     } while (0)
         switch (j.prec) {
-            case UQ_FP64: UQ_SPECIAL(UQ_FP64); break;
-            case UQ_FP32: UQ_SPECIAL(UQ_FP32); break;
-            case UQ_FP16S: UQ_SPECIAL(UQ_FP16S); break;
-            default: UQ_SPECIAL(UQ_BF16S); break;
+            case UQ_FP64: UQ_QL(UQ_FP64); break;
+            case UQ_FP32: UQ_QL(UQ_FP32); break;
+            case UQ_FP16S: UQ_QL(UQ_FP16S); break;
+            default: UQ_QL(UQ_BF16S); break;
         }
-#undef UQ_SPECIAL
+#undef UQ_QL
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
-    else step_cpt<2>(j, d_t, k, parity & 1, nt, grid, block, s, tiles_x, tiles_y, ntiles);
-    return hipGetLastError();
+    if (fd_cols) {
+        dim3 fg((unsigned)(2 * ((j.ny + FD_ROWS - 1) / FD_ROWS)), gs);
+#define UQ_FDC(PP)                                                                  \
+    do {                                                                            \
+        if (odd) k_fd_columns<PP, 1><<<fg, FD_BLOCK, 0, s>>>(j, d_t, k);             \
+        else k_fd_columns<PP, 0><<<fg, FD_BLOCK, 0, s>>>(j, d_t, k);                 \
+    } while (0)
+        switch (j.prec) {
+            case UQ_FP64: UQ_FDC(UQ_FP64); break;
+            case UQ_FP32: UQ_FDC(UQ_FP32); break;
+            case UQ_FP16S: UQ_FDC(UQ_FP16S); break;
+            default: UQ_FDC(UQ_BF16S); break;
+        }
+#undef UQ_FDC
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (cpt == 1) step_cpt<1>(j, d_t, k, parity & 1, nt, grid, block, s_main, tiles_x, tiles_y, ntiles);
+    else step_cpt<2>(j, d_t, k, parity & 1, nt, grid, block, s_main, tiles_x, tiles_y, ntiles);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && s != s_main) {
+        e = hipEventRecord(side->join, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s_main, side->join, 0);
+    }
+    return e;
 }
 
 hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s) {

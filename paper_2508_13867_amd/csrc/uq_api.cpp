@@ -138,10 +138,10 @@ void build_mask(const uq_problem &p, int64_t pitch, std::vector<uint32_t> &mask,
             }
             if (open_x && x == 0) m |= M_INLET;
             if (open_x && x == nx - 1) m |= M_OUTLET;
-            if ((m & M_QLINK) || (p.xbc == UQ_XBC_INTERP && (m & (M_INLET | M_OUTLET)))) {
-                m |= M_SPECIAL;
-                special.push_back((int32_t)((int64_t)y * pitch + x));
-            }
+            // boundary nodes stepped by their own kernels: interpolated links
+            // (listed) and finite-difference open columns (whole columns)
+            if (m & M_QLINK) special.push_back((int32_t)((int64_t)y * pitch + x));
+            if ((m & M_QLINK) || (p.xbc == UQ_XBC_INTERP && (m & (M_INLET | M_OUTLET)))) m |= M_SPECIAL;
             mask[(size_t)y * pitch + x] = m;
         }
 }
@@ -193,6 +193,11 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
     UQ_HIP_TRY(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
     UQ_HIP_TRY(hipEventCreateWithFlags(&j->ev_in, hipEventDisableTiming));
     UQ_HIP_TRY(hipEventCreateWithFlags(&j->ev_out, hipEventDisableTiming));
+    if (needs_ab(P)) {
+        UQ_HIP_TRY(hipStreamCreateWithFlags(&j->side.stream, hipStreamNonBlocking));
+        UQ_HIP_TRY(hipEventCreateWithFlags(&j->side.fork, hipEventDisableTiming));
+        UQ_HIP_TRY(hipEventCreateWithFlags(&j->side.join, hipEventDisableTiming));
+    }
     {
         uq_status e = j->enter();
         if (e != UQ_OK) return e;

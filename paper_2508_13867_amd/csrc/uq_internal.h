@@ -68,7 +68,7 @@ struct alignas(64) SampleDev {
 //  bits 21..29 : the link x -> x + c_i enters the cylinder (force links)
 //  bit  30     : some bounce-back link of the node is interpolated (the link
 //                fractions are in JobDev::q)
-//  bit  31     : the node is stepped by the boundary-node kernel (interpolated
+//  bit  31     : the node is stepped by a boundary-node kernel (interpolated
 //                links, finite-difference open columns), not the bulk kernel
 enum : uint32_t {
     M_BB = 0,
@@ -104,7 +104,7 @@ struct JobDev {
                             // direction i (0: none); null without such links
     double dia;             // diameter in C_D, C_L
     double u_fac;           // their velocity: u_fac * u_peak of the sample
-    const int32_t *special; // [n_special] nodes (y * pitch + x) with M_SPECIAL
+    const int32_t *special; // [n_special] nodes (y * pitch + x) with M_QLINK
     int32_t n_special;
     int32_t pad2;
 };
@@ -131,8 +131,15 @@ struct StepShape {
 // one stream-collide step for all samples at time t = *d_t + k; `parity`
 // must equal t & 1 (the host keeps a mirror of t)
 hipError_t launch_init(const JobDev &j, hipStream_t s);
+// A second stream for the boundary-node kernels (interpolated links,
+// finite-difference columns): they run beside k_step of the same step,
+// forked from and joined back into the main stream with the two events.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
 hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, const StepShape &shape,
-                       hipStream_t s);
+                       hipStream_t s, const SideStream *side = nullptr);
 // one step of every job in a table (AA layout, one row per thread); all jobs
 // must share precision `prec`
 hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s);

@@ -32,6 +32,7 @@ struct Job {
     hipStream_t user_stream = nullptr;  // caller's stream (ordering only)
     hipStream_t stream = nullptr;       // the job's own work stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    SideStream side;                    // boundary-node kernels (AB channel jobs)
 
     JobDev jd{};
     StepShape shape{};
