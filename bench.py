@@ -129,16 +129,18 @@ def study_precision(U, W, log, oracle_samples=8):
         with U.Job(spec) as job:
             inf = job.info()
             ms = job.run_timed(spec["steps"])
+            launches = job.info().step_launches
             st = job.moments("ke")
             ke[prec] = job.qoi_samples("ke")[:, 0]
         nodes = job.S * spec["nx"] * spec["ny"]
-        bpn = 18 * BYTES_PER_POP[prec]
-        launch_ms = ms / spec["steps"]
+        bpn = 18 * BYTES_PER_POP[prec]  # per node per launch (read + write once)
+        launch_ms = ms / launches
         out["runs"][prec] = {"mean": st["mean"][0], "var": st["var"][0],
                              "mlups": round(nodes * spec["steps"] / (ms * 1e-3) / 1e6, 1),
                              "gbs": round(nodes * bpn / (launch_ms * 1e-3) / 1e9, 1),
                              "frac_hbm": round(nodes * bpn / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                             "bytes_per_node_update": bpn, "layout": {1: "aa", 2: "ab"}[inf.layout],
+                             "bytes_per_node_update": round(bpn * launches / spec["steps"], 3),
+                             "steps_per_launch": inf.fused or 1, "layout": {1: "aa", 2: "ab"}[inf.layout],
                              "scale_exp": inf.scale_exp, "tuned_gbs": round(tune["gbs"], 1)}
         log(f"bench: precision {prec}: {out['runs'][prec]}")
     r64 = out["runs"]["fp64"]
@@ -458,15 +460,17 @@ def main():
         job = U.Job(spec, device=0)
         inf = job.info()
         launch.update(layout={1: "aa", 2: "ab"}[inf.layout], cpt=inf.cpt, nt_store=inf.nt_store,
-                      plane_pad=inf.plane_pad, bx=inf.bx, device_bytes=inf.device_bytes)
+                      plane_pad=inf.plane_pad, bx=inf.bx, fused_steps=inf.fused, fused_rows=inf.fused_rows,
+                      device_bytes=inf.device_bytes)
         ms = job.run_timed(spec["steps"]) if timed_kernel else None
         if not timed_kernel:
             job.run(spec["steps"])
+        launches = job.info().step_launches
         job.moments("ke")
         job.moments("vel")
         S = job.S
         job.close()
-        return S, ms
+        return S, ms, launches
 
     log(f"bench: workload {spec['name']} warmup {args.warmup} jobs")
     for _ in range(args.warmup):
@@ -477,10 +481,12 @@ def main():
     kernel_ms = []
     t0 = time.perf_counter()
     S = 0
+    n_launch = []
     for k in range(args.steps):
-        S, ms = one_job(True)
+        S, ms, nl = one_job(True)
         kernel_ms.append(ms)
-        log(f"bench: job {k} done, step launches {ms:.1f} ms")
+        n_launch.append(nl)
+        log(f"bench: job {k} done, {nl} step launches, {ms:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
@@ -489,17 +495,22 @@ def main():
     mlups = updates / wall / 1e6
     ms_per_job = wall / args.steps * 1e3
 
-    # dominant kernel: one step launch updates S * cells nodes, 9 populations
-    # read + 9 written per node
+    # dominant kernel: every step launch (single or fused) reads the 9
+    # populations of each of the S * cells nodes once and writes them once;
+    # a fused launch advances them `fused_steps` steps
     bpn = 18 * BYTES_PER_POP[prec]
-    per_launch_ms = sum(kernel_ms) / (args.steps * spec["steps"])
+    launches = sum(n_launch)
+    per_launch_ms = sum(kernel_ms) / launches
     alg_bytes = S * cells * bpn
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    nfuse = launch.get("fused_steps", 0) or 1
     traffic = measured_traffic(alg_bytes)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "uqi::k_step", "bytes_per_launch": alg_bytes, "launch_ms": round(per_launch_ms, 5),
-            "bytes_per_node_update": bpn, "copy_gbs": round(copy_gbs, 1),
+            "kernel": f"uqi::k_stepN<..., N={nfuse}>" if nfuse > 1 else "uqi::k_step",
+            "bytes_per_launch": alg_bytes, "updates_per_node_per_launch": nfuse,
+            "bytes_per_node_update": round(bpn / nfuse, 3), "launches": launches,
+            "launch_ms": round(per_launch_ms, 5), "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     out = {

@@ -285,6 +285,12 @@ typedef struct {
     int32_t nt_store;   /* 1 if AB stores bypass the caches            */
     int32_t plane_pad;  /* padding elements after each population plane */
     int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
+    int32_t fused;      /* steps per launch of the fused periodic AB
+                           kernel (2..4), 0 if not fused               */
+    int32_t fused_rows; /* its tile height (rows of 64 nodes)          */
+    int64_t step_launches; /* step-kernel launches so far (a fused launch
+                              counts once: each launch reads and writes
+                              every population of every sample once)  */
 } uq_job_info;
 
 /* Set up a job: sample the inputs, map each sample to its solver parameters,
@@ -338,9 +344,12 @@ const char *uq_last_error(void);
  * lattice and sample count) for every candidate shape -- layout AA or AB
  * (only the problem's layout unless it is UQ_LAYOUT_AUTO), workgroups of
  * 64 x 4, 128 x 2 or 256 x 1 threads, 1 or 2 rows per thread, plane padding
- * 0 or 64 elements, cached or non-temporal AB stores --
- * over `steps` steps each (rounded down to even, >= 2), on dev's device with
- * temporary jobs. The fastest becomes the shape of every later job of the
+ * 0 or 64 elements, cached or non-temporal AB stores, and for periodic
+ * lattices in AB the fused kernel (2, 3 or 4 steps per launch on tiles of
+ * 64 x rows nodes kept in LDS between the steps, with a ring of one node per
+ * extra step; rows 8 or 16, FP64 4 or 8) --
+ * over `steps` steps each (rounded down to a multiple of 4, at least 4), on
+ * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
  * and is appended to the file named by UQ_TUNE_CACHE if set. Candidates that
  * do not fit in device memory are skipped. Blocking. */
@@ -350,9 +359,13 @@ typedef struct {
     int32_t nt_store;
     int32_t plane_pad;
     int32_t bx;         /* workgroup width along x: 64, 128 or 256          */
-    double gbs;         /* algorithmic GB/s of the best candidate (18 b per node) */
+    double gbs;         /* GB/s of the best at 18 b per node and step (a ranking
+                           figure: a fused launch moves 18 b per node for all of
+                           its steps, so for those it exceeds the traffic)      */
     double ms_per_step; /* its average step duration                           */
     int32_t n_candidates;
+    int32_t fused;      /* steps per launch of the best if fused (2..4), else 0 */
+    int32_t fused_rows; /* its tile height                                     */
 } uq_tune_result;
 uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out);
 

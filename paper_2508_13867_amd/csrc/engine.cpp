@@ -32,6 +32,8 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
     s.nt = env_int("UQ_NT_STORE", 1);
     s.pad = env_int("UQ_PLANE_PAD", 64);
     s.bx = env_int("UQ_BX", 64);
+    s.fuse = env_int("UQ_FUSE", 0);
+    s.fty = env_int("UQ_FUSE_TY", 8);
     s.layout = UQ_LAYOUT_AA;
     if (p.layout == UQ_LAYOUT_AA || p.layout == UQ_LAYOUT_AB) {
         s.layout = p.layout;
@@ -69,11 +71,47 @@ void Job::release_graph() {
     graph_len = 0;
 }
 
+// steps per fused launch in effect (0: none)
+int Job::fused_n() const { return (shape.fuse >= 2 && shape.fuse <= 4 && fused_supported(jd)) ? shape.fuse : 0; }
+
+// Launches for `n` steps starting at step t + k0 of the host mirror. The
+// state of step u lives in slab u & 1. A launch of N fused steps reads the
+// current slab and writes the other one: for odd N that is the slab of step
+// u + N; even N go in pairs (there and back), so that the invariant holds
+// after each pair. Steps left over run one per launch.
+hipError_t Job::enqueue_steps(int k0, int64_t n) {
+    hipError_t e = hipSuccess;
+    int64_t &enqueued = pending_launches;
+    int64_t k = 0;
+    const int N = fused_n();
+    if (N) {
+        const int64_t block = (N & 1) ? N : 2 * N;
+        for (; k + block <= n && e == hipSuccess; k += block) {
+            const bool odd = ((t + k0 + k) & 1) != 0;
+            e = launch_fused(jd, N, odd, shape.fty, stream);
+            ++enqueued;
+            if (e == hipSuccess && !(N & 1)) {
+                e = launch_fused(jd, N, !odd, shape.fty, stream);
+                ++enqueued;
+            }
+        }
+    }
+    for (; k < n && e == hipSuccess; ++k) {
+        e = launch_step(jd, d_t, (int)(k0 + k), (int)((t + k0 + k) & 1), shape, stream, &side);
+        ++enqueued;
+    }
+    return e;
+}
+
 uq_status Job::advance(int64_t steps) {
-    const int L = env_int("UQ_GRAPH_STEPS", 64) & ~1;
+    int L = env_int("UQ_GRAPH_STEPS", 64) & ~1;
+    // whole fused blocks in a graph: multiples of 2N (N even) or 2N (N odd,
+    // even length keeps every replay starting at an even step)
+    if (const int N = fused_n()) L = L / (2 * N) * (2 * N);
     if (use_graph && L >= 2 && steps >= L + 1) {
         if (t & 1) {
             UQ_HIP_TRY(launch_step(jd, d_t, 0, 1, shape, stream, &side));
+            ++launches;
             UQ_HIP_TRY(launch_advance(d_t, 1, stream));
             t += 1;
             steps -= 1;
@@ -81,8 +119,10 @@ uq_status Job::advance(int64_t steps) {
         if (!gexec || graph_len != L) {
             release_graph();
             UQ_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = hipSuccess;
-            for (int k = 0; k < L && e == hipSuccess; ++k) e = launch_step(jd, d_t, k, k & 1, shape, stream, &side);
+            pending_launches = 0;
+            hipError_t e = enqueue_steps(0, L);
+            graph_launches = pending_launches;
+            pending_launches = 0;
             if (e == hipSuccess) e = launch_advance(d_t, L, stream);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(stream, &g);
@@ -99,11 +139,13 @@ uq_status Job::advance(int64_t steps) {
             UQ_HIP_TRY(hipGraphLaunch(gexec, stream));
             t += L;
             steps -= L;
+            launches += graph_launches;
         }
     }
     if (steps > 0) {
-        for (int64_t k = 0; k < steps; ++k)
-            UQ_HIP_TRY(launch_step(jd, d_t, (int)k, (int)((t + k) & 1), shape, stream, &side));
+        pending_launches = 0;
+        UQ_HIP_TRY(enqueue_steps(0, steps));
+        launches += pending_launches;
         UQ_HIP_TRY(launch_advance(d_t, steps, stream));
         t += steps;
     }

@@ -30,6 +30,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "uq_internal.h"
 
@@ -629,6 +630,126 @@ __global__ __launch_bounds__(FD_BLOCK) void k_fd_columns(JobDev j, const int64_t
     }
 }
 
+// ------------------------------------------------------------------ fused steps
+// Periodic lattices (no boundary rules), AB layout: N = 2..4 steps per launch
+// (temporal blocking). A workgroup takes a tile of 64 x TY output nodes of
+// one sample and keeps a ring of N - 1 nodes around it in LDS. Phase 1 pulls
+// the state at t for tile and ring from the source slab and collides it
+// (step t); each later phase pulls from LDS, collides the next step on a
+// region one node narrower (held in registers across a barrier, then written
+// back to LDS); the last phase covers the tile itself and stores f*(t+N-1)
+// to the other slab. Each population crosses HBM once per N steps (the
+// ring's re-reads are served by L2: neighbouring tiles run together). Same
+// per-node arithmetic as k_step, including the storage rounding of every
+// intermediate state.
+constexpr int FUSE_TX = 64;
+
+template <int P, int TY, int N>
+__global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x, int tiles_y, int64_t ntiles) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    constexpr int RG = N - 1;                 // ring width
+    constexpr int LW = FUSE_TX + 2 * RG;      // LDS row length
+    constexpr int LH = TY + 2 * RG;           // LDS rows
+    constexpr int PER = (LW * LH + 255) / 256; // region nodes per thread (bound)
+    __shared__ C lds[9][LH][LW];
+    const T *src_all = (const T *)(src2 ? j.f2 : j.f);
+    T *dst_all = (T *)(src2 ? j.f : j.f2);
+    const int nx = j.nx, ny = j.ny;
+    const int64_t pitch = j.pitch, plane = j.plane;
+    const float inv = j.inv_scale, sc = j.scale;
+    const int tid = threadIdx.x;
+    const int64_t G = gridDim.x;
+    const int64_t per_sample = (int64_t)tiles_x * tiles_y;
+    for (int64_t tile = xcd_logical(blockIdx.x, G); tile < ntiles; tile += G) {
+        const int64_t smp = tile / per_sample;
+        const int64_t rem = tile - smp * per_sample;
+        const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
+        const int x0 = tx * FUSE_TX, y0 = ty * TY;
+        const int w = min(FUSE_TX, nx - x0), h = min(TY, ny - y0);
+        const T *src = src_all + smp * 9 * plane;
+        T *dst = dst_all + smp * 9 * plane;
+        const C omega = (C)j.smp[smp].omega;
+        // phase 1: step t on tile and ring, from the source slab
+        {
+            const int RW = w + 2 * RG, RH = h + 2 * RG;
+            for (int e = tid; e < RW * RH; e += 256) {
+                const int r = e / RW, c = e - r * RW;
+                int gx = x0 - RG + c, gy = y0 - RG + r;
+                gx = ((gx % nx) + nx) % nx;
+                gy = ((gy % ny) + ny) % ny;
+                C f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    int xs = gx - CXd[i], ys = gy - CYd[i];
+                    xs += xs < 0 ? nx : 0;
+                    xs -= xs >= nx ? nx : 0;
+                    ys += ys < 0 ? ny : 0;
+                    ys -= ys >= ny ? ny : 0;
+                    f[i] = PR::ld(src + i * plane + (int64_t)ys * pitch + xs, inv);
+                }
+                C drho, ux, uy;
+                bgk(f, omega, drho, ux, uy);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    T q;
+                    PR::st(&q, f[i], sc);
+                    lds[i][r][c] = PR::ld(&q, inv);
+                }
+            }
+        }
+        __syncthreads();
+        // middle phases: steps t+1 .. t+N-2 on shrinking regions, in LDS
+#pragma unroll
+        for (int ph = 1; ph < N - 1; ++ph) {
+            const int RW = w + 2 * (RG - ph), RH = h + 2 * (RG - ph);
+            C g[PER][9];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int e = tid + 256 * k;
+                if (e < RW * RH) {
+                    const int r = e / RW + ph, c = e - (e / RW) * RW + ph;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) g[k][i] = lds[i][r - CYd[i]][c - CXd[i]];
+                    C drho, ux, uy;
+                    bgk(g[k], omega, drho, ux, uy);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int e = tid + 256 * k;
+                if (e < RW * RH) {
+                    const int r = e / RW + ph, c = e - (e / RW) * RW + ph;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        T q;
+                        PR::st(&q, g[k][i], sc);
+                        lds[i][r][c] = PR::ld(&q, inv);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // last phase: step t+N-1 on the tile, to the destination slab
+        const int cx = tid & 63;
+        for (int r = tid >> 6; r < h; r += 4) {
+            if (cx < w) {
+                C f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = lds[i][r + RG - CYd[i]][cx + RG - CXd[i]];
+                C drho, ux, uy;
+                bgk(f, omega, drho, ux, uy);
+                const int64_t own = (int64_t)(y0 + r) * pitch + x0 + cx;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) PR::st_nt(dst + i * plane + own, f[i], sc);
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
 // One step for every live node of every sample of every job in a table
 // (continuous batching). Jobs may differ in geometry, lattice, sample count
 // and step parity; all use the AA layout, one row per thread. Tiles of job q
@@ -1149,6 +1270,46 @@ hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, in
 hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     k_advance_multi<<<(unsigned)((njobs + 63) / 64), 64, 0, s>>>(jobs, njobs, n);
+    return hipGetLastError();
+}
+
+bool fused_supported(const JobDev &j) { return j.geom == 0 && j.layout == UQ_LAYOUT_AB; }
+
+template <int P, int N>
+static void stepN_p(const JobDev &j, bool src2, int fty, hipStream_t s) {
+    const int tiles_x = (j.nx + FUSE_TX - 1) / FUSE_TX;
+    auto go = [&](auto ty_c) {
+        constexpr int TY = decltype(ty_c)::value;
+        const int tiles_y = (j.ny + TY - 1) / TY;
+        const int64_t ntiles = (int64_t)j.S * tiles_x * tiles_y;
+        const int64_t G = std::min<int64_t>(ntiles, 0x7fffffff);
+        k_stepN<P, TY, N><<<(unsigned)G, 256, 0, s>>>(j, src2, tiles_x, tiles_y, ntiles);
+    };
+    // FP64 tiles are half as tall (the LDS tile holds doubles)
+    if constexpr (P == UQ_FP64) {
+        if (fty <= 4) go(std::integral_constant<int, 4>());
+        else go(std::integral_constant<int, 8>());
+    } else {
+        if (fty <= 8) go(std::integral_constant<int, 8>());
+        else go(std::integral_constant<int, 16>());
+    }
+}
+
+template <int P>
+static void fused_p(const JobDev &j, int n, bool src2, int fty, hipStream_t s) {
+    if (n == 2) stepN_p<P, 2>(j, src2, fty, s);
+    else if (n == 3) stepN_p<P, 3>(j, src2, fty, s);
+    else stepN_p<P, 4>(j, src2, fty, s);
+}
+
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, hipStream_t s) {
+    if (!fused_supported(j) || n < 2 || n > 4) return hipErrorInvalidValue;
+    switch (j.prec) {
+        case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, s); break;
+        case UQ_FP32: fused_p<UQ_FP32>(j, n, src2, fty, s); break;
+        case UQ_FP16S: fused_p<UQ_FP16S>(j, n, src2, fty, s); break;
+        default: fused_p<UQ_BF16S>(j, n, src2, fty, s); break;
+    }
     return hipGetLastError();
 }
 

@@ -48,17 +48,19 @@ void load_cache_locked() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad, bx;
+    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad, bx, fuse, fty;
     long long S;
     double gbs;
-    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req, &layout,
-                       &cpt, &nt, &pad, &bx, &gbs) == 12) {
+    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req,
+                       &layout, &cpt, &nt, &pad, &bx, &fuse, &fty, &gbs) == 14) {
         Entry e;
         e.shape.layout = layout;
         e.shape.cpt = cpt;
         e.shape.nt = nt;
         e.shape.pad = pad;
         e.shape.bx = bx;
+        e.shape.fuse = fuse;
+        e.shape.fty = fty;
         e.gbs = gbs;
         g_cache[Key(prec, geom, nx, ny, (int64_t)S, lay_req)] = e;
     }
@@ -71,9 +73,9 @@ void store_locked(const Key &k, const Entry &e) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-                 std::get<3>(k), (long long)std::get<4>(k), std::get<5>(k), e.shape.layout, e.shape.cpt, e.shape.nt,
-                 e.shape.pad, e.shape.bx, e.gbs);
+    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k),
+                 std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), std::get<5>(k), e.shape.layout, e.shape.cpt,
+                 e.shape.nt, e.shape.pad, e.shape.bx, e.shape.fuse, e.shape.fty, e.gbs);
     std::fclose(f);
 }
 
@@ -95,7 +97,8 @@ using namespace uqi;
 extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out) {
     if (!p || !out) return fail(UQ_EINVAL, "null argument");
     if (steps < 2) return fail(UQ_EINVAL, "steps must be >= 2");
-    steps &= ~(int64_t)1;
+    steps = steps / 24 * 24;  // whole fused blocks (4, 3 and 8 steps)
+    if (steps < 24) steps = 24;
     Rule r;
     uq_status st = build_rule(*p, r);
     if (st != UQ_OK) return st;
@@ -118,6 +121,19 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         s.bx = bx;
                         cands.push_back(s);
                     }
+        // 2, 3 or 4 steps per launch (periodic lattices, AB)
+        if (layout == UQ_LAYOUT_AB && p->geometry == UQ_GEOM_TGV)
+            for (int n : {2, 3, 4})
+                for (int pad : {0, 64})
+                    for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{4, 8} : std::vector<int>{8, 16})) {
+                        StepShape s;
+                        s.layout = layout;
+                        s.pad = pad;
+                        s.nt = 1;
+                        s.fuse = n;
+                        s.fty = fty;
+                        cands.push_back(s);
+                    }
     }
 
     const double bytes_per_node = 18.0 * (double)storage_bytes(p->precision);
@@ -133,7 +149,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
         double ms = 0.0;
         hipEvent_t a = nullptr, b = nullptr;
         bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-        ok = ok && j->advance(2) == UQ_OK;  // warm-up
+        ok = ok && j->advance(24) == UQ_OK;  // warm-up (whole fused blocks of 2, 3 or 4 steps)
         ok = ok && hipEventRecord(a, j->stream) == hipSuccess;
         ok = ok && j->advance(steps) == UQ_OK;
         ok = ok && hipEventRecord(b, j->stream) == hipSuccess;
@@ -165,6 +181,8 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
     out->nt_store = best.shape.nt;
     out->plane_pad = best.shape.pad;
     out->bx = best.shape.bx;
+    out->fused = best.shape.fuse >= 2 ? best.shape.fuse : 0;
+    out->fused_rows = best.shape.fuse >= 2 ? best.shape.fty : 0;
     out->gbs = best.gbs;
     out->ms_per_step = best_ms;
     out->n_candidates = tried;

@@ -520,6 +520,9 @@ extern "C" uq_status uq_job_get_info(const uq_job *j, uq_job_info *info) {
     info->nt_store = j->shape.nt;
     info->plane_pad = j->plane_pad;
     info->bx = j->shape.bx;
+    info->fused = j->fused_n();
+    info->fused_rows = info->fused ? j->shape.fty : 0;
+    info->step_launches = j->launches;
     return UQ_OK;
 }
 

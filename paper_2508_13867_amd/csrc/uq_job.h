@@ -37,6 +37,9 @@ struct Job {
     JobDev jd{};
     StepShape shape{};
     int64_t t = 0;            // steps done (host mirror)
+    int64_t launches = 0;     // step-kernel launches issued (graph replays counted per launch)
+    int64_t graph_launches = 0; // step-kernel launches in the captured graph
+    int64_t pending_launches = 0; // counted by enqueue_steps
     int64_t *d_t = nullptr;   // steps done at the last base update (device)
 
     std::vector<void *> allocs;
@@ -59,6 +62,8 @@ struct Job {
     uq_status ensure_fields();
     uq_status sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld);
     uq_status advance(int64_t steps);
+    hipError_t enqueue_steps(int k0, int64_t n);
+    int fused_n() const;
     uq_status enter();  // order the job stream after the caller's stream
     uq_status leave();  // order the caller's stream after the job stream
     void release_graph();

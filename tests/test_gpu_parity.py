@@ -289,12 +289,13 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     spec = W.scaled(TGV_4D_SMALL, steps=20)
     say("case autotune")
     r = A.autotune(spec, steps=10)
-    # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes idle)
-    assert r["n_candidates"] == 24 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes
+    # idle), plus 12 fused candidates (2, 3, 4 steps x 2 pads x 2 tile heights)
+    assert r["n_candidates"] == 36 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
-        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx) == \
-            (r["layout"], r["cpt"], r["plane_pad"], r["bx"])
+        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows) == \
+            (r["layout"], r["cpt"], r["plane_pad"], r["bx"], r["fused"], r["fused_rows"])
         job.run(20)
         ref = O.run_problem(spec, qois=["ke"])
         assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
@@ -336,3 +337,92 @@ def test_sparse_grid_qmc_lhs_rules_fp64(rule):
             st = job.moments(q)
             for k in ("mean", "var", "var_alt") + (("coeffs",) if rule["kind"] == "smolyak" else ()):
                 assert rel_l2(st[k], ref["stats"][q][k]) < TOL["fp64"], (q, k)
+
+
+# ----------------------------------------------------------------- fused steps per launch
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("rows", [4, 8])
+@pytest.mark.parametrize("steps", [4, 7, 41, 130])
+def test_fused_kernel_populations_match_oracle(steps, rows, n, monkeypatch):
+    # FP64 (tile heights 4 and 8) on the ragged 72 x 40 vortex: counts that
+    # leave single steps after the fused blocks, and a captured graph
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    spec = W.scaled(TGV_RAGGED, layout="ab")
+    say("case fused", n, "fp64 steps", steps, "rows", rows)
+    with Job(spec) as job:
+        assert job.info().fused == n and job.info().fused_rows == rows
+        job.run(steps)
+        xi, a = job.samples()
+        for smp in (0, 8):
+            p = O.sample_params(TGV_RAGGED, xi[smp])
+            ref = O.tgv_run(72, 40, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+            got = job.populations(smp)
+            assert np.abs(got - ref).max() < 1e-13, (smp, np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("nx, ny", [(20, 12), (3, 5), (130, 17)])
+def test_fused_kernel_small_and_wrapping_lattices(nx, ny, n, monkeypatch):
+    # lattices narrower than a tile and its ring (the ring wraps onto itself)
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision="fp64", phase_x=0.0, phase_y=0.0)
+    say("case fused", n, "lattice", nx, ny)
+    with Job(spec) as job:
+        job.run(24)
+        xi, _ = job.samples()
+        p = O.sample_params(spec, xi[3])
+        ref = O.tgv_run(nx, ny, p["nu"], p["u0"], 24, want_f=True)["f"]
+        assert np.abs(job.populations(3) - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+def test_fused_kernel_matches_single_steps(prec, n, monkeypatch):
+    spec = W.scaled(TGV_4D_SMALL, precision=prec, layout="ab", steps=200)
+    say("case fused", n, "vs single", prec)
+    res = {}
+    for fuse in ("0", str(n)):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        with Job(spec) as job:
+            job.run(200)
+            res[fuse] = (job.populations(7), job.qoi_samples("ke")[:, 0])
+    # the same per-node arithmetic and storage rounding; only the compiler's
+    # contraction choices may differ between the kernels
+    tol = 1e-6 if prec == "fp32" else 1e-4
+    assert np.abs(res["0"][0] - res[str(n)][0]).max() < tol
+    assert rel_l2(res[str(n)][1], res["0"][1]) < tol
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_fused_kernel_full_size_sampled(n, monkeypatch):
+    # the 256^2 x 256 benchmark lattice, fused, 120 steps
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    spec = W.scaled(W.TGV_BATCHED_FP32, steps=120, layout="ab")
+    say("case fused", n, "256^2 x 256")
+    with Job(spec) as job:
+        assert job.info().fused == n
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        pick = [0, 200]
+        ref = O.run_problem(spec, samples=pick, qois=["ke", "vel"])
+        assert rel_l2(ke[pick], ref["samples"]["ke"]) < TOL["fp32"]
+        vel = job.qoi_samples("vel")
+        assert rel_l2(vel[pick], ref["samples"]["vel"].reshape(2, -1)) < TOL["fp32"]
+
+
+def test_fused_graph_replay_equals_eager(monkeypatch):
+    monkeypatch.setenv("UQ_FUSE", "3")
+    spec = W.scaled(TGV_4D_SMALL, steps=150, layout="ab")
+    say("case fused graph vs eager")
+    monkeypatch.setenv("UQ_GRAPH_STEPS", "24")
+    with Job(spec) as a:
+        a.run(5)
+        a.run(145)
+        fa = a.populations(5)
+    monkeypatch.setenv("UQ_GRAPH_STEPS", "0")
+    with Job(spec) as b:
+        b.run(150)
+        fb = b.populations(5)
+    assert np.array_equal(fa, fb)
