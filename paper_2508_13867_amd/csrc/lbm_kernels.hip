@@ -644,6 +644,14 @@ __global__ __launch_bounds__(FD_BLOCK) void k_fd_columns(JobDev j, const int64_t
 // intermediate state.
 constexpr int FUSE_TX = 64;
 
+// wrap a coordinate into [0, n) (it is at most a ring away from it, but the
+// ring may exceed a tiny lattice)
+__device__ inline int wrap_coord(int v, int n) {
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
 template <int P, int TY, int N>
 __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x, int tiles_y, int64_t ntiles) {
     using PR = Prec<P>;
@@ -657,7 +665,8 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
-    const int64_t pitch = j.pitch, plane = j.plane;
+    // offsets inside one sample fit in 32 bits (9 planes < 2^31 elements)
+    const int pitch = (int)j.pitch, plane = (int)j.plane;
     const float inv = j.inv_scale, sc = j.scale;
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x;
@@ -668,70 +677,118 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
         const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
         const int x0 = tx * FUSE_TX, y0 = ty * TY;
         const int w = min(FUSE_TX, nx - x0), h = min(TY, ny - y0);
-        const T *src = src_all + smp * 9 * plane;
-        T *dst = dst_all + smp * 9 * plane;
+        const T *src = src_all + smp * 9 * (int64_t)plane;
+        T *dst = dst_all + smp * 9 * (int64_t)plane;
         const C omega = (C)j.smp[smp].omega;
-        // phase 1: step t on tile and ring, from the source slab
+        // phase 1: step t on tile and ring, from the source slab. A thread's
+        // elements e = tid + 256 k (their (r, c) advance by (256 / RW,
+        // 256 % RW) per k) issue all their loads before any is used.
         {
-            const int RW = w + 2 * RG, RH = h + 2 * RG;
-            for (int e = tid; e < RW * RH; e += 256) {
-                const int r = e / RW, c = e - r * RW;
-                int gx = x0 - RG + c, gy = y0 - RG + r;
-                gx = ((gx % nx) + nx) % nx;
-                gy = ((gy % ny) + ny) % ny;
-                C f[9];
+            const int RW = w + 2 * RG, RH = h + 2 * RG, n_el = RW * RH;
+            const int dq = 256 / RW, dr = 256 - dq * RW;
+            int rr[PER], cc[PER];
+            {
+                int r = tid / RW, c = tid - r * RW;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    int xs = gx - CXd[i], ys = gy - CYd[i];
-                    xs += xs < 0 ? nx : 0;
-                    xs -= xs >= nx ? nx : 0;
-                    ys += ys < 0 ? ny : 0;
-                    ys -= ys >= ny ? ny : 0;
-                    f[i] = PR::ld(src + i * plane + (int64_t)ys * pitch + xs, inv);
+                for (int k = 0; k < PER; ++k) {
+                    rr[k] = r;
+                    cc[k] = c;
+                    r += dq;
+                    c += dr;
+                    if (c >= RW) {
+                        c -= RW;
+                        ++r;
+                    }
                 }
-                C drho, ux, uy;
-                bgk(f, omega, drho, ux, uy);
+            }
+            // B elements at a time issue their loads together: all of them in
+            // FP64 (long load latency per byte, registers to spare), one at a
+            // time in the 4- and 2-byte formats (more waves in flight instead)
+            constexpr int B = P == UQ_FP64 ? PER : 1;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    T q;
-                    PR::st(&q, f[i], sc);
-                    lds[i][r][c] = PR::ld(&q, inv);
+            for (int kb = 0; kb < PER; kb += B) {
+                C f[B][9];
+#pragma unroll
+                for (int q2 = 0; q2 < B; ++q2) {
+                    const int k = kb + q2;
+                    if (k < PER && tid + 256 * k < n_el) {
+                        const int gx = wrap_coord(x0 - RG + cc[k], nx), gy = wrap_coord(y0 - RG + rr[k], ny);
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            int xs = gx - CXd[i], ys = gy - CYd[i];
+                            xs += xs < 0 ? nx : 0;
+                            xs -= xs >= nx ? nx : 0;
+                            ys += ys < 0 ? ny : 0;
+                            ys -= ys >= ny ? ny : 0;
+                            f[q2][i] = PR::ld(src + (i * plane + ys * pitch + xs), inv);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q2 = 0; q2 < B; ++q2) {
+                    const int k = kb + q2;
+                    if (k < PER && tid + 256 * k < n_el) {
+                        C drho, ux, uy;
+                        bgk(f[q2], omega, drho, ux, uy);
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            T q;
+                            PR::st(&q, f[q2][i], sc);
+                            lds[i][rr[k]][cc[k]] = PR::ld(&q, inv);
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
-        // middle phases: steps t+1 .. t+N-2 on shrinking regions, in LDS
+        // middle phases: steps t+1 .. t+N-2 on shrinking regions, in LDS;
+        // each thread keeps its new values in registers across the barrier
+        auto middle = [&](auto ph_c) {
+            constexpr int PH = decltype(ph_c)::value;
+            constexpr int PERM = ((LW - 2 * PH) * (LH - 2 * PH) + 255) / 256;
+            const int RW = w + 2 * (RG - PH), RH = h + 2 * (RG - PH), n_el = RW * RH;
+            const int dq = 256 / RW, dr = 256 - dq * RW;
+            C g[PERM][9];
+            int rr[PERM], cc[PERM];
+            {
+                int r = tid / RW, c = tid - r * RW;
 #pragma unroll
-        for (int ph = 1; ph < N - 1; ++ph) {
-            const int RW = w + 2 * (RG - ph), RH = h + 2 * (RG - ph);
-            C g[PER][9];
+                for (int k = 0; k < PERM; ++k) {
+                    rr[k] = r + PH;
+                    cc[k] = c + PH;
+                    r += dq;
+                    c += dr;
+                    if (c >= RW) {
+                        c -= RW;
+                        ++r;
+                    }
+                }
+            }
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = tid + 256 * k;
-                if (e < RW * RH) {
-                    const int r = e / RW + ph, c = e - (e / RW) * RW + ph;
+            for (int k = 0; k < PERM; ++k) {
+                if (tid + 256 * k < n_el) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) g[k][i] = lds[i][r - CYd[i]][c - CXd[i]];
+                    for (int i = 0; i < 9; ++i) g[k][i] = lds[i][rr[k] - CYd[i]][cc[k] - CXd[i]];
                     C drho, ux, uy;
                     bgk(g[k], omega, drho, ux, uy);
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = tid + 256 * k;
-                if (e < RW * RH) {
-                    const int r = e / RW + ph, c = e - (e / RW) * RW + ph;
+            for (int k = 0; k < PERM; ++k) {
+                if (tid + 256 * k < n_el) {
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         T q;
                         PR::st(&q, g[k][i], sc);
-                        lds[i][r][c] = PR::ld(&q, inv);
+                        lds[i][rr[k]][cc[k]] = PR::ld(&q, inv);
                     }
                 }
             }
             __syncthreads();
-        }
+        };
+        if constexpr (N >= 3) middle(std::integral_constant<int, 1>());
+        if constexpr (N >= 4) middle(std::integral_constant<int, 2>());
         // last phase: step t+N-1 on the tile, to the destination slab
         const int cx = tid & 63;
         for (int r = tid >> 6; r < h; r += 4) {
@@ -741,9 +798,9 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
                 for (int i = 0; i < 9; ++i) f[i] = lds[i][r + RG - CYd[i]][cx + RG - CXd[i]];
                 C drho, ux, uy;
                 bgk(f, omega, drho, ux, uy);
-                const int64_t own = (int64_t)(y0 + r) * pitch + x0 + cx;
+                const int own = (y0 + r) * pitch + x0 + cx;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) PR::st_nt(dst + i * plane + own, f[i], sc);
+                for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
             }
         }
         __syncthreads();  // LDS is reused by the next tile
