@@ -426,3 +426,24 @@ def test_fused_graph_replay_equals_eager(monkeypatch):
         b.run(150)
         fb = b.populations(5)
     assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("layout, fuse", [("aa", "0"), ("ab", "0"), ("ab", "4")])
+def test_more_samples_than_a_grid_dimension(layout, fuse, monkeypatch):
+    # 70,000 samples (> 65,535, the largest grid y extent) on an 8 x 8 lattice:
+    # every per-sample loop must reach the last samples
+    monkeypatch.setenv("UQ_FUSE", fuse)
+    spec = dict(name="tgv8_mc70000", geometry="tgv", precision="fp32", nx=8, ny=8, steps=12, u0=0.02, nu=0.02,
+                dists=[("nu", 0.01, 0.03), ("u0", 0.015, 0.025)], rule=dict(kind="mc", N=70000, seed=5),
+                layout=layout)
+    say("case S = 70000", layout, fuse)
+    with Job(spec) as job:
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        vel = job.qoi_samples("vel")
+        pick = [0, 65535, 65536, 69999]
+        ref = O.run_problem(spec, samples=pick, qois=["ke", "vel"])
+        assert rel_l2(ke[pick], ref["samples"]["ke"]) < TOL["fp32"]
+        assert rel_l2(vel[pick], ref["samples"]["vel"].reshape(4, -1)) < TOL["fp32"]
+        st = job.moments("ke")
+        assert abs(st["mean"][0] - ke.mean()) <= 1e-12 * abs(ke.mean())
