@@ -126,12 +126,25 @@ __device__ inline C third(C x) {
     return fma_c(x, Third<C>::hi, x * Third<C>::lo);
 }
 
+// 1/x from the hardware reciprocal estimate refined by Newton steps (one in
+// single, two in double precision): within an ulp of the quotient, a third of
+// the instructions of the IEEE division sequence
+__device__ inline float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ inline double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
 template <typename C>
 __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     const C drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
     const C jx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
     const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
-    const C ir = C(1) / (C(1) + drho);
+    const C ir = recip(C(1) + drho);
     const C ux = jx * ir, uy = jy * ir;
     const C base = -C(1.5) * (jx * ux + jy * uy);
     const C w0 = C(4) / C(9), w1 = C(1) / C(9), w2 = C(1) / C(36);
@@ -172,7 +185,7 @@ __device__ inline void moments(const C f[9], C &drho, C &ux, C &uy) {
     drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
     const C jx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
     const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
-    const C ir = C(1) / (C(1) + drho);
+    const C ir = recip(C(1) + drho);
     ux = jx * ir;
     uy = jy * ir;
 }
@@ -644,6 +657,41 @@ __global__ __launch_bounds__(FD_BLOCK) void k_fd_columns(JobDev j, const int64_t
 // intermediate state.
 constexpr int FUSE_TX = 64;
 
+// Buffer loads for the fused kernel: base address and size in a (uniform)
+// resource descriptor, a 32-bit byte offset per lane and a uniform offset per
+// population plane; no 64-bit address arithmetic per load. 0x00020000 is the
+// descriptor's fourth word for raw 32-bit data on this GPU family.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <int P>
+struct BufLd;
+template <>
+struct BufLd<UQ_FP64> {
+    __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+};
+template <>
+struct BufLd<UQ_FP32> {
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+};
+template <>
+struct BufLd<UQ_FP16S> {
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) * inv;
+    }
+};
+template <>
+struct BufLd<UQ_BF16S> {
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
+        const unsigned short b = __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+        return __uint_as_float((uint32_t)b << 16) * inv;
+    }
+};
+
 // wrap a coordinate into [0, n) (it is at most a ring away from it, but the
 // ring may exceed a tiny lattice)
 __device__ inline int wrap_coord(int v, int n) {
@@ -680,6 +728,8 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
         const T *src = src_all + smp * 9 * (int64_t)plane;
         T *dst = dst_all + smp * 9 * (int64_t)plane;
         const C omega = (C)j.smp[smp].omega;
+        const int plane_b = plane * (int)sizeof(T);
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b);
         // phase 1: step t on tile and ring, from the source slab. A thread's
         // elements e = tid + 256 k (their (r, c) advance by (256 / RW,
         // 256 % RW) per k) issue all their loads before any is used.
@@ -712,15 +762,19 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
                 for (int q2 = 0; q2 < B; ++q2) {
                     const int k = kb + q2;
                     if (k < PER && tid + 256 * k < n_el) {
-                        const int gx = wrap_coord(x0 - RG + cc[k], nx), gy = wrap_coord(y0 - RG + rr[k], ny);
+                        int gx = x0 - RG + cc[k], gy = y0 - RG + rr[k];
+                        if (gx < 0 || gx >= nx) gx = wrap_coord(gx, nx);
+                        if (gy < 0 || gy >= ny) gy = wrap_coord(gy, ny);
+                        // the pull sources: columns x-1, x, x+1 and rows y-1,
+                        // y, y+1 (wrapped), one byte offset per direction
+                        const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
+                        const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
+                        const int r0 = gy * pitch, rm = ym * pitch, rp = yp * pitch;
 #pragma unroll
                         for (int i = 0; i < 9; ++i) {
-                            int xs = gx - CXd[i], ys = gy - CYd[i];
-                            xs += xs < 0 ? nx : 0;
-                            xs -= xs >= nx ? nx : 0;
-                            ys += ys < 0 ? ny : 0;
-                            ys -= ys >= ny ? ny : 0;
-                            f[q2][i] = PR::ld(src + (i * plane + ys * pitch + xs), inv);
+                            const int col = CXd[i] > 0 ? xm : (CXd[i] < 0 ? xp : gx);
+                            const int row = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
+                            f[q2][i] = BufLd<P>::ld(rsrc, (row + col) * (int)sizeof(T), i * plane_b, inv);
                         }
                     }
                 }
@@ -1330,7 +1384,11 @@ hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_
     return hipGetLastError();
 }
 
-bool fused_supported(const JobDev &j) { return j.geom == 0 && j.layout == UQ_LAYOUT_AB; }
+bool fused_supported(const JobDev &j) {
+    // periodic AB jobs whose per-sample slab fits one buffer descriptor's range
+    const int64_t b = j.prec == UQ_FP64 ? 8 : (j.prec == UQ_FP32 ? 4 : 2);
+    return j.geom == 0 && j.layout == UQ_LAYOUT_AB && 9 * j.plane * b < ((int64_t)1 << 31);
+}
 
 template <int P, int N>
 static void stepN_p(const JobDev &j, bool src2, int fty, hipStream_t s) {
