@@ -490,7 +490,7 @@ def main():
         inf = job.info()
         launch.update(layout={1: "aa", 2: "ab"}[inf.layout], cpt=inf.cpt, nt_store=inf.nt_store,
                       plane_pad=inf.plane_pad, bx=inf.bx, fused_steps=inf.fused, fused_rows=inf.fused_rows,
-                      device_bytes=inf.device_bytes)
+                      fused_window=inf.fused_window, device_bytes=inf.device_bytes)
         ms = job.run_timed(spec["steps"]) if timed_kernel else None
         if not timed_kernel:
             job.run(spec["steps"])
@@ -536,7 +536,8 @@ def main():
     traffic = measured_traffic(alg_bytes)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"uqi::k_stepN<..., N={nfuse}>" if nfuse > 1 else "uqi::k_step",
+            "kernel": (f"uqi::k_stepW<..., N={nfuse}>" if launch.get("fused_window") else
+                       f"uqi::k_stepN<..., N={nfuse}>") if nfuse > 1 else "uqi::k_step",
             "bytes_per_launch": alg_bytes, "updates_per_node_per_launch": nfuse,
             "bytes_per_node_update": round(bpn / nfuse, 3), "launches": launches,
             "launch_ms": round(per_launch_ms, 5), "copy_gbs": round(copy_gbs, 1),

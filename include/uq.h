@@ -287,10 +287,14 @@ typedef struct {
     int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
     int32_t fused;      /* steps per launch of the fused periodic AB
                            kernel (2..4), 0 if not fused               */
-    int32_t fused_rows; /* its tile height (rows of 64 nodes)          */
+    int32_t fused_rows; /* its tile height (rows of 64 nodes), or the
+                           window kernel's chunk height               */
     int64_t step_launches; /* step-kernel launches so far (a fused launch
                               counts once: each launch reads and writes
                               every population of every sample once)  */
+    int32_t fused_window; /* 1 if the fused launches use the sliding-
+                             window kernel, 0 for tiles                */
+    int32_t pad3;
 } uq_job_info;
 
 /* Set up a job: sample the inputs, map each sample to its solver parameters,
@@ -345,10 +349,12 @@ const char *uq_last_error(void);
  * (only the problem's layout unless it is UQ_LAYOUT_AUTO), workgroups of
  * 64 x 4, 128 x 2 or 256 x 1 threads, 1 or 2 rows per thread, plane padding
  * 0 or 64 elements, cached or non-temporal AB stores, and for periodic
- * lattices in AB the fused kernel (2, 3 or 4 steps per launch on tiles of
+ * lattices in AB the fused kernels (2, 3 or 4 steps per launch: on tiles of
  * 64 x rows nodes kept in LDS between the steps, with a ring of one node per
- * extra step; rows 8 or 16, FP64 4 or 8) --
- * over `steps` steps each (rounded down to a multiple of 4, at least 4), on
+ * extra step, rows 8 or 16, FP64 4 or 8; or as a sliding window, one wave
+ * per step, down strips of at most 64 - 2(N - 1) columns in chunks of 64 or
+ * 256 rows, FP64 32 or 64) --
+ * over `steps` steps each (rounded down to a multiple of 24, at least 24), on
  * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
  * and is appended to the file named by UQ_TUNE_CACHE if set. Candidates that
@@ -365,7 +371,8 @@ typedef struct {
     double ms_per_step; /* its average step duration                           */
     int32_t n_candidates;
     int32_t fused;      /* steps per launch of the best if fused (2..4), else 0 */
-    int32_t fused_rows; /* its tile height                                     */
+    int32_t fused_rows; /* its tile height (window: chunk height)              */
+    int32_t fused_window; /* 1 if the best is the sliding-window kernel        */
 } uq_tune_result;
 uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out);
 

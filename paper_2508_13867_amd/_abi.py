@@ -74,13 +74,13 @@ class JobInfo(C.Structure):
                 ("pitch", C.c_int64), ("device_bytes", C.c_int64), ("scale_exp", C.c_int32),
                 ("fluid_nodes", C.c_int32), ("layout", C.c_int32), ("cpt", C.c_int32), ("nt_store", C.c_int32),
                 ("plane_pad", C.c_int32), ("bx", C.c_int32), ("fused", C.c_int32), ("fused_rows", C.c_int32),
-                ("step_launches", C.c_int64)]
+                ("step_launches", C.c_int64), ("fused_window", C.c_int32), ("pad3", C.c_int32)]
 
 
 class TuneResult(C.Structure):
     _fields_ = [("layout", C.c_int32), ("cpt", C.c_int32), ("nt_store", C.c_int32), ("plane_pad", C.c_int32),
                 ("bx", C.c_int32), ("gbs", C.c_double), ("ms_per_step", C.c_double), ("n_candidates", C.c_int32),
-                ("fused", C.c_int32), ("fused_rows", C.c_int32)]
+                ("fused", C.c_int32), ("fused_rows", C.c_int32), ("fused_window", C.c_int32)]
 
 
 RESULT_MAX_COEFFS = 256
@@ -284,7 +284,8 @@ def autotune(spec: dict, steps: int = 40, device: int = 0) -> dict:
     del keep
     return {"layout": {1: "aa", 2: "ab"}[r.layout], "cpt": r.cpt, "nt_store": r.nt_store,
             "plane_pad": r.plane_pad, "bx": r.bx, "gbs": r.gbs, "ms_per_step": r.ms_per_step,
-            "n_candidates": r.n_candidates, "fused": r.fused, "fused_rows": r.fused_rows}
+            "n_candidates": r.n_candidates, "fused": r.fused, "fused_rows": r.fused_rows,
+            "fused_window": r.fused_window}
 
 
 class Job:

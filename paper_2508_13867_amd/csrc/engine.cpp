@@ -34,6 +34,7 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
     s.bx = env_int("UQ_BX", 64);
     s.fuse = env_int("UQ_FUSE", 0);
     s.fty = env_int("UQ_FUSE_TY", 8);
+    s.fwin = env_int("UQ_FUSE_WINDOW", 0);
     s.layout = UQ_LAYOUT_AA;
     if (p.layout == UQ_LAYOUT_AA || p.layout == UQ_LAYOUT_AB) {
         s.layout = p.layout;
@@ -88,10 +89,10 @@ hipError_t Job::enqueue_steps(int k0, int64_t n) {
         const int64_t block = (N & 1) ? N : 2 * N;
         for (; k + block <= n && e == hipSuccess; k += block) {
             const bool odd = ((t + k0 + k) & 1) != 0;
-            e = launch_fused(jd, N, odd, shape.fty, stream);
+            e = launch_fused(jd, N, odd, shape.fty, shape.fwin != 0, shape.nt != 0, stream);
             ++enqueued;
             if (e == hipSuccess && !(N & 1)) {
-                e = launch_fused(jd, N, !odd, shape.fty, stream);
+                e = launch_fused(jd, N, !odd, shape.fty, shape.fwin != 0, shape.nt != 0, stream);
                 ++enqueued;
             }
         }

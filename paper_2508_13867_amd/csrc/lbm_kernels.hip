@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <type_traits>
 
@@ -87,6 +88,8 @@ struct Prec<UQ_BF16S> {
 __device__ constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr int OPPd[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// index of a direction among the three that share its c_y
+__device__ constexpr int GJd[9] = {0, 1, 0, 2, 0, 1, 2, 1, 2};
 
 template <typename C>
 __device__ inline C wgt(int i) {
@@ -861,6 +864,136 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
     }
 }
 
+// ------------------------------------------------------------------ fused steps, sliding window
+// The same N-step fusion organised as a pipeline down a strip of W columns
+// of one sample (W <= 64 - 2(N-1)): each wave of the workgroup computes one
+// time level, one lattice row per iteration, two rows behind the level it
+// reads. Level 1 pulls from the source slab (D rows ahead, in registers);
+// levels 2..N pull from LDS rows of the level below; level N stores to the
+// other slab. Only the strip's x-ring (N-1 columns per side) and a chunk's
+// y-halo are computed twice (11 % at N = 4 with 52-column strips and 64-row
+// chunks, against 45 % for the 8-row tiles above), and every address that
+// depends on the row is wave-uniform (scalar registers): a lane keeps one
+// column for the whole strip.
+template <int P, int N, int D>
+__global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, int strips, int H, int chunks,
+                                                  int64_t nwork, bool nt) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    constexpr int RG = N - 1;
+    // Between two levels each direction is read once, by the row that pulls
+    // it: c_y = -1 directions one iteration after they are written (rows
+    // kept: 2), c_y = 0 two iterations after (3), c_y = +1 three after (4).
+    // Rows are offset by 12 (a multiple of 2, 3 and 4) to keep slots positive.
+    constexpr int NR = N > 1 ? N - 1 : 1;
+    __shared__ C ra[NR][2][3][64], rb[NR][3][3][64], rc[NR][4][3][64];
+    const T *src_all = (const T *)(src2 ? j.f2 : j.f);
+    T *dst_all = (T *)(src2 ? j.f : j.f2);
+    const int nx = j.nx, ny = j.ny;
+    const int pitch = (int)j.pitch, plane = (int)j.plane;
+    const int plane_b = plane * (int)sizeof(T), pitch_b = pitch * (int)sizeof(T);
+    const float inv = j.inv_scale, sc = j.scale;
+    const int lane = threadIdx.x & 63;
+    // level of this wave, rotated with the workgroup index so that the levels'
+    // different instruction mixes spread evenly over a CU's SIMDs
+    const int lvl = __builtin_amdgcn_readfirstlane((int)((threadIdx.x >> 6) + blockIdx.x) % N) + 1;  // 1..N
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / ((int64_t)chunks * strips);
+        const int rem = (int)(wk - smp * chunks * strips);
+        const int chunk = rem / strips, strip = rem - chunk * strips;
+        const int x0 = strip * W, w = min(W, nx - x0);
+        const int yb = chunk * H, ye = min(ny, yb + H);
+        const T *src = src_all + smp * 9 * (int64_t)plane;
+        T *dst = dst_all + smp * 9 * (int64_t)plane;
+        const C omega = (C)j.smp[smp].omega;
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b);
+        // this lane's column at this level, and its LDS column (0 = x0 - RG)
+        const int span = RG - (lvl - 1);  // columns beyond the strip on each side
+        const bool lane_on = lane < w + 2 * span;
+        const int lc = lane + (lvl - 1);
+        int gc = x0 - span + lane;
+        while (gc < 0) gc += nx;
+        while (gc >= nx) gc -= nx;
+        const int vo0 = gc * (int)sizeof(T), vom = (gc == 0 ? nx - 1 : gc - 1) * (int)sizeof(T),
+                  vop = (gc == nx - 1 ? 0 : gc + 1) * (int)sizeof(T);
+        // level 1 pulls row y + D while it collides row y: D rows of loads in
+        // flight per strip, rotated through registers
+        C buf[D][9];
+        auto pull = [&](C *f, int y) {
+            int gy = y;
+            while (gy < 0) gy += ny;
+            while (gy >= ny) gy -= ny;
+            const int r0 = gy * pitch_b, rm = (gy == 0 ? ny - 1 : gy - 1) * pitch_b,
+                      rp = (gy == ny - 1 ? 0 : gy + 1) * pitch_b;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int vo = CXd[i] > 0 ? vom : (CXd[i] < 0 ? vop : vo0);
+                const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
+                f[i] = BufLd<P>::ld(rsrc, vo, i * plane_b + ro, inv);
+            }
+        };
+        const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
+        if (lvl == 1 && lane_on) {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (yb - RG + k < y1_end) pull(buf[k], yb - RG + k);
+        }
+        const int n_it = (ye - yb) + 3 * RG;
+        for (int it0 = 0; it0 < n_it; it0 += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int it = it0 + k;
+                if (it >= n_it) break;
+                const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
+                const bool row_on = y >= yb - span && y < ye + span;
+                if (row_on && lane_on) {
+                    C f[9];
+                    if (lvl == 1) {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) f[i] = buf[k][i];
+                        if (y + D < y1_end) pull(buf[k], y + D);
+                    } else {
+                        const int L = lvl - 2;
+                        const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            const int g = GJd[i], c = lc - CXd[i];
+                            f[i] = CYd[i] < 0 ? ra[L][sa][g][c] : (CYd[i] == 0 ? rb[L][sb][g][c] : rc[L][sc3][g][c]);
+                        }
+                    }
+                    C drho, ux, uy;
+                    bgk(f, omega, drho, ux, uy);
+                    if (lvl < N) {
+                        const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            T q;
+                            PR::st(&q, f[i], sc);
+                            const C v = PR::ld(&q, inv);
+                            const int g = GJd[i];
+                            if (CYd[i] < 0) ra[L][sa][g][lc] = v;
+                            else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
+                            else rc[L][sc3][g][lc] = v;
+                        }
+                    } else {
+                        const int own = y * pitch + x0 + lane;
+                        if (nt) {
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) PR::st(dst + (i * plane + own), f[i], sc);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // One step for every live node of every sample of every job in a table
 // (continuous batching). Jobs may differ in geometry, lattice, sample count
 // and step parity; all use the AA layout, one row per thread. Tiles of job q
@@ -1410,20 +1543,38 @@ static void stepN_p(const JobDev &j, bool src2, int fty, hipStream_t s) {
     }
 }
 
-template <int P>
-static void fused_p(const JobDev &j, int n, bool src2, int fty, hipStream_t s) {
-    if (n == 2) stepN_p<P, 2>(j, src2, fty, s);
-    else if (n == 3) stepN_p<P, 3>(j, src2, fty, s);
-    else stepN_p<P, 4>(j, src2, fty, s);
+template <int P, int N>
+static void stepW_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
+    const int wmax = 64 - 2 * (N - 1);
+    const int strips = (j.nx + wmax - 1) / wmax;
+    const int W = (j.nx + strips - 1) / strips;  // balanced strips
+    const int H = std::max(8, std::min(rows, j.ny));
+    const int chunks = (j.ny + H - 1) / H;
+    const int64_t nwork = (int64_t)j.S * strips * chunks;
+    const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
+    k_stepW<P, N, 2><<<(unsigned)G, 64 * N, 0, s>>>(j, src2, W, strips, H, chunks, nwork, nt);
 }
 
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, hipStream_t s) {
+template <int P>
+static void fused_p(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s) {
+    if (window) {
+        if (n == 2) stepW_p<P, 2>(j, src2, fty, nt, s);
+        else if (n == 3) stepW_p<P, 3>(j, src2, fty, nt, s);
+        else stepW_p<P, 4>(j, src2, fty, nt, s);
+    } else {
+        if (n == 2) stepN_p<P, 2>(j, src2, fty, s);
+        else if (n == 3) stepN_p<P, 3>(j, src2, fty, s);
+        else stepN_p<P, 4>(j, src2, fty, s);
+    }
+}
+
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s) {
     if (!fused_supported(j) || n < 2 || n > 4) return hipErrorInvalidValue;
     switch (j.prec) {
-        case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, s); break;
-        case UQ_FP32: fused_p<UQ_FP32>(j, n, src2, fty, s); break;
-        case UQ_FP16S: fused_p<UQ_FP16S>(j, n, src2, fty, s); break;
-        default: fused_p<UQ_BF16S>(j, n, src2, fty, s); break;
+        case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, window, nt, s); break;
+        case UQ_FP32: fused_p<UQ_FP32>(j, n, src2, fty, window, nt, s); break;
+        case UQ_FP16S: fused_p<UQ_FP16S>(j, n, src2, fty, window, nt, s); break;
+        default: fused_p<UQ_BF16S>(j, n, src2, fty, window, nt, s); break;
     }
     return hipGetLastError();
 }

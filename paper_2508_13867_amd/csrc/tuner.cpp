@@ -48,11 +48,11 @@ void load_cache_locked() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad, bx, fuse, fty;
+    int prec, geom, nx, ny, lay_req, layout, cpt, nt, pad, bx, fuse, fty, fwin;
     long long S;
     double gbs;
-    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req,
-                       &layout, &cpt, &nt, &pad, &bx, &fuse, &fty, &gbs) == 14) {
+    while (std::fscanf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %d %lf", &prec, &geom, &nx, &ny, &S, &lay_req,
+                       &layout, &cpt, &nt, &pad, &bx, &fuse, &fty, &fwin, &gbs) == 15) {
         Entry e;
         e.shape.layout = layout;
         e.shape.cpt = cpt;
@@ -61,6 +61,7 @@ void load_cache_locked() {
         e.shape.bx = bx;
         e.shape.fuse = fuse;
         e.shape.fty = fty;
+        e.shape.fwin = fwin;
         e.gbs = gbs;
         g_cache[Key(prec, geom, nx, ny, (int64_t)S, lay_req)] = e;
     }
@@ -73,9 +74,9 @@ void store_locked(const Key &k, const Entry &e) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k),
+    std::fprintf(f, "%d %d %d %d %lld %d %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k),
                  std::get<2>(k), std::get<3>(k), (long long)std::get<4>(k), std::get<5>(k), e.shape.layout, e.shape.cpt,
-                 e.shape.nt, e.shape.pad, e.shape.bx, e.shape.fuse, e.shape.fty, e.gbs);
+                 e.shape.nt, e.shape.pad, e.shape.bx, e.shape.fuse, e.shape.fty, e.shape.fwin, e.gbs);
     std::fclose(f);
 }
 
@@ -121,8 +122,9 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         s.bx = bx;
                         cands.push_back(s);
                     }
-        // 2, 3 or 4 steps per launch (periodic lattices, AB)
-        if (layout == UQ_LAYOUT_AB && p->geometry == UQ_GEOM_TGV)
+        // 2, 3 or 4 steps per launch (periodic lattices, AB): tiles of 64 x fty
+        // nodes, and sliding windows down chunks of fty rows
+        if (layout == UQ_LAYOUT_AB && p->geometry == UQ_GEOM_TGV) {
             for (int n : {2, 3, 4})
                 for (int pad : {0, 64})
                     for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{4, 8} : std::vector<int>{8, 16})) {
@@ -134,6 +136,18 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         s.fty = fty;
                         cands.push_back(s);
                     }
+            for (int n : {2, 3, 4})
+                for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{32, 64} : std::vector<int>{64, 256})) {
+                    StepShape s;
+                    s.layout = layout;
+                    s.pad = 64;
+                    s.nt = 0;
+                    s.fuse = n;
+                    s.fty = fty;
+                    s.fwin = 1;
+                    cands.push_back(s);
+                }
+        }
     }
 
     const double bytes_per_node = 18.0 * (double)storage_bytes(p->precision);
@@ -183,6 +197,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
     out->bx = best.shape.bx;
     out->fused = best.shape.fuse >= 2 ? best.shape.fuse : 0;
     out->fused_rows = best.shape.fuse >= 2 ? best.shape.fty : 0;
+    out->fused_window = best.shape.fuse >= 2 ? best.shape.fwin : 0;
     out->gbs = best.gbs;
     out->ms_per_step = best_ms;
     out->n_candidates = tried;

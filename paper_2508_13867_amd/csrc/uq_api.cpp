@@ -522,6 +522,7 @@ extern "C" uq_status uq_job_get_info(const uq_job *j, uq_job_info *info) {
     info->bx = j->shape.bx;
     info->fused = j->fused_n();
     info->fused_rows = info->fused ? j->shape.fty : 0;
+    info->fused_window = info->fused ? j->shape.fwin : 0;
     info->step_launches = j->launches;
     return UQ_OK;
 }

@@ -127,7 +127,8 @@ struct StepShape {
     int pad = 64;       // elements of padding after each population plane
     int bx = 64;        // workgroup width along x (64, 128 or 256; height 256/bx)
     int fuse = 0;       // periodic AB jobs: steps per launch of k_stepN (2..4; 0, 1: k_step)
-    int fty = 8;        // k_stepN tile height (rows of 64 output nodes)
+    int fty = 8;        // k_stepN tile height (rows of 64 output nodes); k_stepW chunk rows
+    int fwin = 0;       // fused kernel: 0 tiles (k_stepN), 1 sliding window (k_stepW)
 };
 
 // one stream-collide step for all samples at time t = *d_t + k; `parity`
@@ -145,7 +146,9 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
 // n = 2..4 fused steps of a periodic AB job in one launch: the state is
 // read from slab f2 if src2 else f and n steps later written to the other
 // slab (the host keeps the slab of each step's state; see Job::enqueue_steps)
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, hipStream_t s);
+// (window: the sliding-window kernel with chunks of fty rows, its stores
+// non-temporal if nt; else the 64 x fty tile kernel)
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s);
 bool fused_supported(const JobDev &j);
 // one step of every job in a table (AA layout, one row per thread); all jobs
 // must share precision `prec`

@@ -290,12 +290,14 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     say("case autotune")
     r = A.autotune(spec, steps=10)
     # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes
-    # idle), plus 12 fused candidates (2, 3, 4 steps x 2 pads x 2 tile heights)
-    assert r["n_candidates"] == 36 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # idle), plus 12 fused tile candidates (2, 3, 4 steps x 2 pads x 2 tile
+    # heights) and 6 sliding-window ones (2, 3, 4 steps x 2 chunk heights)
+    assert r["n_candidates"] == 42 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
-        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows) == \
-            (r["layout"], r["cpt"], r["plane_pad"], r["bx"], r["fused"], r["fused_rows"])
+        assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows,
+                inf.fused_window) == \
+            (r["layout"], r["cpt"], r["plane_pad"], r["bx"], r["fused"], r["fused_rows"], r["fused_window"])
         job.run(20)
         ref = O.run_problem(spec, qois=["ke"])
         assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
@@ -342,17 +344,19 @@ def test_sparse_grid_qmc_lhs_rules_fp64(rule):
 # ----------------------------------------------------------------- fused steps per launch
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-@pytest.mark.parametrize("rows", [4, 8])
+@pytest.mark.parametrize("rows, window", [(4, 0), (8, 0), (8, 1), (16, 1)])
 @pytest.mark.parametrize("steps", [4, 7, 41, 130])
-def test_fused_kernel_populations_match_oracle(steps, rows, n, monkeypatch):
-    # FP64 (tile heights 4 and 8) on the ragged 72 x 40 vortex: counts that
-    # leave single steps after the fused blocks, and a captured graph
+def test_fused_kernel_populations_match_oracle(steps, rows, window, n, monkeypatch):
+    # FP64 (tile heights 4 and 8; window chunks of 8 and 16 rows) on the
+    # ragged 72 x 40 vortex: counts that leave single steps after the fused
+    # blocks, and a captured graph
     monkeypatch.setenv("UQ_FUSE", str(n))
     monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
     spec = W.scaled(TGV_RAGGED, layout="ab")
-    say("case fused", n, "fp64 steps", steps, "rows", rows)
+    say("case fused", n, "fp64 steps", steps, "rows", rows, "window", window)
     with Job(spec) as job:
-        assert job.info().fused == n and job.info().fused_rows == rows
+        assert job.info().fused == n and job.info().fused_rows == rows and job.info().fused_window == window
         job.run(steps)
         xi, a = job.samples()
         for smp in (0, 8):
@@ -363,12 +367,15 @@ def test_fused_kernel_populations_match_oracle(steps, rows, n, monkeypatch):
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-@pytest.mark.parametrize("nx, ny", [(20, 12), (3, 5), (130, 17)])
-def test_fused_kernel_small_and_wrapping_lattices(nx, ny, n, monkeypatch):
-    # lattices narrower than a tile and its ring (the ring wraps onto itself)
+@pytest.mark.parametrize("window", [0, 1])
+@pytest.mark.parametrize("nx, ny", [(20, 12), (3, 5), (130, 17), (58, 9), (59, 9)])
+def test_fused_kernel_small_and_wrapping_lattices(nx, ny, window, n, monkeypatch):
+    # lattices narrower than a tile and its ring (the ring wraps onto itself);
+    # 58 and 59 columns: one window strip at N = 4, then two
     monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
     spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision="fp64", phase_x=0.0, phase_y=0.0)
-    say("case fused", n, "lattice", nx, ny)
+    say("case fused", n, "lattice", nx, ny, "window", window)
     with Job(spec) as job:
         job.run(24)
         xi, _ = job.samples()
@@ -378,10 +385,12 @@ def test_fused_kernel_small_and_wrapping_lattices(nx, ny, n, monkeypatch):
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("window", [0, 1])
 @pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
-def test_fused_kernel_matches_single_steps(prec, n, monkeypatch):
+def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     spec = W.scaled(TGV_4D_SMALL, precision=prec, layout="ab", steps=200)
-    say("case fused", n, "vs single", prec)
+    monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
+    say("case fused", n, "vs single", prec, "window", window)
     res = {}
     for fuse in ("0", str(n)):
         monkeypatch.setenv("UQ_FUSE", fuse)
@@ -395,10 +404,11 @@ def test_fused_kernel_matches_single_steps(prec, n, monkeypatch):
     assert rel_l2(res[str(n)][1], res["0"][1]) < tol
 
 
-@pytest.mark.parametrize("n", [2, 3])
-def test_fused_kernel_full_size_sampled(n, monkeypatch):
+@pytest.mark.parametrize("n, window", [(2, 0), (3, 0), (4, 1)])
+def test_fused_kernel_full_size_sampled(n, window, monkeypatch):
     # the 256^2 x 256 benchmark lattice, fused, 120 steps
     monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
     spec = W.scaled(W.TGV_BATCHED_FP32, steps=120, layout="ab")
     say("case fused", n, "256^2 x 256")
     with Job(spec) as job:
