@@ -695,6 +695,35 @@ struct BufLd<UQ_BF16S> {
     }
 };
 
+// buffer stores: per-lane byte offset + wave-uniform byte offset (cached)
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <int P>
+struct BufSt;
+template <>
+struct BufSt<UQ_FP64> {
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, double v, int voff, int soff, float) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
+    }
+};
+template <>
+struct BufSt<UQ_FP32> {
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff, float) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    }
+};
+template <>
+struct BufSt<UQ_FP16S> {
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff, float sc) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)(v * sc)), r, voff, soff, 0);
+    }
+};
+template <>
+struct BufSt<UQ_BF16S> {
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff, float sc) {
+        __builtin_amdgcn_raw_buffer_store_b16(Prec<UQ_BF16S>::rne(v * sc), r, voff, soff, 0);
+    }
+};
+
 // wrap a coordinate into [0, n) (it is at most a ring away from it, but the
 // ring may exceed a tiny lattice)
 __device__ inline int wrap_coord(int v, int n) {
@@ -908,7 +937,8 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
         const T *src = src_all + smp * 9 * (int64_t)plane;
         T *dst = dst_all + smp * 9 * (int64_t)plane;
         const C omega = (C)j.smp[smp].omega;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b);
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b), wrsrc = make_rsrc(dst, 9 * plane_b);
+        const int wvo = (x0 + lane) * (int)sizeof(T);  // level N's store column
         // this lane's column at this level, and its LDS column (0 = x0 - RG)
         const int span = RG - (lvl - 1);  // columns beyond the strip on each side
         const bool lane_on = lane < w + 2 * span;
@@ -978,13 +1008,13 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
                             else rc[L][sc3][g][lc] = v;
                         }
                     } else {
-                        const int own = y * pitch + x0 + lane;
                         if (nt) {
+                            const int own = y * pitch + x0 + lane;
 #pragma unroll
                             for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
                         } else {
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) PR::st(dst + (i * plane + own), f[i], sc);
+                            for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], wvo, i * plane_b + y * pitch_b, sc);
                         }
                     }
                 }
