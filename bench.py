@@ -38,14 +38,18 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg_per_launch):
+def measured_traffic(kernel_prefix):
     """HBM bytes per step launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
+    if they were taken on the current kernel source and on the kernel
+    instance this run launches (its name starts with `kernel_prefix`);
+    else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
     if t.get("kernel_sha") != kernel_hash():
+        return None
+    if not any(k.replace("void ", "").startswith(kernel_prefix) for k in t.get("kernel", [])):
         return None
     return t.get("bytes_per_launch")
 
@@ -533,7 +537,14 @@ def main():
     alg_bytes = S * cells * bpn
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     nfuse = launch.get("fused_steps", 0) or 1
-    traffic = measured_traffic(alg_bytes)
+    pcode = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}[prec]
+    if nfuse > 1 and launch.get("fused_window"):
+        kprefix = f"uqi::k_stepW<{pcode}, {nfuse}, "
+    elif nfuse > 1:
+        kprefix = f"uqi::k_stepN<{pcode}, {launch.get('fused_rows')}, {nfuse}>"
+    else:
+        kprefix = "uqi::k_step<"
+    traffic = measured_traffic(kprefix)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": (f"uqi::k_stepW<..., N={nfuse}>" if launch.get("fused_window") else
