@@ -538,7 +538,9 @@ def main():
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     nfuse = launch.get("fused_steps", 0) or 1
     pcode = {"fp64": 0, "fp32": 1, "fp16s": 2, "bf16s": 3}[prec]
-    if nfuse > 1 and launch.get("fused_window"):
+    if nfuse > 1 and launch.get("fused_window") == 2:
+        kprefix = f"uqi::k_stepR<{pcode}, {nfuse}, "
+    elif nfuse > 1 and launch.get("fused_window"):
         kprefix = f"uqi::k_stepW<{pcode}, {nfuse}, "
     elif nfuse > 1:
         kprefix = f"uqi::k_stepN<{pcode}, {launch.get('fused_rows')}, {nfuse}>"
@@ -547,8 +549,9 @@ def main():
     traffic = measured_traffic(kprefix)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": (f"uqi::k_stepW<..., N={nfuse}>" if launch.get("fused_window") else
-                       f"uqi::k_stepN<..., N={nfuse}>") if nfuse > 1 else "uqi::k_step",
+            "kernel": ({0: f"uqi::k_stepN<..., N={nfuse}>", 1: f"uqi::k_stepW<..., N={nfuse}>",
+                        2: f"uqi::k_stepR<..., N={nfuse}>"}[launch.get("fused_window") or 0]
+                       if nfuse > 1 else "uqi::k_step"),
             "bytes_per_launch": alg_bytes, "updates_per_node_per_launch": nfuse,
             "bytes_per_node_update": round(bpn / nfuse, 3), "launches": launches,
             "launch_ms": round(per_launch_ms, 5), "copy_gbs": round(copy_gbs, 1),

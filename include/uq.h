@@ -292,8 +292,9 @@ typedef struct {
     int64_t step_launches; /* step-kernel launches so far (a fused launch
                               counts once: each launch reads and writes
                               every population of every sample once)  */
-    int32_t fused_window; /* 1 if the fused launches use the sliding-
-                             window kernel, 0 for tiles                */
+    int32_t fused_window; /* fused kernel: 0 tiles, 1 sliding window
+                             down strips, 2 sliding window over whole
+                             rows                                      */
     int32_t pad3;
 } uq_job_info;
 
@@ -352,8 +353,9 @@ const char *uq_last_error(void);
  * lattices in AB the fused kernels (2, 3 or 4 steps per launch: on tiles of
  * 64 x rows nodes kept in LDS between the steps, with a ring of one node per
  * extra step, rows 8 or 16, FP64 4 or 8; or as a sliding window, one wave
- * per step, down strips of at most 64 - 2(N - 1) columns in chunks of 64 or
- * 256 rows, FP64 32 or 64) --
+ * per step, down strips of at most 64 - 2(N - 1) columns or down whole rows
+ * of up to 256 columns (K waves per step, N K <= 16; FP64 at N = 4 up to
+ * 192), in chunks of 64 or 256 rows, FP64 32 or 64) --
  * over `steps` steps each (rounded down to a multiple of 24, at least 24), on
  * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
@@ -372,7 +374,7 @@ typedef struct {
     int32_t n_candidates;
     int32_t fused;      /* steps per launch of the best if fused (2..4), else 0 */
     int32_t fused_rows; /* its tile height (window: chunk height)              */
-    int32_t fused_window; /* 1 if the best is the sliding-window kernel        */
+    int32_t fused_window; /* 0 tiles, 1 window strips, 2 window over whole rows */
 } uq_tune_result;
 uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out);
 

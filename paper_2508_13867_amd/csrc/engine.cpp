@@ -35,6 +35,7 @@ StepShape choose_shape(const uq_problem &p, int64_t S) {
     s.fuse = env_int("UQ_FUSE", 0);
     s.fty = env_int("UQ_FUSE_TY", 8);
     s.fwin = env_int("UQ_FUSE_WINDOW", 0);
+    if (s.fwin == 2 && p.nx > full_rows_max_nx(p.precision, s.fuse)) s.fwin = 1;  // rows too wide
     s.layout = UQ_LAYOUT_AA;
     if (p.layout == UQ_LAYOUT_AA || p.layout == UQ_LAYOUT_AB) {
         s.layout = p.layout;
@@ -89,10 +90,10 @@ hipError_t Job::enqueue_steps(int k0, int64_t n) {
         const int64_t block = (N & 1) ? N : 2 * N;
         for (; k + block <= n && e == hipSuccess; k += block) {
             const bool odd = ((t + k0 + k) & 1) != 0;
-            e = launch_fused(jd, N, odd, shape.fty, shape.fwin != 0, shape.nt != 0, stream);
+            e = launch_fused(jd, N, odd, shape.fty, shape.fwin, shape.nt != 0, stream);
             ++enqueued;
             if (e == hipSuccess && !(N & 1)) {
-                e = launch_fused(jd, N, !odd, shape.fty, shape.fwin != 0, shape.nt != 0, stream);
+                e = launch_fused(jd, N, !odd, shape.fty, shape.fwin, shape.nt != 0, stream);
                 ++enqueued;
             }
         }

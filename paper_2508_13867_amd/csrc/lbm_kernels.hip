@@ -29,7 +29,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <cstdlib>
 #include <cstdint>
 #include <type_traits>
 
@@ -669,29 +668,50 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int bytes) {
 }
 template <int P>
 struct BufLd;
+// raw(): the stored value as loaded; cvt(): its compute value (kept apart so
+// that a load's register is not consumed before it is needed)
 template <>
 struct BufLd<UQ_FP64> {
-    __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float) {
+    using R = double;
+    __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+    __device__ static inline double cvt(R v, float) { return v; }
+    __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
+        return cvt(raw(r, voff, soff), inv);
     }
 };
 template <>
 struct BufLd<UQ_FP32> {
-    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float) {
+    using R = float;
+    __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    __device__ static inline float cvt(R v, float) { return v; }
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
+        return cvt(raw(r, voff, soff), inv);
     }
 };
 template <>
 struct BufLd<UQ_FP16S> {
+    using R = unsigned short;
+    __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+    __device__ static inline float cvt(R v, float inv) { return (float)__builtin_bit_cast(_Float16, v) * inv; }
     __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
-        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) * inv;
+        return cvt(raw(r, voff, soff), inv);
     }
 };
 template <>
 struct BufLd<UQ_BF16S> {
+    using R = unsigned short;
+    __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+    __device__ static inline float cvt(R v, float inv) { return __uint_as_float((uint32_t)v << 16) * inv; }
     __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
-        const unsigned short b = __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-        return __uint_as_float((uint32_t)b << 16) * inv;
+        return cvt(raw(r, voff, soff), inv);
     }
 };
 
@@ -949,9 +969,14 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
         const int vo0 = gc * (int)sizeof(T), vom = (gc == 0 ? nx - 1 : gc - 1) * (int)sizeof(T),
                   vop = (gc == nx - 1 ? 0 : gc + 1) * (int)sizeof(T);
         // level 1 pulls row y + D while it collides row y: D rows of loads in
-        // flight per strip, rotated through registers
-        C buf[D][9];
-        auto pull = [&](C *f, int y) {
+        // flight per strip. D + 1 register buffers in rotation: each step
+        // collides one in place and refills the one the step before used, so
+        // a load never targets a live register (that would leave a copy that
+        // waits for the load).
+        constexpr int B = D + 1;
+        using R = typename BufLd<P>::R;
+        R buf[B][9];
+        auto pull = [&](R *f, int y) {
             int gy = y;
             while (gy < 0) gy += ny;
             while (gy >= ny) gy -= ny;
@@ -961,62 +986,201 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
             for (int i = 0; i < 9; ++i) {
                 const int vo = CXd[i] > 0 ? vom : (CXd[i] < 0 ? vop : vo0);
                 const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
-                f[i] = BufLd<P>::ld(rsrc, vo, i * plane_b + ro, inv);
+                f[i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
             }
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
-        if (lvl == 1 && lane_on) {
+        // collide a pulled row and hand it to the next level (or store it)
+        auto finish = [&](C *f, int y) {
+            C drho, ux, uy;
+            bgk(f, omega, drho, ux, uy);
+            if (lvl < N) {
+                const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (yb - RG + k < y1_end) pull(buf[k], yb - RG + k);
+                for (int i = 0; i < 9; ++i) {
+                    T q;
+                    PR::st(&q, f[i], sc);
+                    const C v = PR::ld(&q, inv);
+                    const int g = GJd[i];
+                    if (CYd[i] < 0) ra[L][sa][g][lc] = v;
+                    else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
+                    else rc[L][sc3][g][lc] = v;
+                }
+            } else if (nt) {
+                const int own = y * pitch + x0 + lane;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], wvo, i * plane_b + y * pitch_b, sc);
+            }
+        };
+        // Level 1's loads are issued by every lane of the wave and for every
+        // row (rows past the chunk's end reload its last row), so that no
+        // register holds a mix of new and old values.
+        if (lvl == 1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
         }
         const int n_it = (ye - yb) + 3 * RG;
-        for (int it0 = 0; it0 < n_it; it0 += D) {
+        for (int it0 = 0; it0 < n_it; it0 += B) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
+            for (int k = 0; k < B; ++k) {
                 const int it = it0 + k;
                 if (it >= n_it) break;
                 const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
                 const bool row_on = y >= yb - span && y < ye + span;
-                if (row_on && lane_on) {
+                if (lvl == 1) {
+                    if (row_on) {
+                        pull(buf[(k + D) % B], min(y + D, y1_end - 1));
+                        if (lane_on) {
+                            C f[9];  // (buffers are written only by loads)
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][i], inv);
+                            finish(f, y);
+                        }
+                    }
+                } else if (row_on && lane_on) {
                     C f[9];
-                    if (lvl == 1) {
+                    const int L = lvl - 2;
+                    const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
 #pragma unroll
-                        for (int i = 0; i < 9; ++i) f[i] = buf[k][i];
-                        if (y + D < y1_end) pull(buf[k], y + D);
-                    } else {
-                        const int L = lvl - 2;
-                        const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
+                    for (int i = 0; i < 9; ++i) {
+                        const int g = GJd[i], c = lc - CXd[i];
+                        f[i] = CYd[i] < 0 ? ra[L][sa][g][c] : (CYd[i] == 0 ? rb[L][sb][g][c] : rc[L][sc3][g][c]);
+                    }
+                    finish(f, y);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fused steps, full rows
+// The sliding window over whole rows: K waves per time level cover the
+// nx <= 64 K columns of a row, so on a periodic lattice no column is computed
+// twice (only a chunk's row halo is). Each LDS row holds its nx columns at
+// 1..nx plus copies of the last and the first column at 0 and nx + 1, so
+// that every pull from the row below is a fixed offset from the lane's own
+// column. N K waves in one workgroup, one barrier per row.
+template <int P, int N, int K, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H, int chunks, int64_t nwork,
+                                                      bool nt) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    constexpr int RG = N - 1;
+    constexpr int NR = N > 1 ? N - 1 : 1;
+    constexpr int CW = 64 * K + 2;
+    __shared__ C ra[NR][2][3][CW], rb[NR][3][3][CW], rc[NR][4][3][CW];
+    const T *src_all = (const T *)(src2 ? j.f2 : j.f);
+    T *dst_all = (T *)(src2 ? j.f : j.f2);
+    const int nx = j.nx, ny = j.ny;
+    const int plane = (int)j.plane;
+    const int plane_b = plane * (int)sizeof(T), pitch_b = (int)j.pitch * (int)sizeof(T);
+    const float inv = j.inv_scale, sc = j.scale;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lvl = wave / K + 1;  // 1..N
+    const int c = (wave - (lvl - 1) * K) * 64 + lane;
+    const bool lane_on = c < nx;
+    const int cc = lane_on ? c : nx - 1;  // idle lanes load a valid column
+    const int lc = c + 1;                  // LDS column
+    const int vo0 = cc * (int)sizeof(T), vom = (cc == 0 ? nx - 1 : cc - 1) * (int)sizeof(T),
+              vop = (cc == nx - 1 ? 0 : cc + 1) * (int)sizeof(T);
+    const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
+    const int64_t G = gridDim.x;
+    constexpr int B = D + 1;
+    using R = typename BufLd<P>::R;
+    R buf[B][9];
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / chunks;
+        const int chunk = (int)(wk - smp * chunks);
+        const int yb = chunk * H, ye = min(ny, yb + H);
+        const T *src = src_all + smp * 9 * (int64_t)plane;
+        T *dst = dst_all + smp * 9 * (int64_t)plane;
+        const C omega = (C)j.smp[smp].omega;
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b), wrsrc = make_rsrc(dst, 9 * plane_b);
+        auto pull = [&](R *f, int y) {
+            int gy = y;
+            while (gy < 0) gy += ny;
+            while (gy >= ny) gy -= ny;
+            const int r0 = gy * pitch_b, rm = (gy == 0 ? ny - 1 : gy - 1) * pitch_b,
+                      rp = (gy == ny - 1 ? 0 : gy + 1) * pitch_b;
 #pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            const int g = GJd[i], c = lc - CXd[i];
-                            f[i] = CYd[i] < 0 ? ra[L][sa][g][c] : (CYd[i] == 0 ? rb[L][sb][g][c] : rc[L][sc3][g][c]);
+            for (int i = 0; i < 9; ++i) {
+                const int vo = CXd[i] > 0 ? vom : (CXd[i] < 0 ? vop : vo0);
+                const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
+                f[i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
+            }
+        };
+        auto put = [&](int L, int y, int col, const C *v) {
+            const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int g = GJd[i];
+                if (CYd[i] < 0) ra[L][sa][g][col] = v[i];
+                else if (CYd[i] == 0) rb[L][sb][g][col] = v[i];
+                else rc[L][sc3][g][col] = v[i];
+            }
+        };
+        auto finish = [&](C *f, int y) {
+            C drho, ux, uy;
+            bgk(f, omega, drho, ux, uy);
+            if (lvl < N) {
+                C v[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    T q;
+                    PR::st(&q, f[i], sc);
+                    v[i] = PR::ld(&q, inv);
+                }
+                put(lvl - 1, y, lc, v);
+                if (c == nx - 1) put(lvl - 1, y, 0, v);       // left copy of the last column
+                if (c == 0) put(lvl - 1, y, nx + 1, v);       // right copy of the first column
+            } else if (nt) {
+                const int own = y * (int)j.pitch + c;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], vo0, i * plane_b + y * pitch_b, sc);
+            }
+        };
+        const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
+        if (lvl == 1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
+        }
+        const int n_it = (ye - yb) + 3 * RG;
+        for (int it0 = 0; it0 < n_it; it0 += B) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int it = it0 + k;
+                if (it >= n_it) break;
+                const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
+                const bool row_on = y >= yb - span && y < ye + span;
+                if (lvl == 1) {
+                    if (row_on) {
+                        pull(buf[(k + D) % B], min(y + D, y1_end - 1));
+                        if (lane_on) {
+                            C f[9];
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][i], inv);
+                            finish(f, y);
                         }
                     }
-                    C drho, ux, uy;
-                    bgk(f, omega, drho, ux, uy);
-                    if (lvl < N) {
-                        const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
+                } else if (row_on && lane_on) {
+                    C f[9];
+                    const int L = lvl - 2;
+                    const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
 #pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            T q;
-                            PR::st(&q, f[i], sc);
-                            const C v = PR::ld(&q, inv);
-                            const int g = GJd[i];
-                            if (CYd[i] < 0) ra[L][sa][g][lc] = v;
-                            else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
-                            else rc[L][sc3][g][lc] = v;
-                        }
-                    } else {
-                        if (nt) {
-                            const int own = y * pitch + x0 + lane;
-#pragma unroll
-                            for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], wvo, i * plane_b + y * pitch_b, sc);
-                        }
+                    for (int i = 0; i < 9; ++i) {
+                        const int g = GJd[i], cl = lc - CXd[i];
+                        f[i] = CYd[i] < 0 ? ra[L][sa][g][cl] : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
                     }
+                    finish(f, y);
                 }
                 __syncthreads();
             }
@@ -1582,12 +1746,53 @@ static void stepW_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
     const int chunks = (j.ny + H - 1) / H;
     const int64_t nwork = (int64_t)j.S * strips * chunks;
     const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
-    k_stepW<P, N, 2><<<(unsigned)G, 64 * N, 0, s>>>(j, src2, W, strips, H, chunks, nwork, nt);
+    // rows of loads in flight: 3 (2 at FP64, whose registers are scarcer)
+    constexpr int D = P == UQ_FP64 ? 2 : 3;
+    k_stepW<P, N, D><<<(unsigned)G, 64 * N, 0, s>>>(j, src2, W, strips, H, chunks, nwork, nt);
+}
+
+// full-row kernel: K = ceil(nx / 64) waves per level, N K <= 16 waves, LDS
+// rows within 160 KB
+template <int P, int N, int K>
+static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
+    const int H = std::max(8, std::min(rows, j.ny));
+    const int chunks = (j.ny + H - 1) / H;
+    const int64_t nwork = (int64_t)j.S * chunks;
+    const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
+    k_stepR<P, N, K, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, src2, H, chunks, nwork, nt);
+}
+
+template <int P, int N>
+static void stepR_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
+    const int K = (j.nx + 63) / 64;
+    if constexpr (N * 2 <= 16) {
+        if (K <= 2) return stepR_k<P, N, 2>(j, src2, rows, nt, s);
+    }
+    if constexpr (N * 3 <= 16) {
+        if (K == 3) return stepR_k<P, N, 3>(j, src2, rows, nt, s);
+    }
+    if constexpr (N * 4 <= 16 && (P != UQ_FP64 || N < 4)) {
+        if (K == 4) return stepR_k<P, N, 4>(j, src2, rows, nt, s);
+    }
+}
+
+int full_rows_max_nx(int prec, int n) {
+    // 64 K columns with N K <= 16 waves and (N - 1) 27 rows of 64 K + 2
+    // values in LDS
+    const int b = prec == UQ_FP64 ? 8 : 4;
+    int best = 0;
+    for (int K = 2; K <= 4; ++K)
+        if (n * K <= 16 && (int64_t)(n - 1) * 27 * (64 * K + 2) * b <= 160 * 1024) best = 64 * K;
+    return best;
 }
 
 template <int P>
-static void fused_p(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s) {
-    if (window) {
+static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s) {
+    if (window == 2) {
+        if (n == 2) stepR_p<P, 2>(j, src2, fty, nt, s);
+        else if (n == 3) stepR_p<P, 3>(j, src2, fty, nt, s);
+        else stepR_p<P, 4>(j, src2, fty, nt, s);
+    } else if (window) {
         if (n == 2) stepW_p<P, 2>(j, src2, fty, nt, s);
         else if (n == 3) stepW_p<P, 3>(j, src2, fty, nt, s);
         else stepW_p<P, 4>(j, src2, fty, nt, s);
@@ -1598,8 +1803,9 @@ static void fused_p(const JobDev &j, int n, bool src2, int fty, bool window, boo
     }
 }
 
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s) {
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s) {
     if (!fused_supported(j) || n < 2 || n > 4) return hipErrorInvalidValue;
+    if (window == 2 && j.nx > full_rows_max_nx(j.prec, n)) return hipErrorInvalidValue;
     switch (j.prec) {
         case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, window, nt, s); break;
         case UQ_FP32: fused_p<UQ_FP32>(j, n, src2, fty, window, nt, s); break;

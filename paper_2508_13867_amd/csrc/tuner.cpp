@@ -136,17 +136,19 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         s.fty = fty;
                         cands.push_back(s);
                     }
-            for (int n : {2, 3, 4})
-                for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{32, 64} : std::vector<int>{64, 256})) {
-                    StepShape s;
-                    s.layout = layout;
-                    s.pad = 64;
-                    s.nt = 0;
-                    s.fuse = n;
-                    s.fty = fty;
-                    s.fwin = 1;
-                    cands.push_back(s);
-                }
+            for (int win : {1, 2})
+                for (int n : {2, 3, 4})
+                    for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{32, 64} : std::vector<int>{64, 256})) {
+                        if (win == 2 && p->nx > full_rows_max_nx(p->precision, n)) continue;
+                        StepShape s;
+                        s.layout = layout;
+                        s.pad = 64;
+                        s.nt = 0;
+                        s.fuse = n;
+                        s.fty = fty;
+                        s.fwin = win;
+                        cands.push_back(s);
+                    }
         }
     }
 

@@ -128,7 +128,7 @@ struct StepShape {
     int bx = 64;        // workgroup width along x (64, 128 or 256; height 256/bx)
     int fuse = 0;       // periodic AB jobs: steps per launch of k_stepN (2..4; 0, 1: k_step)
     int fty = 8;        // k_stepN tile height (rows of 64 output nodes); k_stepW chunk rows
-    int fwin = 0;       // fused kernel: 0 tiles (k_stepN), 1 sliding window (k_stepW)
+    int fwin = 0;       // fused kernel: 0 tiles (k_stepN), 1 sliding window (k_stepW), 2 full rows (k_stepR)
 };
 
 // one stream-collide step for all samples at time t = *d_t + k; `parity`
@@ -146,9 +146,11 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
 // n = 2..4 fused steps of a periodic AB job in one launch: the state is
 // read from slab f2 if src2 else f and n steps later written to the other
 // slab (the host keeps the slab of each step's state; see Job::enqueue_steps)
-// (window: the sliding-window kernel with chunks of fty rows, its stores
-// non-temporal if nt; else the 64 x fty tile kernel)
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, bool window, bool nt, hipStream_t s);
+// (window 1: the sliding-window kernel with chunks of fty rows, its stores
+// non-temporal if nt; 2: the same over whole rows; 0: the 64 x fty tile kernel)
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s);
+// widest lattice the full-row kernel takes at this precision and N (0: none)
+int full_rows_max_nx(int prec, int n);
 bool fused_supported(const JobDev &j);
 // one step of every job in a table (AA layout, one row per thread); all jobs
 // must share precision `prec`

@@ -291,8 +291,9 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     r = A.autotune(spec, steps=10)
     # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes
     # idle), plus 12 fused tile candidates (2, 3, 4 steps x 2 pads x 2 tile
-    # heights) and 6 sliding-window ones (2, 3, 4 steps x 2 chunk heights)
-    assert r["n_candidates"] == 42 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # heights) and 6 sliding-window and 6 full-row ones (2, 3, 4 steps x 2
+    # chunk heights)
+    assert r["n_candidates"] == 48 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
         assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows,
@@ -344,12 +345,12 @@ def test_sparse_grid_qmc_lhs_rules_fp64(rule):
 # ----------------------------------------------------------------- fused steps per launch
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-@pytest.mark.parametrize("rows, window", [(4, 0), (8, 0), (8, 1), (16, 1)])
+@pytest.mark.parametrize("rows, window", [(4, 0), (8, 0), (8, 1), (16, 1), (8, 2), (16, 2)])
 @pytest.mark.parametrize("steps", [4, 7, 41, 130])
 def test_fused_kernel_populations_match_oracle(steps, rows, window, n, monkeypatch):
-    # FP64 (tile heights 4 and 8; window chunks of 8 and 16 rows) on the
-    # ragged 72 x 40 vortex: counts that leave single steps after the fused
-    # blocks, and a captured graph
+    # FP64 (tile heights 4 and 8; window and full-row chunks of 8 and 16
+    # rows) on the ragged 72 x 40 vortex: counts that leave single steps
+    # after the fused blocks, and a captured graph
     monkeypatch.setenv("UQ_FUSE", str(n))
     monkeypatch.setenv("UQ_FUSE_TY", str(rows))
     monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
@@ -367,16 +368,18 @@ def test_fused_kernel_populations_match_oracle(steps, rows, window, n, monkeypat
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-@pytest.mark.parametrize("window", [0, 1])
-@pytest.mark.parametrize("nx, ny", [(20, 12), (3, 5), (130, 17), (58, 9), (59, 9)])
+@pytest.mark.parametrize("window", [0, 1, 2])
+@pytest.mark.parametrize("nx, ny", [(20, 12), (3, 5), (2, 4), (130, 17), (58, 9), (59, 9), (192, 6)])
 def test_fused_kernel_small_and_wrapping_lattices(nx, ny, window, n, monkeypatch):
     # lattices narrower than a tile and its ring (the ring wraps onto itself);
-    # 58 and 59 columns: one window strip at N = 4, then two
+    # 58 and 59 columns: one window strip at N = 4, then two; two columns
+    # and 192 (three waves per row, the widest FP64 full-row lattice at N = 4)
     monkeypatch.setenv("UQ_FUSE", str(n))
     monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
     spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision="fp64", phase_x=0.0, phase_y=0.0)
     say("case fused", n, "lattice", nx, ny, "window", window)
     with Job(spec) as job:
+        assert job.info().fused == n and job.info().fused_window == window
         job.run(24)
         xi, _ = job.samples()
         p = O.sample_params(spec, xi[3])
@@ -385,7 +388,7 @@ def test_fused_kernel_small_and_wrapping_lattices(nx, ny, window, n, monkeypatch
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-@pytest.mark.parametrize("window", [0, 1])
+@pytest.mark.parametrize("window", [0, 1, 2])
 @pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
 def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     spec = W.scaled(TGV_4D_SMALL, precision=prec, layout="ab", steps=200)
@@ -404,7 +407,7 @@ def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     assert rel_l2(res[str(n)][1], res["0"][1]) < tol
 
 
-@pytest.mark.parametrize("n, window", [(2, 0), (3, 0), (4, 1)])
+@pytest.mark.parametrize("n, window", [(2, 0), (3, 0), (4, 1), (4, 2), (3, 2)])
 def test_fused_kernel_full_size_sampled(n, window, monkeypatch):
     # the 256^2 x 256 benchmark lattice, fused, 120 steps
     monkeypatch.setenv("UQ_FUSE", str(n))
