@@ -286,7 +286,8 @@ typedef struct {
     int32_t plane_pad;  /* padding elements after each population plane */
     int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
     int32_t fused;      /* steps per launch of the fused periodic AB
-                           kernel (2..4), 0 if not fused               */
+                           kernel (2..4; up to 6 over whole rows), 0
+                           if not fused                                */
     int32_t fused_rows; /* its tile height (rows of 64 nodes), or the
                            window kernel's chunk height               */
     int64_t step_launches; /* step-kernel launches so far (a fused launch
@@ -354,9 +355,10 @@ const char *uq_last_error(void);
  * 64 x rows nodes kept in LDS between the steps, with a ring of one node per
  * extra step, rows 8 or 16, FP64 4 or 8; or as a sliding window, one wave
  * per step, down strips of at most 64 - 2(N - 1) columns or down whole rows
- * of up to 256 columns (K waves per step, N K <= 16; FP64 at N = 4 up to
- * 192), in chunks of 64 or 256 rows, FP64 32 or 64) --
- * over `steps` steps each (rounded down to a multiple of 24, at least 24), on
+ * of up to 256 columns (K waves per step, one or two columns per lane,
+ * N K <= 16, 3 to 6 steps; FP64 at N = 4 up to 192), in chunks of 64 or
+ * 256 rows, FP64 32 or 64) --
+ * over `steps` steps each (rounded down to a multiple of 120, at least 120), on
  * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
  * and is appended to the file named by UQ_TUNE_CACHE if set. Candidates that
@@ -372,7 +374,7 @@ typedef struct {
                            its steps, so for those it exceeds the traffic)      */
     double ms_per_step; /* its average step duration                           */
     int32_t n_candidates;
-    int32_t fused;      /* steps per launch of the best if fused (2..4), else 0 */
+    int32_t fused;      /* steps per launch of the best if fused (2..6), else 0 */
     int32_t fused_rows; /* its tile height (window: chunk height)              */
     int32_t fused_window; /* 0 tiles, 1 window strips, 2 window over whole rows */
 } uq_tune_result;

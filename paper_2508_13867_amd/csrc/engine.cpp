@@ -74,7 +74,10 @@ void Job::release_graph() {
 }
 
 // steps per fused launch in effect (0: none)
-int Job::fused_n() const { return (shape.fuse >= 2 && shape.fuse <= 4 && fused_supported(jd)) ? shape.fuse : 0; }
+int Job::fused_n() const {
+    const int nmax = shape.fwin == 2 ? 6 : 4;  // whole rows: up to 6 steps
+    return (shape.fuse >= 2 && shape.fuse <= nmax && fused_supported(jd)) ? shape.fuse : 0;
+}
 
 // Launches for `n` steps starting at step t + k0 of the host mirror. The
 // state of step u lives in slab u & 1. A launch of N fused steps reads the

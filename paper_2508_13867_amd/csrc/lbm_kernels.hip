@@ -127,6 +127,12 @@ template <typename C>
 __device__ inline C third(C x) {
     return fma_c(x, Third<C>::hi, x * Third<C>::lo);
 }
+// x / 12 = third(x) / 4 with the quarter folded into the (exactly scaled)
+// constants: the same value, one multiplication fewer
+template <typename C>
+__device__ inline C twelfth(C x) {
+    return fma_c(x, Third<C>::hi * C(0.25), x * (Third<C>::lo * C(0.25)));
+}
 
 // 1/x from the hardware reciprocal estimate refined by Newton steps (one in
 // single, two in double precision): within an ulp of the quotient, a third of
@@ -166,13 +172,13 @@ __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     }
     {
         const C cj = jx + jy, cu = ux + uy;
-        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = third(cj) * C(0.25);
+        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = twelfth(cj);
         f[5] = om1 * f[5] + omega * (q + l);
         f[7] = om1 * f[7] + omega * (q - l);
     }
     {
         const C cj = jy - jx, cu = uy - ux;
-        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = third(cj) * C(0.25);
+        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = twelfth(cj);
         f[6] = om1 * f[6] + omega * (q + l);
         f[8] = om1 * f[8] + omega * (q - l);
     }
@@ -1058,13 +1064,13 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
 }
 
 // ------------------------------------------------------------------ fused steps, full rows
-// The sliding window over whole rows: K waves per time level cover the
-// nx <= 64 K columns of a row, so on a periodic lattice no column is computed
-// twice (only a chunk's row halo is). Each LDS row holds its nx columns at
-// 1..nx plus copies of the last and the first column at 0 and nx + 1, so
-// that every pull from the row below is a fixed offset from the lane's own
-// column. N K waves in one workgroup, one barrier per row.
-template <int P, int N, int K, int D>
+// The sliding window over whole rows: K waves per time level, M columns per
+// lane, cover the nx <= 64 K M columns of a row, so on a periodic lattice no
+// column is computed twice (only a chunk's row halo is). Each LDS row holds
+// its nx columns at 1..nx plus copies of the last and the first column at 0
+// and nx + 1, so that every pull from the row below is a fixed offset from
+// the lane's own column. N K waves in one workgroup, one barrier per row.
+template <int P, int N, int K, int M, int D>
 __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H, int chunks, int64_t nwork,
                                                       bool nt) {
     using PR = Prec<P>;
@@ -1072,7 +1078,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     using T = typename PR::T;
     constexpr int RG = N - 1;
     constexpr int NR = N > 1 ? N - 1 : 1;
-    constexpr int CW = 64 * K + 2;
+    constexpr int CW = 64 * K * M + 2;
     __shared__ C ra[NR][2][3][CW], rb[NR][3][3][CW], rc[NR][4][3][CW];
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
@@ -1083,17 +1089,22 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lvl = wave / K + 1;  // 1..N
-    const int c = (wave - (lvl - 1) * K) * 64 + lane;
-    const bool lane_on = c < nx;
-    const int cc = lane_on ? c : nx - 1;  // idle lanes load a valid column
-    const int lc = c + 1;                  // LDS column
-    const int vo0 = cc * (int)sizeof(T), vom = (cc == 0 ? nx - 1 : cc - 1) * (int)sizeof(T),
-              vop = (cc == nx - 1 ? 0 : cc + 1) * (int)sizeof(T);
+    int c[M], vo0[M], vom[M], vop[M];
+    bool on[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        c[m] = ((wave - (lvl - 1) * K) * M + m) * 64 + lane;
+        on[m] = c[m] < nx;
+        const int cc = on[m] ? c[m] : nx - 1;  // idle lanes load a valid column
+        vo0[m] = cc * (int)sizeof(T);
+        vom[m] = (cc == 0 ? nx - 1 : cc - 1) * (int)sizeof(T);
+        vop[m] = (cc == nx - 1 ? 0 : cc + 1) * (int)sizeof(T);
+    }
     const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
     const int64_t G = gridDim.x;
     constexpr int B = D + 1;
     using R = typename BufLd<P>::R;
-    R buf[B][9];
+    R buf[B][M][9];
     for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
         const int64_t smp = wk / chunks;
         const int chunk = (int)(wk - smp * chunks);
@@ -1102,18 +1113,20 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
         T *dst = dst_all + smp * 9 * (int64_t)plane;
         const C omega = (C)j.smp[smp].omega;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b), wrsrc = make_rsrc(dst, 9 * plane_b);
-        auto pull = [&](R *f, int y) {
+        auto pull = [&](R (*f)[9], int y) {
             int gy = y;
             while (gy < 0) gy += ny;
             while (gy >= ny) gy -= ny;
             const int r0 = gy * pitch_b, rm = (gy == 0 ? ny - 1 : gy - 1) * pitch_b,
                       rp = (gy == ny - 1 ? 0 : gy + 1) * pitch_b;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int vo = CXd[i] > 0 ? vom : (CXd[i] < 0 ? vop : vo0);
-                const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
-                f[i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
-            }
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int vo = CXd[i] > 0 ? vom[m] : (CXd[i] < 0 ? vop[m] : vo0[m]);
+                    const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
+                    f[m][i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
+                }
         };
         auto put = [&](int L, int y, int col, const C *v) {
             const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3;
@@ -1125,7 +1138,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 else rc[L][sc3][g][col] = v[i];
             }
         };
-        auto finish = [&](C *f, int y) {
+        auto finish = [&](C *f, int y, int m) {
             C drho, ux, uy;
             bgk(f, omega, drho, ux, uy);
             if (lvl < N) {
@@ -1136,16 +1149,16 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     PR::st(&q, f[i], sc);
                     v[i] = PR::ld(&q, inv);
                 }
-                put(lvl - 1, y, lc, v);
-                if (c == nx - 1) put(lvl - 1, y, 0, v);       // left copy of the last column
-                if (c == 0) put(lvl - 1, y, nx + 1, v);       // right copy of the first column
+                put(lvl - 1, y, c[m] + 1, v);
+                if (c[m] == nx - 1) put(lvl - 1, y, 0, v);   // left copy of the last column
+                if (c[m] == 0) put(lvl - 1, y, nx + 1, v);   // right copy of the first column
             } else if (nt) {
-                const int own = y * (int)j.pitch + c;
+                const int own = y * (int)j.pitch + c[m];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
             } else {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], vo0, i * plane_b + y * pitch_b, sc);
+                for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], vo0[m], i * plane_b + y * pitch_b, sc);
             }
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
@@ -1164,23 +1177,31 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 if (lvl == 1) {
                     if (row_on) {
                         pull(buf[(k + D) % B], min(y + D, y1_end - 1));
-                        if (lane_on) {
-                            C f[9];
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][i], inv);
-                            finish(f, y);
-                        }
+                        for (int m = 0; m < M; ++m)
+                            if (on[m]) {
+                                C f[9];
+#pragma unroll
+                                for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][m][i], inv);
+                                finish(f, y, m);
+                            }
                     }
-                } else if (row_on && lane_on) {
-                    C f[9];
+                } else if (row_on) {
                     const int L = lvl - 2;
                     const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const int g = GJd[i], cl = lc - CXd[i];
-                        f[i] = CYd[i] < 0 ? ra[L][sa][g][cl] : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
-                    }
-                    finish(f, y);
+                    for (int m = 0; m < M; ++m)
+                        if (on[m]) {
+                            C f[9];
+                            const int lc = c[m] + 1;
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) {
+                                const int g = GJd[i], cl = lc - CXd[i];
+                                f[i] = CYd[i] < 0 ? ra[L][sa][g][cl]
+                                                  : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
+                            }
+                            finish(f, y, m);
+                        }
                 }
                 __syncthreads();
             }
@@ -1751,38 +1772,61 @@ static void stepW_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
     k_stepW<P, N, D><<<(unsigned)G, 64 * N, 0, s>>>(j, src2, W, strips, H, chunks, nwork, nt);
 }
 
-// full-row kernel: K = ceil(nx / 64) waves per level, N K <= 16 waves, LDS
-// rows within 160 KB
-template <int P, int N, int K>
+// full-row kernel: K waves per level of M columns per lane cover nx, with
+// N K <= 16 waves and (N - 1) 27 LDS rows of 64 K M + 2 values within 160 KB
+template <int P, int N, int K, int M>
 static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
     const int H = std::max(8, std::min(rows, j.ny));
     const int chunks = (j.ny + H - 1) / H;
     const int64_t nwork = (int64_t)j.S * chunks;
     const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
-    k_stepR<P, N, K, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, src2, H, chunks, nwork, nt);
+    k_stepR<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, src2, H, chunks, nwork, nt);
+}
+
+template <int P, int N>
+static constexpr bool rows_fit(int K, int M) {
+    return N * K <= 16 && (int64_t)(N - 1) * 27 * (64 * K * M + 2) * (P == UQ_FP64 ? 8 : 4) <= 160 * 1024;
+}
+
+// the shape used for a lattice nx wide: the fewest columns per lane (M = 1,
+// else 2) whose K = ceil(nx / 64 M) fits; 0 if none
+static int rows_shape(int prec, int n, int nx, int *K, int *M) {
+    const int b = prec == UQ_FP64 ? 8 : 4;
+    for (int m = 1; m <= 2; ++m) {
+        const int k = std::max(2, (nx + 64 * m - 1) / (64 * m));
+        if (k > 4) continue;
+        if (n * k <= 16 && (int64_t)(n - 1) * 27 * (64 * k * m + 2) * b <= 160 * 1024) {
+            *K = k;
+            *M = m;
+            return 1;
+        }
+    }
+    return 0;
 }
 
 template <int P, int N>
 static void stepR_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
-    const int K = (j.nx + 63) / 64;
-    if constexpr (N * 2 <= 16) {
-        if (K <= 2) return stepR_k<P, N, 2>(j, src2, rows, nt, s);
+    int K = 0, M = 0;
+    if (!rows_shape(P, N, j.nx, &K, &M)) return;
+#define UQ_ROWS_CASE(k, m)                                                        \
+    if constexpr (rows_fit<P, N>(k, m)) {                                         \
+        if (K == k && M == m) return stepR_k<P, N, k, m>(j, src2, rows, nt, s);   \
     }
-    if constexpr (N * 3 <= 16) {
-        if (K == 3) return stepR_k<P, N, 3>(j, src2, rows, nt, s);
-    }
-    if constexpr (N * 4 <= 16 && (P != UQ_FP64 || N < 4)) {
-        if (K == 4) return stepR_k<P, N, 4>(j, src2, rows, nt, s);
-    }
+    UQ_ROWS_CASE(2, 1)
+    UQ_ROWS_CASE(3, 1)
+    UQ_ROWS_CASE(4, 1)
+    UQ_ROWS_CASE(2, 2)
+    UQ_ROWS_CASE(3, 2)
+    UQ_ROWS_CASE(4, 2)
+#undef UQ_ROWS_CASE
 }
 
 int full_rows_max_nx(int prec, int n) {
-    // 64 K columns with N K <= 16 waves and (N - 1) 27 rows of 64 K + 2
-    // values in LDS
-    const int b = prec == UQ_FP64 ? 8 : 4;
     int best = 0;
-    for (int K = 2; K <= 4; ++K)
-        if (n * K <= 16 && (int64_t)(n - 1) * 27 * (64 * K + 2) * b <= 160 * 1024) best = 64 * K;
+    for (int nx = 64; nx <= 512; nx += 64) {
+        int K, M;
+        if (rows_shape(prec, n, nx, &K, &M)) best = nx;
+    }
     return best;
 }
 
@@ -1791,7 +1835,9 @@ static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool
     if (window == 2) {
         if (n == 2) stepR_p<P, 2>(j, src2, fty, nt, s);
         else if (n == 3) stepR_p<P, 3>(j, src2, fty, nt, s);
-        else stepR_p<P, 4>(j, src2, fty, nt, s);
+        else if (n == 4) stepR_p<P, 4>(j, src2, fty, nt, s);
+        else if (n == 5) stepR_p<P, 5>(j, src2, fty, nt, s);
+        else stepR_p<P, 6>(j, src2, fty, nt, s);
     } else if (window) {
         if (n == 2) stepW_p<P, 2>(j, src2, fty, nt, s);
         else if (n == 3) stepW_p<P, 3>(j, src2, fty, nt, s);
@@ -1804,7 +1850,7 @@ static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool
 }
 
 hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s) {
-    if (!fused_supported(j) || n < 2 || n > 4) return hipErrorInvalidValue;
+    if (!fused_supported(j) || n < 2 || n > (window == 2 ? 6 : 4)) return hipErrorInvalidValue;
     if (window == 2 && j.nx > full_rows_max_nx(j.prec, n)) return hipErrorInvalidValue;
     switch (j.prec) {
         case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, window, nt, s); break;

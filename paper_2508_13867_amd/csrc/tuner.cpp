@@ -98,8 +98,8 @@ using namespace uqi;
 extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out) {
     if (!p || !out) return fail(UQ_EINVAL, "null argument");
     if (steps < 2) return fail(UQ_EINVAL, "steps must be >= 2");
-    steps = steps / 24 * 24;  // whole fused blocks (4, 3 and 8 steps)
-    if (steps < 24) steps = 24;
+    steps = steps / 120 * 120;  // whole fused blocks (4, 3, 8, 5 and 12 steps)
+    if (steps < 120) steps = 120;
     Rule r;
     uq_status st = build_rule(*p, r);
     if (st != UQ_OK) return st;
@@ -137,9 +137,10 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         cands.push_back(s);
                     }
             for (int win : {1, 2})
-                for (int n : {2, 3, 4})
+                for (int n : {2, 3, 4, 5, 6})
                     for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{32, 64} : std::vector<int>{64, 256})) {
-                        if (win == 2 && p->nx > full_rows_max_nx(p->precision, n)) continue;
+                        if (win == 1 && n > 4) continue;  // strips: up to 4 steps
+                        if (win == 2 && (n < 3 || p->nx > full_rows_max_nx(p->precision, n))) continue;
                         StepShape s;
                         s.layout = layout;
                         s.pad = 64;
@@ -165,7 +166,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
         double ms = 0.0;
         hipEvent_t a = nullptr, b = nullptr;
         bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-        ok = ok && j->advance(24) == UQ_OK;  // warm-up (whole fused blocks of 2, 3 or 4 steps)
+        ok = ok && j->advance(120) == UQ_OK;  // warm-up (whole fused blocks of 2 to 6 steps)
         ok = ok && hipEventRecord(a, j->stream) == hipSuccess;
         ok = ok && j->advance(steps) == UQ_OK;
         ok = ok && hipEventRecord(b, j->stream) == hipSuccess;

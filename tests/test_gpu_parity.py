@@ -291,9 +291,9 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     r = A.autotune(spec, steps=10)
     # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes
     # idle), plus 12 fused tile candidates (2, 3, 4 steps x 2 pads x 2 tile
-    # heights) and 6 sliding-window and 6 full-row ones (2, 3, 4 steps x 2
-    # chunk heights)
-    assert r["n_candidates"] == 48 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # heights), 6 sliding-window ones (2, 3, 4 steps x 2 chunk heights) and 8
+    # full-row ones (3, 4, 5, 6 steps x 2 chunk heights)
+    assert r["n_candidates"] == 50 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
         assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows,
@@ -385,6 +385,49 @@ def test_fused_kernel_small_and_wrapping_lattices(nx, ny, window, n, monkeypatch
         p = O.sample_params(spec, xi[3])
         ref = O.tgv_run(nx, ny, p["nu"], p["u0"], 24, want_f=True)["f"]
         assert np.abs(job.populations(3) - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [5, 6])
+@pytest.mark.parametrize("nx, ny, rows", [(72, 40, 16), (72, 40, 256), (20, 12, 8), (3, 5, 8), (2, 4, 8),
+                                          (128, 9, 64)])
+def test_full_row_kernel_five_and_six_steps(nx, ny, rows, n, monkeypatch):
+    # 5 and 6 steps per launch exist only over whole rows (two columns per
+    # lane where one would need more than 16 waves); FP64 against the oracle
+    # over counts that leave single steps after the fused blocks
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision="fp64")
+    say("case full rows", n, "lattice", nx, ny, "rows", rows)
+    for steps in (n + 1, 4 * n + 3):
+        with Job(spec) as job:
+            assert job.info().fused == n and job.info().fused_window == 2
+            job.run(steps)
+            xi, _ = job.samples()
+            p = O.sample_params(spec, xi[5])
+            ref = O.tgv_run(nx, ny, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+            assert np.abs(job.populations(5) - ref).max() < 1e-13, steps
+
+
+@pytest.mark.parametrize("n", [5, 6])
+@pytest.mark.parametrize("prec", ["fp32", "bf16s"])
+def test_full_row_kernel_five_and_six_steps_full_size(prec, n, monkeypatch):
+    # the 256^2 x 256 lattice (two waves of two columns per lane per step),
+    # against single steps
+    spec = W.scaled(W.TGV_BATCHED_FP32, precision=prec, layout="ab", steps=60)
+    say("case full rows", n, "256^2 x 256", prec)
+    res = {}
+    for fuse in ("0", str(n)):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        monkeypatch.setenv("UQ_FUSE_TY", "256")
+        monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+        with Job(spec) as job:
+            assert job.info().fused == (n if fuse != "0" else 0)
+            job.run(60)
+            res[fuse] = (job.populations(200), job.qoi_samples("ke")[:, 0])
+    tol = 1e-6 if prec == "fp32" else 1e-4
+    assert np.abs(res["0"][0] - res[str(n)][0]).max() < tol
+    assert rel_l2(res[str(n)][1], res["0"][1]) < tol
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
