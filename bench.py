@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16s": 2, "bf16s": 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_13867_amd", "csrc", "lbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_tgv256_fp32.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_k_stepR_tgv256_fp32.json")
+VALU_ISSUE_PER_S = 256 * 2.4e9  # one wave64 VALU instruction per CU and cycle
 
 
 def log(*a):
@@ -52,6 +54,21 @@ def measured_traffic(kernel_prefix):
     if not any(k.replace("void ", "").startswith(kernel_prefix) for k in t.get("kernel", [])):
         return None
     return t.get("bytes_per_launch")
+
+
+def measured_valu(kernel_prefix):
+    """VALU instructions per step launch from the committed rocprofv3 counter
+    run, if taken on the current kernel source and kernel instance; else
+    None."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    with open(VALU_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    if not any(k.replace("void ", "").startswith(kernel_prefix) for k in t.get("kernel", [])):
+        return None
+    return t
 
 
 def copy_probe(torch, nbytes=1207959552, reps=10):
@@ -547,6 +564,7 @@ def main():
     else:
         kprefix = "uqi::k_step<"
     traffic = measured_traffic(kprefix)
+    valu = measured_valu(kprefix)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ({0: f"uqi::k_stepN<..., N={nfuse}>", 1: f"uqi::k_stepW<..., N={nfuse}>",
@@ -556,6 +574,12 @@ def main():
             "bytes_per_node_update": round(bpn / nfuse, 3), "launches": launches,
             "launch_ms": round(per_launch_ms, 5), "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4)}
+    if valu is not None:
+        # the second bound of the fused kernels: VALU instruction issue
+        roof["valu_issue"] = {"insts_per_launch": valu["valu_insts_per_launch"],
+                              "lane_ops_per_update": round(valu["valu_lane_ops_per_update"], 2),
+                              "frac": round(valu["valu_insts_per_launch"] / (per_launch_ms * 1e-3 * VALU_ISSUE_PER_S), 4),
+                              "capacity": "256 CUs x 2.4 GHz, one wave64 VALU instruction per CU per cycle"}
 
     out = {
         "metric": "aggregate MLUPS & % HBM peak; UQ solves/hr + p50/p99 latency vs plain",
