@@ -47,6 +47,8 @@ struct Prec<UQ_FP64> {
     __device__ static inline C ld(const T *p, float) { return *p; }
     __device__ static inline void st(T *p, C v, float) { *p = v; }
     __device__ static inline void st_nt(T *p, C v, float) { __builtin_nontemporal_store(v, p); }
+    // the value a store and a reload would give back
+    __device__ static inline C rt(C v, float, float) { return v; }
 };
 template <>
 struct Prec<UQ_FP32> {
@@ -55,6 +57,7 @@ struct Prec<UQ_FP32> {
     __device__ static inline C ld(const T *p, float) { return *p; }
     __device__ static inline void st(T *p, C v, float) { *p = v; }
     __device__ static inline void st_nt(T *p, C v, float) { __builtin_nontemporal_store(v, p); }
+    __device__ static inline C rt(C v, float, float) { return v; }
 };
 template <>
 struct Prec<UQ_FP16S> {
@@ -65,6 +68,7 @@ struct Prec<UQ_FP16S> {
     __device__ static inline C ld(const T *p, float inv) { return (float)(*p) * inv; }
     __device__ static inline void st(T *p, C v, float sc) { *p = (_Float16)(v * sc); }
     __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store((_Float16)(v * sc), p); }
+    __device__ static inline C rt(C v, float sc, float inv) { return (float)(_Float16)(v * sc) * inv; }
 };
 template <>
 struct Prec<UQ_BF16S> {
@@ -81,6 +85,13 @@ struct Prec<UQ_BF16S> {
     }
     __device__ static inline void st(T *p, C v, float sc) { *p = rne(v * sc); }
     __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store(rne(v * sc), p); }
+    // bfloat16 has float's exponent range, so scaling by the power of two sc
+    // and back commutes with the rounding: round in place
+    __device__ static inline C rt(C v, float, float) {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return __uint_as_float(u & 0xFFFF0000u);
+    }
 };
 
 // ------------------------------------------------------------------ lattice
@@ -843,11 +854,7 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
                         C drho, ux, uy;
                         bgk(f[q2], omega, drho, ux, uy);
 #pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            T q;
-                            PR::st(&q, f[q2][i], sc);
-                            lds[i][rr[k]][cc[k]] = PR::ld(&q, inv);
-                        }
+                        for (int i = 0; i < 9; ++i) lds[i][rr[k]][cc[k]] = PR::rt(f[q2][i], sc, inv);
                     }
                 }
             }
@@ -890,11 +897,7 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
             for (int k = 0; k < PERM; ++k) {
                 if (tid + 256 * k < n_el) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        T q;
-                        PR::st(&q, g[k][i], sc);
-                        lds[i][rr[k]][cc[k]] = PR::ld(&q, inv);
-                    }
+                    for (int i = 0; i < 9; ++i) lds[i][rr[k]][cc[k]] = PR::rt(g[k][i], sc, inv);
                 }
             }
             __syncthreads();
@@ -1004,9 +1007,7 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
                 const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    T q;
-                    PR::st(&q, f[i], sc);
-                    const C v = PR::ld(&q, inv);
+                    const C v = PR::rt(f[i], sc, inv);
                     const int g = GJd[i];
                     if (CYd[i] < 0) ra[L][sa][g][lc] = v;
                     else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
@@ -1144,11 +1145,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
             if (lvl < N) {
                 C v[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    T q;
-                    PR::st(&q, f[i], sc);
-                    v[i] = PR::ld(&q, inv);
-                }
+                for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[i], sc, inv);
                 put(lvl - 1, y, c[m] + 1, v);
                 if (c[m] == nx - 1) put(lvl - 1, y, 0, v);   // left copy of the last column
                 if (c[m] == 0) put(lvl - 1, y, nx + 1, v);   // right copy of the first column
