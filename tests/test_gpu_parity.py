@@ -304,6 +304,36 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
         assert rel_l2(job.qoi_samples("ke")[:, 0], ref["samples"]["ke"]) < TOL["fp32"]
 
 
+def test_tune_cache_file_carries_the_shape_to_another_process(tmp_path, monkeypatch):
+    # uq_autotune appends its choice to the file named by UQ_TUNE_CACHE; a
+    # fresh process reads it back and gives the same problem class that shape
+    import json
+    import subprocess
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("UQ_TUNE_CACHE", str(cache))
+    spec = W.scaled(TGV_4D_SMALL, name="tgv96x80_cache", ny=72, steps=20)
+    say("case tune cache")
+    r = A.autotune(spec, steps=10)
+    fields = cache.read_text().split()
+    assert len(fields) == 15
+    want = {"layout": {1: "aa", 2: "ab"}[int(fields[6])], "cpt": int(fields[7]), "plane_pad": int(fields[9]),
+            "bx": int(fields[10]), "fused": int(fields[11]) if int(fields[11]) >= 2 else 0,
+            "fused_window": int(fields[13]) if int(fields[11]) >= 2 else 0}
+    assert want == {k: r[k] for k in want}
+    code = ("import json, sys; from paper_2508_13867_amd import Job; spec = json.loads(sys.argv[1]); "
+            "j = Job(spec); i = j.info(); "
+            "print(json.dumps(dict(layout={1: 'aa', 2: 'ab'}[i.layout], cpt=i.cpt, plane_pad=i.plane_pad, bx=i.bx, "
+            "fused=i.fused, fused_window=i.fused_window))); j.close()")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, UQ_TUNE_CACHE=str(cache), PYTHONPATH=root)
+    for k in ("UQ_FUSE", "UQ_FUSE_TY", "UQ_FUSE_WINDOW", "UQ_LAYOUT"):
+        env.pop(k, None)
+    out = subprocess.run([sys.executable, "-c", code, json.dumps(spec)], env=env, capture_output=True, text=True,
+                         timeout=120, cwd=root)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert json.loads(out.stdout.strip().splitlines()[-1]) == want
+
+
 def test_mc4096_full_size_precisions_vs_fp64_and_oracle():
     # the 128^2 x 4096-sample Monte Carlo workload at full size and length:
     # FP64 re-checked on sampled samples by the oracle, FP32 and FP16-storage
