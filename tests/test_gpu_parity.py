@@ -480,15 +480,19 @@ def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     assert rel_l2(res[str(n)][1], res["0"][1]) < tol
 
 
-@pytest.mark.parametrize("n, window", [(2, 0), (3, 0), (4, 1), (4, 2), (3, 2)])
-def test_fused_kernel_full_size_sampled(n, window, monkeypatch):
-    # the 256^2 x 256 benchmark lattice, fused, 120 steps
+@pytest.mark.parametrize("n, window, rows, nt", [(2, 0, 8, 1), (3, 0, 8, 1), (4, 1, 64, 0), (4, 2, 256, 0),
+                                                 (3, 2, 256, 0), (5, 2, 256, 0), (6, 2, 256, 0)])
+def test_fused_kernel_full_size_sampled(n, window, rows, nt, monkeypatch):
+    # the 256^2 x 256 benchmark lattice, fused, 120 steps, two samples
+    # re-solved by the oracle
     monkeypatch.setenv("UQ_FUSE", str(n))
     monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
+    monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    monkeypatch.setenv("UQ_NT_STORE", str(nt))
     spec = W.scaled(W.TGV_BATCHED_FP32, steps=120, layout="ab")
-    say("case fused", n, "256^2 x 256")
+    say("case fused", n, "window", window, "rows", rows, "256^2 x 256")
     with Job(spec) as job:
-        assert job.info().fused == n
+        assert job.info().fused == n and job.info().fused_window == window
         job.run(spec["steps"])
         ke = job.qoi_samples("ke")[:, 0]
         pick = [0, 200]
@@ -496,6 +500,31 @@ def test_fused_kernel_full_size_sampled(n, window, monkeypatch):
         assert rel_l2(ke[pick], ref["samples"]["ke"]) < TOL["fp32"]
         vel = job.qoi_samples("vel")
         assert rel_l2(vel[pick], ref["samples"]["vel"].reshape(2, -1)) < TOL["fp32"]
+
+
+def test_benchmark_workload_in_its_tuned_launch_shape(tmp_path, monkeypatch):
+    # the benchmark's own path: tune the 256^2 x 256 FP32 job as bench.py
+    # does, then run it in the chosen shape (graph replay included) and
+    # re-solve sampled samples with the oracle
+    monkeypatch.setenv("UQ_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    for k in ("UQ_FUSE", "UQ_FUSE_TY", "UQ_FUSE_WINDOW", "UQ_NT_STORE", "UQ_LAYOUT"):
+        monkeypatch.delenv(k, raising=False)
+    spec = W.scaled(W.TGV_BATCHED_FP32, steps=250)
+    say("case benchmark shape: tuning")
+    r = A.autotune(spec, steps=120)
+    say("tuned", r)
+    with Job(spec) as job:
+        inf = job.info()
+        assert (inf.fused, inf.fused_window, inf.fused_rows) == (r["fused"], r["fused_window"], r["fused_rows"])
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        vel = job.qoi_samples("vel")
+        pick = [3, 129, 255]
+        ref = O.run_problem(spec, samples=pick, qois=["ke", "vel"])
+        assert rel_l2(ke[pick], ref["samples"]["ke"]) < TOL["fp32"]
+        assert rel_l2(vel[pick], ref["samples"]["vel"].reshape(3, -1)) < TOL["fp32"]
+        st = job.moments("ke")
+        assert abs(st["mean"][0] - float(np.dot(job.samples()[1], ke))) <= 1e-12 * abs(st["mean"][0])
 
 
 def test_fused_graph_replay_equals_eager(monkeypatch):
