@@ -1139,23 +1139,34 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 else rc[L][sc3][g][col] = v[i];
             }
         };
-        auto finish = [&](C *f, int y, int m) {
-            C drho, ux, uy;
-            bgk(f, omega, drho, ux, uy);
-            if (lvl < N) {
-                C v[9];
+        // collide the lane's M nodes of row y together (independent work for
+        // the scheduler to interleave; lanes past the lattice compute on
+        // valid but unused data) and hand each on to the next level
+        auto finish = [&](C (*f)[9], int y) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[i], sc, inv);
-                put(lvl - 1, y, c[m] + 1, v);
-                if (c[m] == nx - 1) put(lvl - 1, y, 0, v);   // left copy of the last column
-                if (c[m] == 0) put(lvl - 1, y, nx + 1, v);   // right copy of the first column
-            } else if (nt) {
-                const int own = y * (int)j.pitch + c[m];
+            for (int m = 0; m < M; ++m) {
+                C drho, ux, uy;
+                bgk(f[m], omega, drho, ux, uy);
+            }
 #pragma unroll
-                for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[i], sc);
-            } else {
+            for (int m = 0; m < M; ++m) {
+                if (!on[m]) continue;
+                if (lvl < N) {
+                    C v[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) BufSt<P>::st(wrsrc, f[i], vo0[m], i * plane_b + y * pitch_b, sc);
+                    for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
+                    put(lvl - 1, y, c[m] + 1, v);
+                    if (c[m] == nx - 1) put(lvl - 1, y, 0, v);   // left copy of the last column
+                    if (c[m] == 0) put(lvl - 1, y, nx + 1, v);   // right copy of the first column
+                } else if (nt) {
+                    const int own = y * (int)j.pitch + c[m];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[m][i], sc);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        BufSt<P>::st(wrsrc, f[m][i], vo0[m], i * plane_b + y * pitch_b, sc);
+                }
             }
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
@@ -1174,31 +1185,28 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 if (lvl == 1) {
                     if (row_on) {
                         pull(buf[(k + D) % B], min(y + D, y1_end - 1));
+                        C f[M][9];
 #pragma unroll
                         for (int m = 0; m < M; ++m)
-                            if (on[m]) {
-                                C f[9];
 #pragma unroll
-                                for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][m][i], inv);
-                                finish(f, y, m);
-                            }
+                            for (int i = 0; i < 9; ++i) f[m][i] = BufLd<P>::cvt(buf[k][m][i], inv);
+                        finish(f, y);
                     }
                 } else if (row_on) {
                     const int L = lvl - 2;
                     const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
+                    C f[M][9];
 #pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        if (on[m]) {
-                            C f[9];
-                            const int lc = c[m] + 1;
+                    for (int m = 0; m < M; ++m) {
+                        const int lc = c[m] + 1;  // <= 64 K M - 1 + 1: inside the row even past the lattice
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) {
-                                const int g = GJd[i], cl = lc - CXd[i];
-                                f[i] = CYd[i] < 0 ? ra[L][sa][g][cl]
-                                                  : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
-                            }
-                            finish(f, y, m);
+                        for (int i = 0; i < 9; ++i) {
+                            const int g = GJd[i], cl = lc - CXd[i];
+                            f[m][i] = CYd[i] < 0 ? ra[L][sa][g][cl]
+                                                 : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
                         }
+                    }
+                    finish(f, y);
                 }
                 __syncthreads();
             }
