@@ -75,8 +75,14 @@ void Job::release_graph() {
 
 // steps per fused launch in effect (0: none)
 int Job::fused_n() const {
+    if (shape.fuse < 2) return 0;
+    if (jd.geom == 1)  // channel: whole rows, up to 4 steps, where the LDS rows fit
+        return (shape.fwin == 2 && shape.fuse <= 4 && channel_fusable(jd) &&
+                jd.nx <= channel_rows_max_nx(jd.prec, shape.fuse))
+                   ? shape.fuse
+                   : 0;
     const int nmax = shape.fwin == 2 ? 6 : 4;  // whole rows: up to 6 steps
-    return (shape.fuse >= 2 && shape.fuse <= nmax && fused_supported(jd)) ? shape.fuse : 0;
+    return (shape.fuse <= nmax && fused_supported(jd)) ? shape.fuse : 0;
 }
 
 // Launches for `n` steps starting at step t + k0 of the host mirror. The
@@ -93,10 +99,10 @@ hipError_t Job::enqueue_steps(int k0, int64_t n) {
         const int64_t block = (N & 1) ? N : 2 * N;
         for (; k + block <= n && e == hipSuccess; k += block) {
             const bool odd = ((t + k0 + k) & 1) != 0;
-            e = launch_fused(jd, N, odd, shape.fty, shape.fwin, shape.nt != 0, stream);
+            e = launch_fused(jd, N, odd, shape.fty, shape.fwin, shape.nt != 0, d_t, (int)(k0 + k), stream);
             ++enqueued;
             if (e == hipSuccess && !(N & 1)) {
-                e = launch_fused(jd, N, !odd, shape.fty, shape.fwin, shape.nt != 0, stream);
+                e = launch_fused(jd, N, !odd, shape.fty, shape.fwin, shape.nt != 0, d_t, (int)(k0 + k + N), stream);
                 ++enqueued;
             }
         }

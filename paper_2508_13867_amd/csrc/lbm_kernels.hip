@@ -216,13 +216,22 @@ __device__ inline double ramp_factor(int64_t t, double T) {
     return s * s;
 }
 
+// inflow profile u_x at row y, time t: s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2,
+// from a = s(t) 4 u_peak
+__device__ inline double inflow_u_a(double a, int ny, int y) {
+    const double H = (double)ny, yy = (double)y + 0.5;
+    return a * yy * (H - yy) / (H * H);
+}
+__device__ inline double inflow_u(int ny, double ramp, int y, int64_t t, double u_peak) {
+    return inflow_u_a(ramp_factor(t, ramp) * 4.0 * u_peak, ny, y);
+}
+
 // Zou-He (1997) completion of the unknown populations on the open columns,
-// written for shifted populations (the weights cancel in every relation).
+// written for shifted populations (the weights cancel in every relation):
+// the inlet with the imposed velocity u, the outlet at rho = 1.
 template <typename C>
-__device__ inline void zou_he(C f[9], const JobDev &j, int x, int y, int64_t t, double u_peak) {
-    if (x == 0) {
-        const double H = (double)j.ny, yy = (double)y + 0.5;
-        const C u = (C)(ramp_factor(t, j.ramp) * 4.0 * u_peak * yy * (H - yy) / (H * H));
+__device__ inline void zou_he_u(C f[9], bool inlet, C u) {
+    if (inlet) {
         const C S = (f[0] + f[2] + f[4]) + C(2) * (f[3] + f[6] + f[7]);
         const C drho = (S + u) / (C(1) - u);
         const C ru = (C(1) + drho) * u;
@@ -230,11 +239,16 @@ __device__ inline void zou_he(C f[9], const JobDev &j, int x, int y, int64_t t, 
         f[5] = f[7] - C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
         f[8] = f[6] + C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
     } else {
-        const C u = (f[0] + f[2] + f[4]) + C(2) * (f[1] + f[5] + f[8]);  // rho = 1
-        f[3] = f[1] - (C(2) / C(3)) * u;
-        f[7] = f[5] + C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * u;
-        f[6] = f[8] - C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * u;
+        const C v = (f[0] + f[2] + f[4]) + C(2) * (f[1] + f[5] + f[8]);
+        f[3] = f[1] - (C(2) / C(3)) * v;
+        f[7] = f[5] + C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * v;
+        f[6] = f[8] - C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * v;
     }
+}
+
+template <typename C>
+__device__ inline void zou_he(C f[9], const JobDev &j, int x, int y, int64_t t, double u_peak) {
+    zou_he_u(f, x == 0, x == 0 ? (C)inflow_u(j.ny, j.ramp, y, t, u_peak) : C(0));
 }
 
 // Addressing inside one sample's slab.
@@ -296,10 +310,8 @@ template <int P, bool CHANNEL, int MODE, bool FD = true, bool QL = true>
 __device__ inline void gather(const JobDev &j, const typename Prec<P>::T *base, const Site &s, uint32_t m,
                               int64_t t, double u_peak, double omega, typename Prec<P>::C f[9]);
 
-// inflow profile u_x at row y, time t: s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2
 __device__ inline double inlet_ux(const JobDev &j, int y, int64_t t, double u_peak) {
-    const double H = (double)j.ny, yy = (double)y + 0.5;
-    return ramp_factor(t, j.ramp) * 4.0 * u_peak * yy * (H - yy) / (H * H);
+    return inflow_u(j.ny, j.ramp, y, t, u_peak);
 }
 
 // velocity of an outlet-column node from its known populations (rho = 1)
@@ -1214,6 +1226,206 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     }
 }
 
+// ------------------------------------------------------------------ fused channel steps, full rows
+// The full-row pipeline on the channel with half-way bounce-back walls and
+// cylinder and Zou-He inlet / outlet (no interpolated rules): the same wall
+// and open-column rules as the single-step gather, applied at every level.
+// A bounce-back pull takes the node's own opposite population of the level
+// below, so the LDS also keeps the row being computed: 3 rows of the
+// c_y = -1 directions (their opposites), 3 of c_y = 0, 4 of c_y = +1. Rows
+// outside the channel are not computed (their pulls are bounce-backs);
+// along x the end columns are open, walls or periodic, as the node masks
+// say. Solid nodes are skipped.
+// Level L of a launch computes step t0 + L - 1 (the inflow ramp).
+template <int P, int N, int K, int M, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *d_t, int k0, bool src2, int H,
+                                                       int chunks, int64_t nwork) {
+    using PR = Prec<P>;
+    using C = typename PR::C;
+    using T = typename PR::T;
+    constexpr int RG = N - 1;
+    constexpr int NR = N > 1 ? N - 1 : 1;
+    constexpr int CW = 64 * K * M + 2;
+    constexpr uint32_t BB_BITS = 0x1FFu << M_BB, OPEN_BITS = 0x1FFu << M_OPEN;
+    __shared__ C ra[NR][3][3][CW], rb[NR][3][3][CW], rc[NR][4][3][CW];
+    const int64_t t0 = *d_t + k0;
+    const T *src_all = (const T *)(src2 ? j.f2 : j.f);
+    T *dst_all = (T *)(src2 ? j.f : j.f2);
+    const int nx = j.nx, ny = j.ny;
+    const int plane = (int)j.plane;
+    const int plane_b = plane * (int)sizeof(T), pitch_b = (int)j.pitch * (int)sizeof(T);
+    const float inv = j.inv_scale, sc = j.scale;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lvl = wave / K + 1;  // 1..N
+    const int64_t t_lvl = t0 + (lvl - 1);
+    int c[M], vo0[M], vom[M], vop[M], mvo[M];
+    bool on[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        c[m] = ((wave - (lvl - 1) * K) * M + m) * 64 + lane;
+        on[m] = c[m] < nx;
+        const int cc = on[m] ? c[m] : nx - 1;
+        mvo[m] = cc * 4;
+        vo0[m] = cc * (int)sizeof(T);
+        vom[m] = (cc == 0 ? nx - 1 : cc - 1) * (int)sizeof(T);
+        vop[m] = (cc == nx - 1 ? 0 : cc + 1) * (int)sizeof(T);
+    }
+    const __amdgpu_buffer_rsrc_t mrsrc = make_rsrc(j.mask, ny * (int)j.pitch * 4);
+    const int span = RG - (lvl - 1);
+    const int64_t G = gridDim.x;
+    constexpr int B = D + 1;
+    using R = typename BufLd<P>::R;
+    R buf[B][M][9];
+    uint32_t mb[B][M];
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / chunks;
+        const int chunk = (int)(wk - smp * chunks);
+        const int yb = chunk * H, ye = min(ny, yb + H);
+        const int lo = max(0, yb - span), hi = min(ny, ye + span);  // this level's rows
+        const T *src = src_all + smp * 9 * (int64_t)plane;
+        T *dst = dst_all + smp * 9 * (int64_t)plane;
+        const C omega = (C)j.smp[smp].omega;
+        // s(t) 4 u_peak of this level's step (uniform)
+        const double a_in = ramp_factor(t_lvl, j.ramp) * 4.0 * j.smp[smp].u_peak;
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, 9 * plane_b), wrsrc = make_rsrc(dst, 9 * plane_b);
+        auto clampy = [&](int y) { return y < 0 ? 0 : (y >= ny ? ny - 1 : y); };
+        auto pull = [&](R (*f)[9], int y) {
+            const int gy = clampy(y);
+            const int r0 = gy * pitch_b, rm = (gy == 0 ? ny - 1 : gy - 1) * pitch_b,
+                      rp = (gy == ny - 1 ? 0 : gy + 1) * pitch_b;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int vo = CXd[i] > 0 ? vom[m] : (CXd[i] < 0 ? vop[m] : vo0[m]);
+                    const int ro = CYd[i] > 0 ? rm : (CYd[i] < 0 ? rp : r0);
+                    f[m][i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
+                }
+        };
+        auto pullm = [&](uint32_t *mm, int y) {
+            const int mo = clampy(y) * (int)j.pitch * 4;
+#pragma unroll
+            for (int m = 0; m < M; ++m) mm[m] = __builtin_amdgcn_raw_buffer_load_b32(mrsrc, mvo[m], mo, 0);
+        };
+        auto put = [&](int L, int y, int col, const C *v) {
+            const int s3 = (y + 12) % 3, s4 = (y + 12) & 3;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int g = GJd[i];
+                if (CYd[i] < 0) ra[L][s3][g][col] = v[i];
+                else if (CYd[i] == 0) rb[L][s3][g][col] = v[i];
+                else rc[L][s4][g][col] = v[i];
+            }
+        };
+        // the open-column rule, then collide, then hand on or store
+        auto finish = [&](C (*f)[9], const uint32_t *mm, int y) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (mm[m] & OPEN_BITS) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) f[m][i] = ((mm[m] >> (M_OPEN + i)) & 1u) ? C(0) : f[m][i];
+                    if (t_lvl > 0)
+                        zou_he_u(f[m], c[m] == 0, c[m] == 0 ? (C)inflow_u_a(a_in, ny, y) : C(0));
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                C drho, ux, uy;
+                bgk(f[m], omega, drho, ux, uy);
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!on[m] || (mm[m] & M_SOLID)) continue;
+                if (lvl < N) {
+                    C v[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
+                    put(lvl - 1, y, c[m] + 1, v);
+                    // end-column copies (read only when x is periodic)
+                    if (c[m] == nx - 1) put(lvl - 1, y, 0, v);
+                    if (c[m] == 0) put(lvl - 1, y, nx + 1, v);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        BufSt<P>::st(wrsrc, f[m][i], vo0[m], i * plane_b + y * pitch_b, sc);
+                }
+            }
+        };
+        const int y_first = yb - RG - 2 * (lvl - 1);  // this level's row at iteration 0
+        if (lvl == 1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) pull(buf[k], yb - RG + k);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) pullm(mb[k], y_first + k);
+        const int n_it = (ye - yb) + 3 * RG;
+        for (int it0 = 0; it0 < n_it; it0 += B) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int it = it0 + k;
+                if (it >= n_it) break;
+                const int y = y_first + it;  // this level's row (wave-uniform)
+                const bool row_on = y >= lo && y < hi;
+                pullm(mb[(k + D) % B], y + D);
+                if (lvl == 1) {
+                    pull(buf[(k + D) % B], y + D);
+                    if (row_on) {
+                        C f[M][9];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) f[m][i] = BufLd<P>::cvt(buf[k][m][i], inv);
+                            if (mb[k][m] & BB_BITS) {
+                                // bounce-back: the node's own opposite population
+#pragma unroll
+                                for (int i = 0; i < 9; ++i) {
+                                    const C o = BufLd<P>::ld(rsrc, vo0[m], OPPd[i] * plane_b + y * pitch_b, inv);
+                                    f[m][i] = ((mb[k][m] >> (M_BB + i)) & 1u) ? o : f[m][i];
+                                }
+                            }
+                        }
+                        finish(f, mb[k], y);
+                    }
+                } else if (row_on) {
+                    const int L = lvl - 2;
+                    const int pa = (y + 13) % 3, pb = (y + 12) % 3, pc = (y + 11) & 3;  // pull rows
+                    const int oa = (y + 12) % 3, oc = (y + 12) & 3;                     // own row
+                    C f[M][9];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        const int lc = c[m] + 1;
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            const int g = GJd[i], cl = lc - CXd[i];
+                            f[m][i] = CYd[i] < 0 ? ra[L][pa][g][cl]
+                                                 : (CYd[i] == 0 ? rb[L][pb][g][cl] : rc[L][pc][g][cl]);
+                        }
+                        if (mb[k][m] & BB_BITS) {
+                            // this node's populations of the level below, by direction
+                            C own[9];
+                            own[0] = rb[L][pb][0][lc];
+                            own[1] = rb[L][pb][1][lc];
+                            own[3] = rb[L][pb][2][lc];
+                            own[2] = rc[L][oc][0][lc];
+                            own[5] = rc[L][oc][1][lc];
+                            own[6] = rc[L][oc][2][lc];
+                            own[4] = ra[L][oa][0][lc];
+                            own[7] = ra[L][oa][1][lc];
+                            own[8] = ra[L][oa][2][lc];
+#pragma unroll
+                            for (int i = 0; i < 9; ++i)
+                                f[m][i] = ((mb[k][m] >> (M_BB + i)) & 1u) ? own[OPPd[i]] : f[m][i];
+                        }
+                    }
+                    finish(f, mb[k], y);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // One step for every live node of every sample of every job in a table
 // (continuous batching). Jobs may differ in geometry, lattice, sample count
 // and step parity; all use the AA layout, one row per thread. Tiles of job q
@@ -1835,6 +2047,80 @@ int full_rows_max_nx(int prec, int n) {
     return best;
 }
 
+// bytes of one LDS value of the full-row kernels (the compute type)
+static constexpr int rows_lds_bytes(int prec) { return prec == UQ_FP64 ? 8 : 4; }
+
+// channel: (N - 1) 30 LDS rows of 64 K M + 2 values
+static constexpr int rows_ch_lds(int n, int K, int M, int prec) {
+    return (n - 1) * 30 * (64 * K * M + 2) * rows_lds_bytes(prec);
+}
+
+template <int P, int N>
+static constexpr bool rows_ch_fit(int K, int M) {
+    return N * K <= 16 && rows_ch_lds(N, K, M, P) <= 160 * 1024;
+}
+
+static int rows_ch_shape(int prec, int n, int nx, int *K, int *M) {
+    for (int m = 1; m <= 2; ++m) {
+        const int k = std::max(2, (nx + 64 * m - 1) / (64 * m));
+        if (k > 4) continue;
+        if (n * k <= 16 && rows_ch_lds(n, k, m, prec) <= 160 * 1024) {
+            *K = k;
+            *M = m;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+int channel_rows_max_nx(int prec, int n) {
+    int best = 0;
+    for (int nx = 64; nx <= 512; nx += 64) {
+        int K, M;
+        if (rows_ch_shape(prec, n, nx, &K, &M)) best = nx;
+    }
+    return best;
+}
+
+bool channel_fusable(const JobDev &j) {
+    const int64_t b = j.prec == UQ_FP64 ? 8 : (j.prec == UQ_FP32 ? 4 : 2);
+    return j.geom == 1 && j.layout == UQ_LAYOUT_AB && j.n_special == 0 && j.q == nullptr &&
+           j.xbc != UQ_XBC_INTERP && 9 * j.plane * b < ((int64_t)1 << 31) && j.plane * 4 < ((int64_t)1 << 31);
+}
+
+template <int P, int N, int K, int M>
+static void stepRC_k(const JobDev &j, const int64_t *d_t, int k, bool src2, int rows, hipStream_t s) {
+    const int H = std::max(8, std::min(rows, j.ny));
+    const int chunks = (j.ny + H - 1) / H;
+    const int64_t nwork = (int64_t)j.S * chunks;
+    const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
+    k_stepRC<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, d_t, k, src2, H, chunks, nwork);
+}
+
+template <int P, int N>
+static void stepRC_p(const JobDev &j, const int64_t *d_t, int k, bool src2, int rows, hipStream_t s) {
+    int K = 0, M = 0;
+    if (!rows_ch_shape(P, N, j.nx, &K, &M)) return;
+#define UQ_ROWS_CASE(kk, mm)                                                               \
+    if constexpr (rows_ch_fit<P, N>(kk, mm)) {                                             \
+        if (K == kk && M == mm) return stepRC_k<P, N, kk, mm>(j, d_t, k, src2, rows, s);   \
+    }
+    UQ_ROWS_CASE(2, 1)
+    UQ_ROWS_CASE(3, 1)
+    UQ_ROWS_CASE(4, 1)
+    UQ_ROWS_CASE(2, 2)
+    UQ_ROWS_CASE(3, 2)
+    UQ_ROWS_CASE(4, 2)
+#undef UQ_ROWS_CASE
+}
+
+template <int P>
+static void fused_ch_p(const JobDev &j, int n, const int64_t *d_t, int k, bool src2, int fty, hipStream_t s) {
+    if (n == 2) stepRC_p<P, 2>(j, d_t, k, src2, fty, s);
+    else if (n == 3) stepRC_p<P, 3>(j, d_t, k, src2, fty, s);
+    else stepRC_p<P, 4>(j, d_t, k, src2, fty, s);
+}
+
 template <int P>
 static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s) {
     if (window == 2) {
@@ -1854,7 +2140,19 @@ static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool
     }
 }
 
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s) {
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, const int64_t *d_t, int k,
+                        hipStream_t s) {
+    if (j.geom == 1) {
+        if (!channel_fusable(j) || window != 2 || n < 2 || n > 4 || j.nx > channel_rows_max_nx(j.prec, n))
+            return hipErrorInvalidValue;
+        switch (j.prec) {
+            case UQ_FP64: fused_ch_p<UQ_FP64>(j, n, d_t, k, src2, fty, s); break;
+            case UQ_FP32: fused_ch_p<UQ_FP32>(j, n, d_t, k, src2, fty, s); break;
+            case UQ_FP16S: fused_ch_p<UQ_FP16S>(j, n, d_t, k, src2, fty, s); break;
+            default: fused_ch_p<UQ_BF16S>(j, n, d_t, k, src2, fty, s); break;
+        }
+        return hipGetLastError();
+    }
     if (!fused_supported(j) || n < 2 || n > (window == 2 ? 6 : 4)) return hipErrorInvalidValue;
     if (window == 2 && j.nx > full_rows_max_nx(j.prec, n)) return hipErrorInvalidValue;
     switch (j.prec) {

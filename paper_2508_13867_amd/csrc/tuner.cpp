@@ -122,6 +122,30 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         s.bx = bx;
                         cands.push_back(s);
                     }
+        // channels with half-way and Zou-He / wall / periodic ends (AB): the
+        // full-row window, 2 to 4 steps per launch, the height cut into 1 to 8
+        // balanced chunks (a workgroup per chunk and sample: few samples
+        // need several chunks to fill the chip)
+        if (layout == UQ_LAYOUT_AB && p->geometry == UQ_GEOM_CHANNEL && p->cyl_bc == UQ_CYL_HALFWAY &&
+            p->xbc != UQ_XBC_INTERP) {
+            std::vector<int> heights;
+            for (int nch : {1, 2, 3, 4, 6, 8}) {
+                const int h = (p->ny + nch - 1) / nch;
+                if (h >= 8 && (heights.empty() || heights.back() != h)) heights.push_back(h);
+            }
+            for (int n : {2, 3, 4})
+                for (int fty : heights) {
+                    if (p->nx > channel_rows_max_nx(p->precision, n)) continue;
+                    StepShape s;
+                    s.layout = layout;
+                    s.pad = 64;
+                    s.nt = 0;
+                    s.fuse = n;
+                    s.fty = fty;
+                    s.fwin = 2;
+                    cands.push_back(s);
+                }
+        }
         // 2, 3 or 4 steps per launch (periodic lattices, AB): tiles of 64 x fty
         // nodes, and sliding windows down chunks of fty rows
         if (layout == UQ_LAYOUT_AB && p->geometry == UQ_GEOM_TGV) {

@@ -148,7 +148,15 @@ hipError_t launch_step(const JobDev &j, const int64_t *d_t, int k, int parity, c
 // slab (the host keeps the slab of each step's state; see Job::enqueue_steps)
 // (window 1: the sliding-window kernel with chunks of fty rows, its stores
 // non-temporal if nt; 2: the same over whole rows; 0: the 64 x fty tile kernel)
-hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, hipStream_t s);
+// (channel jobs: window 2 only, advancing the steps t = *d_t + k ..; see
+// channel_fusable)
+hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, bool nt, const int64_t *d_t, int k,
+                        hipStream_t s);
+// channel jobs the fused channel kernel takes: AB, half-way walls and
+// cylinder, Zou-He / wall / periodic ends (no interpolated rule)
+bool channel_fusable(const JobDev &j);
+// widest channel the fused channel kernel takes at this precision and N
+int channel_rows_max_nx(int prec, int n);
 // widest lattice the full-row kernel takes at this precision and N (0: none)
 int full_rows_max_nx(int prec, int n);
 bool fused_supported(const JobDev &j);

@@ -174,6 +174,88 @@ def test_channel_fp64_drag_lift_moments(layout):
         assert rel_l2(st["coeffs"], ref["stats"]["vel"]["coeffs"]) < TOL["fp64"]
 
 
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("rows", [8, 64])
+@pytest.mark.parametrize("steps", [2, 7, 201, 401])
+def test_fused_channel_populations_match_oracle(steps, rows, n, monkeypatch):
+    # the full-row window on the channel (half-way walls and cylinder, Zou-He
+    # ends, the inflow ramp ending at step 200): FP64 against the oracle,
+    # counts that leave single steps after the fused blocks, chunks of 8
+    # rows (halos next to the walls) and of the whole height
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(CHANNEL_SMALL, layout="ab")
+    say("case fused channel", n, "steps", steps, "rows", rows)
+    with Job(spec) as job:
+        assert job.info().fused == n and job.info().fused_window == 2
+        job.run(steps)
+        xi, _ = job.samples()
+        for s in (0, 3):
+            p = O.sample_params(CHANNEL_SMALL, xi[s])
+            ref = O.channel_run(100, 41, p["nu"], p["u_peak"], steps, D=10, cx=25, cy=18, ramp=200,
+                                want_f=True)["f"]
+            got = job.populations(s)
+            assert np.abs(got - ref).max() < 1e-13, (s, np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("xbc", ["walls", "periodic"])
+@pytest.mark.parametrize("n", [3, 4])
+def test_fused_channel_wall_and_periodic_ends(xbc, n, monkeypatch):
+    monkeypatch.setenv("UQ_FUSE", str(n))
+    monkeypatch.setenv("UQ_FUSE_TY", "16")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(CHANNEL_SMALL, layout="ab", xbc=xbc, ramp=0)
+    say("case fused channel", xbc, n)
+    with Job(spec) as job:
+        assert job.info().fused == n
+        job.run(37)
+        xi, _ = job.samples()
+        p = O.sample_params(spec, xi[1])
+        code = {"walls": 1, "periodic": 2}[xbc]
+        ref = O.channel_run(100, 41, p["nu"], p["u_peak"], 37, D=10, cx=25, cy=18, xbc=code, want_f=True)["f"]
+        got = job.populations(1)
+        # (a channel without inflow stays at rest: this checks that the end
+        # columns and walls bring in nothing from unwritten LDS)
+        assert np.all(np.isfinite(got)) and np.abs(got - ref).max() < 1e-13
+
+
+def test_fused_channel_refused_for_interpolated_rules(monkeypatch):
+    # Bouzidi links and finite-difference columns need the boundary-node
+    # kernels: such jobs are not fused, whatever the shape asks for
+    monkeypatch.setenv("UQ_FUSE", "3")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = dict(name="chan70x27_interp", geometry="channel", precision="fp64", nx=70, ny=27, steps=20,
+                u_peak=0.06, nu=0.04, cyl_bc="bouzidi", cyl_x=17.3, cyl_y=12.6, cyl_d=8.6, ramp=120,
+                xbc="interp", force_ref="mean", layout="ab", dists=[("re", 16.0, 24.0)],
+                rule=dict(kind="gl", n=2, order=1))
+    with Job(spec) as job:
+        assert job.info().fused == 0
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "1")
+    with Job(W.scaled(CHANNEL_SMALL, layout="ab")) as job:
+        assert job.info().fused == 0  # strips and tiles are periodic-only
+
+
+def test_fused_cylinder_config_fp32_sampled(monkeypatch):
+    # the 440 x 82 cylinder workload (64 samples), 3 steps per launch over
+    # whole rows (4 waves of two columns per lane per step), 600 steps; two
+    # samples re-solved by the oracle
+    monkeypatch.setenv("UQ_FUSE", "3")
+    monkeypatch.setenv("UQ_FUSE_TY", "256")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    monkeypatch.setenv("UQ_NT_STORE", "0")
+    spec = W.scaled(W.CYLINDER_FP32, steps=600, layout="ab")
+    say("case", spec["name"], "fused 3, 600 steps")
+    with Job(spec) as job:
+        assert job.info().fused == 3
+        job.run(spec["steps"])
+        cd = job.qoi_samples("cd")[:, 0]
+        vel = job.qoi_samples("vel")
+        ref = O.run_problem(spec, samples=[0, 63])
+        assert rel_l2(cd[[0, 63]], ref["samples"]["cd"]) < TOL["fp32"]
+        assert rel_l2(vel[[0, 63]], ref["samples"]["vel"].reshape(2, -1)) < TOL["fp32"]
+
+
 @pytest.mark.parametrize("layout", ["aa", "ab"])
 def test_cylinder_config_geometry_fp32_sampled(layout):
     # the 440 x 82 cylinder workload (64 samples) at reduced steps; two
