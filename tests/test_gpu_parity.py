@@ -220,6 +220,48 @@ def test_fused_channel_wall_and_periodic_ends(xbc, n, monkeypatch):
         assert np.all(np.isfinite(got)) and np.abs(got - ref).max() < 1e-13
 
 
+@pytest.mark.parametrize("nx, ny", [(5, 3), (64, 9), (129, 7)])
+def test_fused_channel_small_lattices(nx, ny, monkeypatch):
+    # three rows (every row touches a wall), a single wave of columns, and
+    # one column past two waves; no cylinder
+    monkeypatch.setenv("UQ_FUSE", "3")
+    monkeypatch.setenv("UQ_FUSE_TY", "8")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(CHANNEL_SMALL, nx=nx, ny=ny, D=0, layout="ab", ramp=10,
+                    dists=[("nu", 0.04, 0.06), ("u_peak", 0.045, 0.055)])
+    say("case fused channel", nx, ny)
+    with Job(spec) as job:
+        assert job.info().fused == 3
+        job.run(29)
+        xi, _ = job.samples()
+        p = O.sample_params(spec, xi[2])
+        ref = O.channel_run(nx, ny, p["nu"], p["u_peak"], 29, ramp=10, want_f=True)["f"]
+        assert np.abs(job.populations(2) - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+def test_fused_channel_matches_single_steps(prec, monkeypatch):
+    spec = W.scaled(CHANNEL_SMALL, precision=prec, layout="ab", steps=300)
+    say("case fused channel vs single", prec)
+    res = {}
+    for fuse in ("0", "3"):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        monkeypatch.setenv("UQ_FUSE_TY", "16")
+        monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+        with Job(spec) as job:
+            job.run(300)
+            res[fuse] = (job.populations(1), job.qoi_samples("cd")[:, 0])
+    # the same rules and arithmetic; the two kernels may contract FP32
+    # operations differently, and with 16-bit storage such a last-bit
+    # difference can flip a rounding to 16 bits: there the two agree to a few
+    # storage units in the last place (2^-10 relative for FP16, 2^-7 for
+    # bfloat16), populations and drag alike
+    ulp = {"fp32": 0.0, "fp16s": 2.0 ** -10, "bf16s": 2.0 ** -7}[prec]
+    fmax = np.abs(res["0"][0]).max()
+    assert np.abs(res["0"][0] - res["3"][0]).max() <= max(1e-6, 4 * ulp * fmax)
+    assert rel_l2(res["3"][1], res["0"][1]) <= max(1e-6, 4 * ulp)
+
+
 def test_fused_channel_refused_for_interpolated_rules(monkeypatch):
     # Bouzidi links and finite-difference columns need the boundary-node
     # kernels: such jobs are not fused, whatever the shape asks for
