@@ -2000,19 +2000,22 @@ static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
     k_stepR<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, src2, H, chunks, nwork, nt);
 }
 
-template <int P, int N>
-static constexpr bool rows_fit(int K, int M) {
-    return N * K <= 16 && (int64_t)(N - 1) * 27 * (64 * K * M + 2) * (P == UQ_FP64 ? 8 : 4) <= 160 * 1024;
+// Shapes of the full-row kernels: K waves per level of M columns per lane,
+// N K <= 16 waves, and (N - 1) LDS rings of ROWS direction-rows (27 on the
+// periodic lattice, 30 on the channel) of 64 K M + 2 compute values within
+// 160 KB. The shape used for a lattice nx wide: the fewest columns per lane
+// (M = 1, else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
+static constexpr int RING_ROWS_TGV = 27, RING_ROWS_CH = 30;
+
+static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
+    return n * K <= 16 && K <= 4 &&
+           (int64_t)(n - 1) * rows * (64 * K * M + 2) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
 }
 
-// the shape used for a lattice nx wide: the fewest columns per lane (M = 1,
-// else 2) whose K = ceil(nx / 64 M) fits; 0 if none
-static int rows_shape(int prec, int n, int nx, int *K, int *M) {
-    const int b = prec == UQ_FP64 ? 8 : 4;
+static int rows_shape(int prec, int n, int rows, int nx, int *K, int *M) {
     for (int m = 1; m <= 2; ++m) {
         const int k = std::max(2, (nx + 64 * m - 1) / (64 * m));
-        if (k > 4) continue;
-        if (n * k <= 16 && (int64_t)(n - 1) * 27 * (64 * k * m + 2) * b <= 160 * 1024) {
+        if (rows_fit(prec, n, rows, k, m)) {
             *K = k;
             *M = m;
             return 1;
@@ -2020,66 +2023,32 @@ static int rows_shape(int prec, int n, int nx, int *K, int *M) {
     }
     return 0;
 }
+
+static int rows_max_nx(int prec, int n, int rows) {
+    int best = 0;
+    for (int nx = 64; nx <= 512; nx += 64) {
+        int K, M;
+        if (rows_shape(prec, n, rows, nx, &K, &M)) best = nx;
+    }
+    return best;
+}
+
+int full_rows_max_nx(int prec, int n) { return rows_max_nx(prec, n, RING_ROWS_TGV); }
+int channel_rows_max_nx(int prec, int n) { return rows_max_nx(prec, n, RING_ROWS_CH); }
+
+// the instances (K, M) a launcher may take
+#define UQ_ROWS_CASES(CASE) CASE(2, 1) CASE(3, 1) CASE(4, 1) CASE(2, 2) CASE(3, 2) CASE(4, 2)
 
 template <int P, int N>
 static void stepR_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
     int K = 0, M = 0;
-    if (!rows_shape(P, N, j.nx, &K, &M)) return;
-#define UQ_ROWS_CASE(k, m)                                                        \
-    if constexpr (rows_fit<P, N>(k, m)) {                                         \
-        if (K == k && M == m) return stepR_k<P, N, k, m>(j, src2, rows, nt, s);   \
+    if (!rows_shape(P, N, RING_ROWS_TGV, j.nx, &K, &M)) return;
+#define UQ_ROWS_CASE(kk, mm)                                                      \
+    if constexpr (rows_fit(P, N, RING_ROWS_TGV, kk, mm)) {                        \
+        if (K == kk && M == mm) return stepR_k<P, N, kk, mm>(j, src2, rows, nt, s); \
     }
-    UQ_ROWS_CASE(2, 1)
-    UQ_ROWS_CASE(3, 1)
-    UQ_ROWS_CASE(4, 1)
-    UQ_ROWS_CASE(2, 2)
-    UQ_ROWS_CASE(3, 2)
-    UQ_ROWS_CASE(4, 2)
+    UQ_ROWS_CASES(UQ_ROWS_CASE)
 #undef UQ_ROWS_CASE
-}
-
-int full_rows_max_nx(int prec, int n) {
-    int best = 0;
-    for (int nx = 64; nx <= 512; nx += 64) {
-        int K, M;
-        if (rows_shape(prec, n, nx, &K, &M)) best = nx;
-    }
-    return best;
-}
-
-// bytes of one LDS value of the full-row kernels (the compute type)
-static constexpr int rows_lds_bytes(int prec) { return prec == UQ_FP64 ? 8 : 4; }
-
-// channel: (N - 1) 30 LDS rows of 64 K M + 2 values
-static constexpr int rows_ch_lds(int n, int K, int M, int prec) {
-    return (n - 1) * 30 * (64 * K * M + 2) * rows_lds_bytes(prec);
-}
-
-template <int P, int N>
-static constexpr bool rows_ch_fit(int K, int M) {
-    return N * K <= 16 && rows_ch_lds(N, K, M, P) <= 160 * 1024;
-}
-
-static int rows_ch_shape(int prec, int n, int nx, int *K, int *M) {
-    for (int m = 1; m <= 2; ++m) {
-        const int k = std::max(2, (nx + 64 * m - 1) / (64 * m));
-        if (k > 4) continue;
-        if (n * k <= 16 && rows_ch_lds(n, k, m, prec) <= 160 * 1024) {
-            *K = k;
-            *M = m;
-            return 1;
-        }
-    }
-    return 0;
-}
-
-int channel_rows_max_nx(int prec, int n) {
-    int best = 0;
-    for (int nx = 64; nx <= 512; nx += 64) {
-        int K, M;
-        if (rows_ch_shape(prec, n, nx, &K, &M)) best = nx;
-    }
-    return best;
 }
 
 bool channel_fusable(const JobDev &j) {
@@ -2100,19 +2069,15 @@ static void stepRC_k(const JobDev &j, const int64_t *d_t, int k, bool src2, int 
 template <int P, int N>
 static void stepRC_p(const JobDev &j, const int64_t *d_t, int k, bool src2, int rows, hipStream_t s) {
     int K = 0, M = 0;
-    if (!rows_ch_shape(P, N, j.nx, &K, &M)) return;
-#define UQ_ROWS_CASE(kk, mm)                                                               \
-    if constexpr (rows_ch_fit<P, N>(kk, mm)) {                                             \
-        if (K == kk && M == mm) return stepRC_k<P, N, kk, mm>(j, d_t, k, src2, rows, s);   \
+    if (!rows_shape(P, N, RING_ROWS_CH, j.nx, &K, &M)) return;
+#define UQ_ROWS_CASE(kk, mm)                                                              \
+    if constexpr (rows_fit(P, N, RING_ROWS_CH, kk, mm)) {                                 \
+        if (K == kk && M == mm) return stepRC_k<P, N, kk, mm>(j, d_t, k, src2, rows, s);  \
     }
-    UQ_ROWS_CASE(2, 1)
-    UQ_ROWS_CASE(3, 1)
-    UQ_ROWS_CASE(4, 1)
-    UQ_ROWS_CASE(2, 2)
-    UQ_ROWS_CASE(3, 2)
-    UQ_ROWS_CASE(4, 2)
+    UQ_ROWS_CASES(UQ_ROWS_CASE)
 #undef UQ_ROWS_CASE
 }
+#undef UQ_ROWS_CASES
 
 template <int P>
 static void fused_ch_p(const JobDev &j, int n, const int64_t *d_t, int k, bool src2, int fty, hipStream_t s) {
