@@ -134,17 +134,6 @@ struct Third<double> {
 };
 __device__ inline float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
-template <typename C>
-__device__ inline C third(C x) {
-    return fma_c(x, Third<C>::hi, x * Third<C>::lo);
-}
-// x / 12 = third(x) / 4 with the quarter folded into the (exactly scaled)
-// constants: the same value, one multiplication fewer
-template <typename C>
-__device__ inline C twelfth(C x) {
-    return fma_c(x, Third<C>::hi * C(0.25), x * (Third<C>::lo * C(0.25)));
-}
-
 // 1/x from the hardware reciprocal estimate refined by Newton steps (one in
 // single, two in double precision): within an ulp of the quotient, a third of
 // the instructions of the IEEE division sequence
@@ -165,33 +154,41 @@ __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
     const C ir = recip(C(1) + drho);
     const C ux = jx * ir, uy = jy * ir;
-    const C base = -C(1.5) * (jx * ux + jy * uy);
-    const C w0 = C(4) / C(9), w1 = C(1) / C(9), w2 = C(1) / C(36);
+    const C db = fma_c(C(-1.5), fma_c(jy, uy, jx * ux), drho);
+    // omega folded into the constants (per sample: the compiler hoists them
+    // out of the node loops): omega w_i, and omega / 3 as an unevaluated sum
+    // hi + lo (exact product of omega with the split of 1/3, rounded once to
+    // the pair), so that the first-order term omega (c_i . j) / 3 is still
+    // formed with a single rounding. Every multiply-add is an explicit fma:
+    // the compiler's contraction choices, which may differ between the
+    // kernels that inline this, never change a result.
+    const C ow0 = omega * (C(4) / C(9)), ow1 = omega * (C(1) / C(9)), ow2 = omega * (C(1) / C(36));
+    const C o3h = omega * Third<C>::hi;
+    const C o3l = fma_c(omega, Third<C>::lo, fma_c(omega, Third<C>::hi, -o3h));
+    const C o12h = o3h * C(0.25), o12l = o3l * C(0.25);
     const C om1 = C(1) - omega;
-    f[0] = om1 * f[0] + omega * (w0 * (drho + base));
+    f[0] = fma_c(om1, f[0], ow0 * db);
     {
-        const C cj = jx, cu = ux;
-        const C q = w1 * (drho + base + C(4.5) * cj * cu), l = third(cj);
-        f[1] = om1 * f[1] + omega * (q + l);
-        f[3] = om1 * f[3] + omega * (q - l);
+        const C q = fma_c(C(4.5) * jx, ux, db), l = fma_c(jx, o3h, jx * o3l);
+        f[1] = fma_c(om1, f[1], fma_c(q, ow1, l));
+        f[3] = fma_c(om1, f[3], fma_c(q, ow1, -l));
     }
     {
-        const C cj = jy, cu = uy;
-        const C q = w1 * (drho + base + C(4.5) * cj * cu), l = third(cj);
-        f[2] = om1 * f[2] + omega * (q + l);
-        f[4] = om1 * f[4] + omega * (q - l);
+        const C q = fma_c(C(4.5) * jy, uy, db), l = fma_c(jy, o3h, jy * o3l);
+        f[2] = fma_c(om1, f[2], fma_c(q, ow1, l));
+        f[4] = fma_c(om1, f[4], fma_c(q, ow1, -l));
     }
     {
         const C cj = jx + jy, cu = ux + uy;
-        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = twelfth(cj);
-        f[5] = om1 * f[5] + omega * (q + l);
-        f[7] = om1 * f[7] + omega * (q - l);
+        const C q = fma_c(C(4.5) * cj, cu, db), l = fma_c(cj, o12h, cj * o12l);
+        f[5] = fma_c(om1, f[5], fma_c(q, ow2, l));
+        f[7] = fma_c(om1, f[7], fma_c(q, ow2, -l));
     }
     {
         const C cj = jy - jx, cu = uy - ux;
-        const C q = w2 * (drho + base + C(4.5) * cj * cu), l = twelfth(cj);
-        f[6] = om1 * f[6] + omega * (q + l);
-        f[8] = om1 * f[8] + omega * (q - l);
+        const C q = fma_c(C(4.5) * cj, cu, db), l = fma_c(cj, o12h, cj * o12l);
+        f[6] = fma_c(om1, f[6], fma_c(q, ow2, l));
+        f[8] = fma_c(om1, f[8], fma_c(q, ow2, -l));
     }
     drho_o = drho;
     ux_o = ux;
@@ -229,20 +226,22 @@ __device__ inline double inflow_u(int ny, double ramp, int y, int64_t t, double 
 // Zou-He (1997) completion of the unknown populations on the open columns,
 // written for shifted populations (the weights cancel in every relation):
 // the inlet with the imposed velocity u, the outlet at rho = 1.
+// (explicit fmas, as in the collision: the same result in every kernel)
 template <typename C>
 __device__ inline void zou_he_u(C f[9], bool inlet, C u) {
+    const C h = C(0.5) * (f[2] - f[4]);
     if (inlet) {
-        const C S = (f[0] + f[2] + f[4]) + C(2) * (f[3] + f[6] + f[7]);
+        const C S = fma_c(C(2), (f[3] + f[6]) + f[7], (f[0] + f[2]) + f[4]);
         const C drho = (S + u) / (C(1) - u);
         const C ru = (C(1) + drho) * u;
-        f[1] = f[3] + (C(2) / C(3)) * ru;
-        f[5] = f[7] - C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
-        f[8] = f[6] + C(0.5) * (f[2] - f[4]) + (C(1) / C(6)) * ru;
+        f[1] = fma_c(C(2) / C(3), ru, f[3]);
+        f[5] = fma_c(C(1) / C(6), ru, f[7] - h);
+        f[8] = fma_c(C(1) / C(6), ru, f[6] + h);
     } else {
-        const C v = (f[0] + f[2] + f[4]) + C(2) * (f[1] + f[5] + f[8]);
-        f[3] = f[1] - (C(2) / C(3)) * v;
-        f[7] = f[5] + C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * v;
-        f[6] = f[8] - C(0.5) * (f[2] - f[4]) - (C(1) / C(6)) * v;
+        const C v = fma_c(C(2), (f[1] + f[5]) + f[8], (f[0] + f[2]) + f[4]);
+        f[3] = fma_c(-(C(2) / C(3)), v, f[1]);
+        f[7] = fma_c(-(C(1) / C(6)), v, f[5] + h);
+        f[6] = fma_c(-(C(1) / C(6)), v, f[8] - h);
     }
 }
 
