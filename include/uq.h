@@ -357,7 +357,10 @@ const char *uq_last_error(void);
  * per step, down strips of at most 64 - 2(N - 1) columns or down whole rows
  * of up to 256 columns (K waves per step, one or two columns per lane,
  * N K <= 16, 3 to 6 steps; FP64 at N = 4 up to 192), in chunks of 64 or
- * 256 rows, FP64 32 or 64) --
+ * 256 rows, FP64 32 or 64), and for channels in AB with half-way walls and
+ * cylinder and Zou-He, wall or periodic ends the fused kernel over whole rows
+ * (2 to 4 steps per launch where the LDS rows fit: FP32 N = 3 at 440
+ * columns; the height cut into 1 to 8 balanced chunks) --
  * over `steps` steps each (rounded down to a multiple of 120, at least 120), on
  * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
