@@ -667,6 +667,25 @@ def test_fused_graph_replay_equals_eager(monkeypatch):
     assert np.array_equal(fa, fb)
 
 
+@pytest.mark.parametrize("nx, ny, steps, fused", [(4096, 4096, 9, True), (8192, 7300, 3, False)])
+def test_fused_kernels_at_the_buffer_range_limit(nx, ny, steps, fused, monkeypatch):
+    # one FP32 sample: 4096^2 (604 MB per slab) runs the window kernel;
+    # 8192 x 7300 (2.15 GB per slab, beyond the 2^31-byte range of a buffer
+    # descriptor) falls back to single steps; both against the oracle
+    monkeypatch.setenv("UQ_FUSE", "4")
+    monkeypatch.setenv("UQ_FUSE_TY", "64")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "1")
+    spec = dict(name=f"tgv{nx}x{ny}_single", geometry="tgv", precision="fp32", nx=nx, ny=ny, steps=steps, u0=0.03,
+                nu=0.02, dists=[("nu", 0.015, 0.025)], rule=dict(kind="gl", n=1, order=0), layout="ab")
+    say("case buffer range", nx, ny)
+    with Job(spec) as job:
+        assert (job.info().fused == 4) == fused
+        job.run(spec["steps"])
+        ke = job.qoi_samples("ke")[:, 0]
+        ref = O.run_problem(spec, qois=["ke"])
+        assert rel_l2(ke, ref["samples"]["ke"]) < TOL["fp32"]
+
+
 @pytest.mark.parametrize("layout, fuse", [("aa", "0"), ("ab", "0"), ("ab", "4")])
 def test_more_samples_than_a_grid_dimension(layout, fuse, monkeypatch):
     # 70,000 samples (> 65,535, the largest grid y extent) on an 8 x 8 lattice:
