@@ -262,6 +262,29 @@ def test_fused_channel_matches_single_steps(prec, monkeypatch):
     assert rel_l2(res["3"][1], res["0"][1]) <= max(1e-6, 4 * ulp)
 
 
+def test_autotune_channel_includes_fused_candidates(tmp_path, monkeypatch):
+    # 100 x 41 channel, FP64, layout left to the tuner: 8 AA and 16 AB
+    # single-step shapes (64- and 128-wide workgroups), plus the fused channel
+    # kernel at 2, 3 and 4 steps on 1, 2, 3 and 4 row chunks (41, 21, 14, 11
+    # rows); the job then runs in the chosen shape and matches the oracle
+    monkeypatch.setenv("UQ_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    for k in ("UQ_FUSE", "UQ_FUSE_TY", "UQ_FUSE_WINDOW", "UQ_NT_STORE", "UQ_LAYOUT"):
+        monkeypatch.delenv(k, raising=False)
+    spec = W.scaled(CHANNEL_SMALL, name="chan100x41_tuned", steps=121)
+    say("case channel autotune")
+    r = A.autotune(spec, steps=120)
+    assert r["n_candidates"] == 36
+    with Job(spec) as job:
+        inf = job.info()
+        assert (inf.fused, inf.fused_window, inf.fused_rows) == (r["fused"], r["fused_window"], r["fused_rows"])
+        job.run(spec["steps"])
+        xi, _ = job.samples()
+        p = O.sample_params(spec, xi[2])
+        ref = O.channel_run(100, 41, p["nu"], p["u_peak"], spec["steps"], D=10, cx=25, cy=18, ramp=200,
+                            want_f=True)["f"]
+        assert np.abs(job.populations(2) - ref).max() < 1e-13
+
+
 def test_fused_channel_refused_for_interpolated_rules(monkeypatch):
     # Bouzidi links and finite-difference columns need the boundary-node
     # kernels: such jobs are not fused, whatever the shape asks for
