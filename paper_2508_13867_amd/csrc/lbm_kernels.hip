@@ -77,21 +77,13 @@ struct Prec<UQ_BF16S> {
     __device__ static inline C ld(const T *p, float inv) {
         return __uint_as_float((uint32_t)(*p) << 16) * inv;
     }
-    // round to nearest, ties to even, on the upper 16 bits
-    __device__ static inline uint16_t rne(float v) {
-        uint32_t u = __float_as_uint(v);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-    }
+    // round to nearest, ties to even (the conversion instruction of gfx950)
+    __device__ static inline uint16_t rne(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     __device__ static inline void st(T *p, C v, float sc) { *p = rne(v * sc); }
     __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store(rne(v * sc), p); }
     // bfloat16 has float's exponent range, so scaling by the power of two sc
     // and back commutes with the rounding: round in place
-    __device__ static inline C rt(C v, float, float) {
-        uint32_t u = __float_as_uint(v);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return __uint_as_float(u & 0xFFFF0000u);
-    }
+    __device__ static inline C rt(C v, float, float) { return (float)(__bf16)v; }
 };
 
 // ------------------------------------------------------------------ lattice
