@@ -34,6 +34,14 @@
 
 #include "uq_internal.h"
 
+// Every fused multiply-add in these kernels is written out (fma_c). Implicit
+// contraction is off so that the compiler cannot fuse the last fma of the
+// collision with the conversion to a 16-bit storage format (one rounding
+// where the storage model has two), which it would do in some kernels and
+// not in others: with it off, every kernel rounds the same operations the
+// same way and their results agree bit for bit in every format.
+#pragma clang fp contract(off)
+
 namespace uqi {
 
 // ------------------------------------------------------------------ storage types

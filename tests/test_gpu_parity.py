@@ -239,7 +239,7 @@ def test_fused_channel_small_lattices(nx, ny, monkeypatch):
         assert np.abs(job.populations(2) - ref).max() < 1e-13
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s", "bf16s"])
 def test_fused_channel_matches_single_steps(prec, monkeypatch):
     spec = W.scaled(CHANNEL_SMALL, precision=prec, layout="ab", steps=300)
     say("case fused channel vs single", prec)
@@ -251,15 +251,11 @@ def test_fused_channel_matches_single_steps(prec, monkeypatch):
         with Job(spec) as job:
             job.run(300)
             res[fuse] = (job.populations(1), job.qoi_samples("cd")[:, 0])
-    # the same rules and arithmetic; the two kernels may contract FP32
-    # operations differently, and with 16-bit storage such a last-bit
-    # difference can flip a rounding to 16 bits: there the two agree to a few
-    # storage units in the last place (2^-10 relative for FP16, 2^-7 for
-    # bfloat16), populations and drag alike
-    ulp = {"fp32": 0.0, "fp16s": 2.0 ** -10, "bf16s": 2.0 ** -7}[prec]
-    fmax = np.abs(res["0"][0]).max()
-    assert np.abs(res["0"][0] - res["3"][0]).max() <= max(1e-6, 4 * ulp * fmax)
-    assert rel_l2(res["3"][1], res["0"][1]) <= max(1e-6, 4 * ulp)
+    # the same rules and the same operations in the same order, every fma
+    # explicit and no implicit contraction: bit for bit the same populations
+    # and drag, also where storage rounds to 16 bits
+    assert np.array_equal(res["0"][0], res["3"][0])
+    assert np.array_equal(res["0"][1], res["3"][1])
 
 
 def test_autotune_channel_includes_fused_candidates(tmp_path, monkeypatch):
@@ -602,14 +598,13 @@ def test_full_row_kernel_five_and_six_steps_full_size(prec, n, monkeypatch):
             assert job.info().fused == (n if fuse != "0" else 0)
             job.run(60)
             res[fuse] = (job.populations(200), job.qoi_samples("ke")[:, 0])
-    tol = 1e-6 if prec == "fp32" else 1e-4
-    assert np.abs(res["0"][0] - res[str(n)][0]).max() < tol
-    assert rel_l2(res[str(n)][1], res["0"][1]) < tol
+    assert np.array_equal(res["0"][0], res[str(n)][0])
+    assert np.array_equal(res["0"][1], res[str(n)][1])
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
 @pytest.mark.parametrize("window", [0, 1, 2])
-@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s", "bf16s"])
 def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     spec = W.scaled(TGV_4D_SMALL, precision=prec, layout="ab", steps=200)
     monkeypatch.setenv("UQ_FUSE_WINDOW", str(window))
@@ -620,11 +615,10 @@ def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
         with Job(spec) as job:
             job.run(200)
             res[fuse] = (job.populations(7), job.qoi_samples("ke")[:, 0])
-    # the same per-node arithmetic and storage rounding; only the compiler's
-    # contraction choices may differ between the kernels
-    tol = 1e-6 if prec == "fp32" else 1e-4
-    assert np.abs(res["0"][0] - res[str(n)][0]).max() < tol
-    assert rel_l2(res[str(n)][1], res["0"][1]) < tol
+    # the same per-node operations in the same order and the same storage
+    # rounding: bit for bit the same populations and kinetic energy
+    assert np.array_equal(res["0"][0], res[str(n)][0])
+    assert np.array_equal(res["0"][1], res[str(n)][1])
 
 
 @pytest.mark.parametrize("n, window, rows, nt", [(2, 0, 8, 1), (3, 0, 8, 1), (4, 1, 64, 0), (4, 2, 256, 0),
