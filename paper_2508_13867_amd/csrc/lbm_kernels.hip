@@ -1101,16 +1101,17 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lvl = wave / K + 1;  // 1..N
+    // Lanes past the lattice take the last column: they read what its own
+    // lane reads, compute the same values and write them to the same places
+    // (the same bits), so no lane needs a guard and the compiler keeps the
+    // collisions and the LDS reads that feed them unconditional.
     int c[M], vo0[M], vom[M], vop[M];
-    bool on[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        c[m] = ((wave - (lvl - 1) * K) * M + m) * 64 + lane;
-        on[m] = c[m] < nx;
-        const int cc = on[m] ? c[m] : nx - 1;  // idle lanes load a valid column
-        vo0[m] = cc * (int)sizeof(T);
-        vom[m] = (cc == 0 ? nx - 1 : cc - 1) * (int)sizeof(T);
-        vop[m] = (cc == nx - 1 ? 0 : cc + 1) * (int)sizeof(T);
+        c[m] = min(((wave - (lvl - 1) * K) * M + m) * 64 + lane, nx - 1);
+        vo0[m] = c[m] * (int)sizeof(T);
+        vom[m] = (c[m] == 0 ? nx - 1 : c[m] - 1) * (int)sizeof(T);
+        vop[m] = (c[m] == nx - 1 ? 0 : c[m] + 1) * (int)sizeof(T);
     }
     const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
     const int64_t G = gridDim.x;
@@ -1150,9 +1151,8 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 else rc[L][sc3][g][col] = v[i];
             }
         };
-        // collide the lane's M nodes of row y together (independent work for
-        // the scheduler to interleave; lanes past the lattice compute on
-        // valid but unused data) and hand each on to the next level
+        // collide the lane's M nodes of row y and hand each on to the next
+        // level
         auto finish = [&](C (*f)[9], int y) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -1161,7 +1161,6 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
             }
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (!on[m]) continue;
                 if (lvl < N) {
                     C v[9];
 #pragma unroll
@@ -1181,20 +1180,18 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
             }
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
+        const int n_it = (ye - yb) + 3 * RG;
+        // Both loops below pass n_it barriers, one per row step.
         if (lvl == 1) {
 #pragma unroll
             for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
-        }
-        const int n_it = (ye - yb) + 3 * RG;
-        for (int it0 = 0; it0 < n_it; it0 += B) {
+            for (int it0 = 0; it0 < n_it; it0 += B) {
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                const int it = it0 + k;
-                if (it >= n_it) break;
-                const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
-                const bool row_on = y >= yb - span && y < ye + span;
-                if (lvl == 1) {
-                    if (row_on) {
+                for (int k = 0; k < B; ++k) {
+                    const int it = it0 + k;
+                    if (it >= n_it) break;
+                    const int y = yb - RG + it;
+                    if (y < ye + span) {
                         pull(buf[(k + D) % B], min(y + D, y1_end - 1));
                         C f[M][9];
 #pragma unroll
@@ -1203,23 +1200,61 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                             for (int i = 0; i < 9; ++i) f[m][i] = BufLd<P>::cvt(buf[k][m][i], inv);
                         finish(f, y);
                     }
-                } else if (row_on) {
-                    const int L = lvl - 2;
-                    const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
-                    C f[M][9];
-#pragma unroll
-                    for (int m = 0; m < M; ++m) {
-                        const int lc = c[m] + 1;  // <= 64 K M - 1 + 1: inside the row even past the lattice
-#pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            const int g = GJd[i], cl = lc - CXd[i];
-                            f[m][i] = CYd[i] < 0 ? ra[L][sa][g][cl]
-                                                 : (CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl]);
-                        }
-                    }
-                    finish(f, y);
+                    __syncthreads();
                 }
-                __syncthreads();
+            }
+        } else {
+            // Levels above the first read the level below from the LDS rows.
+            // The c_y = 0 and c_y = +1 pulls of the next row (rows y + 1 and
+            // y of the level below) are complete before this row step begins
+            // and their slots are not rewritten in it, so they are read one
+            // step ahead into registers (two sets, alternating), and only the
+            // c_y = -1 pulls (row y + 1, written in the previous step) wait
+            // at the start of the step.
+            const int L = lvl - 2;
+            C pre[2][M][6];
+            auto ahead = [&](C (*q)[6], int y) {  // c_y >= 0 pulls of row y
+                const int sb = (y + 12) % 3, sc3 = (y + 11) & 3;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    int n = 0;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        if (CYd[i] < 0) continue;
+                        const int g = GJd[i], cl = c[m] + 1 - CXd[i];
+                        q[m][n++] = CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl];
+                    }
+                }
+            };
+            const int y_lo = yb - span, y_hi = ye + span;  // this level's rows
+            for (int it0 = 0; it0 < n_it; it0 += 2) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int it = it0 + k;
+                    if (it >= n_it) break;
+                    const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
+                    if (y >= y_lo && y < y_hi) {
+                        if (y == y_lo) ahead(pre[k], y);  // nothing read ahead yet
+                        const int sa = (y + 13) & 1;
+                        C f[M][9];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            int n = 0;
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) {
+                                if (CYd[i] < 0)
+                                    f[m][i] = ra[L][sa][GJd[i]][c[m] + 1 - CXd[i]];
+                                else
+                                    f[m][i] = pre[k][m][n++];
+                            }
+                        }
+                        // after this row's own reads; past the last row the
+                        // values are read but not used
+                        ahead(pre[k ^ 1], y + 1);
+                        finish(f, y);
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
