@@ -46,7 +46,7 @@ typedef enum {
     UQ_FP64 = 0,  /* double storage, double compute                        */
     UQ_FP32 = 1,  /* float storage, float compute                          */
     UQ_FP16S = 2, /* IEEE half storage scaled by 2^s per job, float compute */
-    UQ_BF16S = 3  /* bfloat16 storage scaled by 2^s per job, float compute  */
+    UQ_BF16S = 3  /* bfloat16 storage (unscaled), float compute           */
 } uq_precision;
 
 /* Memory layout of the populations (an execution choice; results agree to
@@ -278,7 +278,7 @@ typedef struct {
     int64_t steps_done; /* LBM steps taken so far                      */
     int64_t pitch;      /* row pitch of a population plane (elements)  */
     int64_t device_bytes; /* device memory held by the job            */
-    int32_t scale_exp;  /* FP16S/BF16S storage scale 2^scale_exp       */
+    int32_t scale_exp;  /* FP16S storage scale 2^scale_exp (else 0)    */
     int32_t fluid_nodes;
     int32_t layout;     /* uq_layout in use (AA or AB)                 */
     int32_t cpt;        /* rows per thread of the step kernel          */

@@ -72,26 +72,34 @@ struct Prec<UQ_FP16S> {
     using T = _Float16;
     using C = float;
     // stored value = f~ * 2^s (power-of-two scale, exact); rounding to half is
-    // round-to-nearest-even (v_cvt_f16_f32 in the default mode)
-    __device__ static inline C ld(const T *p, float inv) { return (float)(*p) * inv; }
+    // round-to-nearest-even (v_cvt_f16_f32 in the default mode). Back to
+    // float as h * 2^-s + 0: one mixed-precision fma (v_fma_mix_f32) where a
+    // product would take a conversion and a multiply; the same value, except
+    // that -0 comes back as +0.
+    __device__ static inline C up(_Float16 h, float inv) { return __builtin_fmaf((float)h, inv, 0.0f); }
+    __device__ static inline C ld(const T *p, float inv) { return up(*p, inv); }
     __device__ static inline void st(T *p, C v, float sc) { *p = (_Float16)(v * sc); }
     __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store((_Float16)(v * sc), p); }
-    __device__ static inline C rt(C v, float sc, float inv) { return (float)(_Float16)(v * sc) * inv; }
+    __device__ static inline C rt(C v, float sc, float inv) { return up((_Float16)(v * sc), inv); }
 };
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 template <>
 struct Prec<UQ_BF16S> {
+    // bfloat16 has float's exponent range: stored unscaled (the job's scale
+    // exponent is 0 and sc, inv are not used)
     using T = uint16_t;
     using C = float;
-    __device__ static inline C ld(const T *p, float inv) {
-        return __uint_as_float((uint32_t)(*p) << 16) * inv;
-    }
+    __device__ static inline C ld(const T *p, float) { return __uint_as_float((uint32_t)(*p) << 16); }
     // round to nearest, ties to even (the conversion instruction of gfx950)
     __device__ static inline uint16_t rne(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-    __device__ static inline void st(T *p, C v, float sc) { *p = rne(v * sc); }
-    __device__ static inline void st_nt(T *p, C v, float sc) { __builtin_nontemporal_store(rne(v * sc), p); }
-    // bfloat16 has float's exponent range, so scaling by the power of two sc
-    // and back commutes with the rounding: round in place
-    __device__ static inline C rt(C v, float, float) { return (float)(__bf16)v; }
+    __device__ static inline void st(T *p, C v, float) { *p = rne(v); }
+    __device__ static inline void st_nt(T *p, C v, float) { __builtin_nontemporal_store(rne(v), p); }
+    // the rounded value in the upper half of a word whose lower half is +0:
+    // that word is the float itself, from one conversion instruction
+    __device__ static inline C rt(C v, float, float) {
+        return __builtin_bit_cast(float, __builtin_convertvector((f32x2_t){0.0f, v}, bf16x2_t));
+    }
 };
 
 // ------------------------------------------------------------------ lattice
@@ -147,21 +155,31 @@ __device__ inline double recip(double x) {
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
+// 1/(1 + drho) inside the collision. The velocity it gives enters only the
+// second-order terms of the equilibrium (the first-order term uses j), so
+// in single precision the hardware estimate (within an ulp) is used as it
+// is; double precision refines it to full accuracy.
+__device__ inline float coll_recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double coll_recip(double x) { return recip(x); }
+
 template <typename C>
 __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     const C drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
-    const C jx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
-    const C jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
-    const C ir = recip(C(1) + drho);
+    const C d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const C jx = ((f[1] - f[3]) + d57) + d86;
+    const C jy = ((f[2] - f[4]) + d57) - d86;
+    const C ir = coll_recip(C(1) + drho);
     const C ux = jx * ir, uy = jy * ir;
-    const C db = fma_c(C(-1.5), fma_c(jy, uy, jx * ux), drho);
+    // second-order terms from the products j_x u_x, j_y u_y and j_x u_y
+    // (= j_y u_x): (c.j)(c.u) is j_x u_x or j_y u_y on the axes and
+    // j_x u_x + j_y u_y +- 2 j_x u_y on the diagonals
+    const C px = jx * ux, py = jy * uy, pp = px + py;
+    const C db = fma_c(C(-1.5), pp, drho);
     // omega folded into the constants (per sample: the compiler hoists them
     // out of the node loops): omega w_i, and omega / 3 as an unevaluated sum
     // hi + lo (exact product of omega with the split of 1/3, rounded once to
     // the pair), so that the first-order term omega (c_i . j) / 3 is still
-    // formed with a single rounding. Every multiply-add is an explicit fma:
-    // the compiler's contraction choices, which may differ between the
-    // kernels that inline this, never change a result.
+    // formed with a single rounding. Every multiply-add is an explicit fma.
     const C ow0 = omega * (C(4) / C(9)), ow1 = omega * (C(1) / C(9)), ow2 = omega * (C(1) / C(36));
     const C o3h = omega * Third<C>::hi;
     const C o3l = fma_c(omega, Third<C>::lo, fma_c(omega, Third<C>::hi, -o3h));
@@ -169,24 +187,25 @@ __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     const C om1 = C(1) - omega;
     f[0] = fma_c(om1, f[0], ow0 * db);
     {
-        const C q = fma_c(C(4.5) * jx, ux, db), l = fma_c(jx, o3h, jx * o3l);
+        const C q = fma_c(C(4.5), px, db), l = fma_c(jx, o3h, jx * o3l);
         f[1] = fma_c(om1, f[1], fma_c(q, ow1, l));
         f[3] = fma_c(om1, f[3], fma_c(q, ow1, -l));
     }
     {
-        const C q = fma_c(C(4.5) * jy, uy, db), l = fma_c(jy, o3h, jy * o3l);
+        const C q = fma_c(C(4.5), py, db), l = fma_c(jy, o3h, jy * o3l);
         f[2] = fma_c(om1, f[2], fma_c(q, ow1, l));
         f[4] = fma_c(om1, f[4], fma_c(q, ow1, -l));
     }
+    const C t = fma_c(C(4.5), pp, db), jx9 = C(9) * jx;
     {
-        const C cj = jx + jy, cu = ux + uy;
-        const C q = fma_c(C(4.5) * cj, cu, db), l = fma_c(cj, o12h, cj * o12l);
+        const C cj = jx + jy;
+        const C q = fma_c(jx9, uy, t), l = fma_c(cj, o12h, cj * o12l);
         f[5] = fma_c(om1, f[5], fma_c(q, ow2, l));
         f[7] = fma_c(om1, f[7], fma_c(q, ow2, -l));
     }
     {
-        const C cj = jy - jx, cu = uy - ux;
-        const C q = fma_c(C(4.5) * cj, cu, db), l = fma_c(cj, o12h, cj * o12l);
+        const C cj = jy - jx;
+        const C q = fma_c(-jx9, uy, t), l = fma_c(cj, o12h, cj * o12l);
         f[6] = fma_c(om1, f[6], fma_c(q, ow2, l));
         f[8] = fma_c(om1, f[8], fma_c(q, ow2, -l));
     }
@@ -726,7 +745,7 @@ struct BufLd<UQ_FP16S> {
     __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
     }
-    __device__ static inline float cvt(R v, float inv) { return (float)__builtin_bit_cast(_Float16, v) * inv; }
+    __device__ static inline float cvt(R v, float inv) { return Prec<UQ_FP16S>::up(__builtin_bit_cast(_Float16, v), inv); }
     __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
         return cvt(raw(r, voff, soff), inv);
     }
@@ -737,7 +756,7 @@ struct BufLd<UQ_BF16S> {
     __device__ static inline R raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
     }
-    __device__ static inline float cvt(R v, float inv) { return __uint_as_float((uint32_t)v << 16) * inv; }
+    __device__ static inline float cvt(R v, float) { return __uint_as_float((uint32_t)v << 16); }
     __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff, float inv) {
         return cvt(raw(r, voff, soff), inv);
     }
@@ -767,8 +786,8 @@ struct BufSt<UQ_FP16S> {
 };
 template <>
 struct BufSt<UQ_BF16S> {
-    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff, float sc) {
-        __builtin_amdgcn_raw_buffer_store_b16(Prec<UQ_BF16S>::rne(v * sc), r, voff, soff, 0);
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, float v, int voff, int soff, float) {
+        __builtin_amdgcn_raw_buffer_store_b16(Prec<UQ_BF16S>::rne(v), r, voff, soff, 0);
     }
 };
 

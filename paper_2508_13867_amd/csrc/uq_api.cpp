@@ -224,10 +224,11 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
         const double uc = P.geometry == UQ_GEOM_TGV ? std::fabs(in.u0) : 1.5 * std::fabs(in.u_peak);
         umax = std::max(umax, uc);
     }
-    // storage scale 2^s for 16-bit formats: the largest shifted population is
-    // about u/3, so 2^12 / (u/2) keeps stored magnitudes near 2^11
+    // storage scale 2^s for FP16 (bfloat16 has float's exponent range and is
+    // stored unscaled): the largest shifted population is about u/3, so
+    // 2^12 / (u/2) keeps stored magnitudes near 2^11
     j->scale_exp = 0;
-    if (P.precision == UQ_FP16S || P.precision == UQ_BF16S) {
+    if (P.precision == UQ_FP16S) {
         const double B = 0.5 * umax + 1e-4;
         j->scale_exp = (int)std::floor(std::log2(4096.0 / B));
         j->scale_exp = std::max(0, std::min(j->scale_exp, 24));
