@@ -286,7 +286,7 @@ typedef struct {
     int32_t plane_pad;  /* padding elements after each population plane */
     int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
     int32_t fused;      /* steps per launch of the fused periodic AB
-                           kernel (2..4; up to 6 over whole rows), 0
+                           kernel (2..4; up to 8 over whole rows), 0
                            if not fused                                */
     int32_t fused_rows; /* its tile height (rows of 64 nodes), or the
                            window kernel's chunk height               */
@@ -356,12 +356,13 @@ const char *uq_last_error(void);
  * extra step, rows 8 or 16, FP64 4 or 8; or as a sliding window, one wave
  * per step, down strips of at most 64 - 2(N - 1) columns or down whole rows
  * of up to 256 columns (K waves per step, one or two columns per lane,
- * N K <= 16, 3 to 6 steps; FP64 at N = 4 up to 192), in chunks of 64 or
+ * N K <= 16, 3 to 8 steps where (N - 1) 21 rows fit in the LDS), in chunks of 64 or
  * 256 rows, FP64 32 or 64), and for channels in AB with half-way walls and
  * cylinder and Zou-He, wall or periodic ends the fused kernel over whole rows
  * (2 to 4 steps per launch where the LDS rows fit: FP32 N = 3 at 440
  * columns; the height cut into 1 to 8 balanced chunks) --
- * over `steps` steps each (rounded down to a multiple of 120, at least 120), on
+ * over `steps` steps each (at least 120; rounded down to whole launches of a
+ * fused kernel: N steps, 2N for even N), on
  * dev's device with temporary jobs. The fastest becomes the shape of every later job of the
  * same class (precision, geometry, nx, ny, S, layout field) in this process,
  * and is appended to the file named by UQ_TUNE_CACHE if set. Candidates that

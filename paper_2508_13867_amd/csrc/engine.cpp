@@ -81,7 +81,7 @@ int Job::fused_n() const {
                 jd.nx <= channel_rows_max_nx(jd.prec, shape.fuse))
                    ? shape.fuse
                    : 0;
-    const int nmax = shape.fwin == 2 ? 6 : 4;  // whole rows: up to 6 steps
+    const int nmax = shape.fwin == 2 ? 8 : 4;  // whole rows: up to 8 steps
     return (shape.fuse <= nmax && fused_supported(jd)) ? shape.fuse : 0;
 }
 

@@ -1110,7 +1110,10 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     constexpr int RG = N - 1;
     constexpr int NR = N > 1 ? N - 1 : 1;
     constexpr int CW = 64 * K * M + 2;
-    __shared__ C ra[NR][2][3][CW], rb[NR][3][3][CW], rc[NR][4][3][CW];
+    // LDS rings of the level below, by the row a direction group pulls from:
+    // c_y = -1 (row y + 1) and c_y = 0 (row y): 2 rows; c_y = +1 (row y - 1):
+    // 3 rows. Row r sits in slot (r + 12) mod 2 or mod 3.
+    __shared__ C ra[NR][2][3][CW], rb[NR][2][3][CW], rc[NR][3][3][CW];
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -1161,7 +1164,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 }
         };
         auto put = [&](int L, int y, int col, const C *v) {
-            const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3;
+            const int sa = (y + 12) & 1, sb = sa, sc3 = (y + 12) % 3;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int g = GJd[i];
@@ -1227,13 +1230,15 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
             // The c_y = 0 and c_y = +1 pulls of the next row (rows y + 1 and
             // y of the level below) are complete before this row step begins
             // and their slots are not rewritten in it, so they are read one
-            // step ahead into registers (two sets, alternating), and only the
-            // c_y = -1 pulls (row y + 1, written in the previous step) wait
-            // at the start of the step.
+            // step ahead into registers (two sets, alternating; for the first
+            // row in the step before it), and only the c_y = -1 pulls (row
+            // y + 1, written in the previous step) wait at the start of the
+            // step. What is read ahead never sits in LDS for more than one
+            // step, hence the short rings.
             const int L = lvl - 2;
             C pre[2][M][6];
             auto ahead = [&](C (*q)[6], int y) {  // c_y >= 0 pulls of row y
-                const int sb = (y + 12) % 3, sc3 = (y + 11) & 3;
+                const int sb = (y + 12) & 1, sc3 = (y + 11) % 3;
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     int n = 0;
@@ -1252,8 +1257,9 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     const int it = it0 + k;
                     if (it >= n_it) break;
                     const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
-                    if (y >= y_lo && y < y_hi) {
-                        if (y == y_lo) ahead(pre[k], y);  // nothing read ahead yet
+                    if (y == y_lo - 1) {
+                        ahead(pre[k ^ 1], y + 1);  // the first row's
+                    } else if (y >= y_lo && y < y_hi) {
                         const int sa = (y + 13) & 1;
                         C f[M][9];
 #pragma unroll
@@ -2054,14 +2060,22 @@ static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
 }
 
 // Shapes of the full-row kernels: K waves per level of M columns per lane,
-// N K <= 16 waves, and (N - 1) LDS rings of ROWS direction-rows (27 on the
+// N K <= 16 waves, and (N - 1) LDS rings of ROWS direction-rows (21 on the
 // periodic lattice, 30 on the channel) of 64 K M + 2 compute values within
 // 160 KB. The shape used for a lattice nx wide: the fewest columns per lane
 // (M = 1, else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
-static constexpr int RING_ROWS_TGV = 27, RING_ROWS_CH = 30;
+static constexpr int RING_ROWS_TGV = 21, RING_ROWS_CH = 30;
+
+// Registers: a lane colliding two columns needs about 165 VGPRs in single
+// precision (twice as many in double), so such shapes keep to 12 waves (3 per
+// SIMD, 168 VGPRs each; FP64: 8 waves, 256); one column per lane fits 128
+// (FP64: 168), the budget of 16 waves, in single precision only.
+static constexpr bool rows_regs_fit(int prec, int waves, int M) {
+    return prec == UQ_FP64 ? waves <= (M == 2 ? 8 : 12) : (M == 2 ? waves <= 12 : true);
+}
 
 static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
-    return n * K <= 16 && K <= 4 &&
+    return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M) &&
            (int64_t)(n - 1) * rows * (64 * K * M + 2) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
 }
 
@@ -2146,7 +2160,9 @@ static void fused_p(const JobDev &j, int n, bool src2, int fty, int window, bool
         else if (n == 3) stepR_p<P, 3>(j, src2, fty, nt, s);
         else if (n == 4) stepR_p<P, 4>(j, src2, fty, nt, s);
         else if (n == 5) stepR_p<P, 5>(j, src2, fty, nt, s);
-        else stepR_p<P, 6>(j, src2, fty, nt, s);
+        else if (n == 6) stepR_p<P, 6>(j, src2, fty, nt, s);
+        else if (n == 7) stepR_p<P, 7>(j, src2, fty, nt, s);
+        else stepR_p<P, 8>(j, src2, fty, nt, s);
     } else if (window) {
         if (n == 2) stepW_p<P, 2>(j, src2, fty, nt, s);
         else if (n == 3) stepW_p<P, 3>(j, src2, fty, nt, s);
@@ -2171,7 +2187,7 @@ hipError_t launch_fused(const JobDev &j, int n, bool src2, int fty, int window, 
         }
         return hipGetLastError();
     }
-    if (!fused_supported(j) || n < 2 || n > (window == 2 ? 6 : 4)) return hipErrorInvalidValue;
+    if (!fused_supported(j) || n < 2 || n > (window == 2 ? 8 : 4)) return hipErrorInvalidValue;
     if (window == 2 && j.nx > full_rows_max_nx(j.prec, n)) return hipErrorInvalidValue;
     switch (j.prec) {
         case UQ_FP64: fused_p<UQ_FP64>(j, n, src2, fty, window, nt, s); break;

@@ -98,7 +98,6 @@ using namespace uqi;
 extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, uq_tune_result *out) {
     if (!p || !out) return fail(UQ_EINVAL, "null argument");
     if (steps < 2) return fail(UQ_EINVAL, "steps must be >= 2");
-    steps = steps / 120 * 120;  // whole fused blocks (4, 3, 8, 5 and 12 steps)
     if (steps < 120) steps = 120;
     Rule r;
     uq_status st = build_rule(*p, r);
@@ -161,7 +160,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
                         cands.push_back(s);
                     }
             for (int win : {1, 2})
-                for (int n : {2, 3, 4, 5, 6})
+                for (int n : {2, 3, 4, 5, 6, 7, 8})
                     for (int fty : (p->precision == UQ_FP64 ? std::vector<int>{32, 64} : std::vector<int>{64, 256})) {
                         if (win == 1 && n > 4) continue;  // strips: up to 4 steps
                         if (win == 2 && (n < 3 || p->nx > full_rows_max_nx(p->precision, n))) continue;
@@ -190,9 +189,12 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
         double ms = 0.0;
         hipEvent_t a = nullptr, b = nullptr;
         bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-        ok = ok && j->advance(120) == UQ_OK;  // warm-up (whole fused blocks of 2 to 6 steps)
+        // each candidate times whole launch blocks (N steps, 2N for even N)
+        const int64_t block = cand.fuse >= 2 ? ((cand.fuse & 1) ? cand.fuse : 2 * cand.fuse) : 1;
+        const int64_t csteps = std::max(block, steps / block * block);
+        ok = ok && j->advance(2 * block) == UQ_OK;  // warm-up
         ok = ok && hipEventRecord(a, j->stream) == hipSuccess;
-        ok = ok && j->advance(steps) == UQ_OK;
+        ok = ok && j->advance(csteps) == UQ_OK;
         ok = ok && hipEventRecord(b, j->stream) == hipSuccess;
         ok = ok && hipEventSynchronize(b) == hipSuccess;
         float f = 0.0f;
@@ -202,7 +204,7 @@ extern "C" uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int6
         (void)hipSetDevice(j->dev.device);
         delete j;
         if (!ok) return fail(UQ_EDEVICE, "timing a tuning candidate failed");
-        ms = (double)f / (double)steps;
+        ms = (double)f / (double)csteps;
         ++tried;
         const double gbs = (double)r.S * p->nx * p->ny * bytes_per_node / (ms * 1e-3) / 1e9;
         if (tried == 1 || gbs > best.gbs) {

@@ -434,9 +434,9 @@ def test_autotune_picks_a_candidate_and_jobs_use_it():
     r = A.autotune(spec, steps=10)
     # nx = 96: 64- and 128-wide workgroups (256 would leave half the lanes
     # idle), plus 12 fused tile candidates (2, 3, 4 steps x 2 pads x 2 tile
-    # heights), 6 sliding-window ones (2, 3, 4 steps x 2 chunk heights) and 8
-    # full-row ones (3, 4, 5, 6 steps x 2 chunk heights)
-    assert r["n_candidates"] == 50 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
+    # heights), 6 sliding-window ones (2, 3, 4 steps x 2 chunk heights) and 12
+    # full-row ones (3 to 8 steps x 2 chunk heights)
+    assert r["n_candidates"] == 54 and r["layout"] in ("aa", "ab") and r["gbs"] > 0
     with Job(spec) as job:
         inf = job.info()
         assert ({1: "aa", 2: "ab"}[inf.layout], inf.cpt, inf.plane_pad, inf.bx, inf.fused, inf.fused_rows,
@@ -619,6 +619,45 @@ def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
     # rounding: bit for bit the same populations and kinetic energy
     assert np.array_equal(res["0"][0], res[str(n)][0])
     assert np.array_equal(res["0"][1], res[str(n)][1])
+
+
+@pytest.mark.parametrize("n", [7, 8])
+@pytest.mark.parametrize("nx, ny, rows", [(72, 40, 16), (128, 9, 64), (20, 12, 8), (3, 5, 8), (128, 128, 256)])
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+def test_full_row_kernel_seven_and_eight_steps(prec, nx, ny, rows, n, monkeypatch):
+    # 7 and 8 steps per launch: whole rows of at most 128 columns (one column
+    # per lane, 14 or 16 waves), single precision and 16-bit storage; bit for
+    # bit the single-step result, over counts that leave single steps after
+    # the fused blocks
+    monkeypatch.setenv("UQ_FUSE_TY", str(rows))
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision=prec)
+    say("case full rows", n, prec, "lattice", nx, ny, "rows", rows)
+    for steps in (n + 1, 3 * n + 5):
+        res = {}
+        for fuse in ("0", str(n)):
+            monkeypatch.setenv("UQ_FUSE", fuse)
+            with Job(spec) as job:
+                assert job.info().fused == (n if fuse != "0" else 0)
+                job.run(steps)
+                res[fuse] = job.populations(5)
+        assert np.array_equal(res["0"], res[str(n)]), steps
+    if prec == "fp32":
+        with Job(spec) as job:
+            xi, _ = job.samples()
+        p = O.sample_params(spec, xi[5])
+        ref = O.tgv_run(nx, ny, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+        assert np.abs(res[str(n)] - ref).max() < 1e-6
+
+
+def test_full_row_kernel_eight_steps_refused_where_rows_are_too_wide(monkeypatch):
+    # 256 columns need two columns per lane: 16 waves of those do not fit the
+    # registers, so 8 steps over whole rows fall back to single steps
+    monkeypatch.setenv("UQ_FUSE", "8")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(TGV_RAGGED, nx=256, ny=16, layout="ab", precision="fp32")
+    with Job(spec) as job:
+        assert job.info().fused == 0
 
 
 @pytest.mark.parametrize("n, window, rows, nt", [(2, 0, 8, 1), (3, 0, 8, 1), (4, 1, 64, 0), (4, 2, 256, 0),
