@@ -164,10 +164,14 @@ __device__ inline double coll_recip(double x) { return recip(x); }
 
 template <typename C>
 __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
-    const C drho = ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
-    const C d57 = f[5] - f[7], d86 = f[8] - f[6];
-    const C jx = ((f[1] - f[3]) + d57) + d86;
-    const C jy = ((f[2] - f[4]) + d57) - d86;
+    // moments from the sums of the c_y = +1 and c_y = -1 populations (j_y is
+    // their difference), with the c_y = -1 terms last: the fused kernels
+    // read the others a row ahead, so most of this runs while those loads
+    // are in flight
+    const C cs = f[2] + (f[5] + f[6]), as = f[4] + (f[7] + f[8]);
+    const C drho = ((f[0] + (f[1] + f[3])) + cs) + as;
+    const C jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+    const C jy = cs - as;
     const C ir = coll_recip(C(1) + drho);
     const C ux = jx * ir, uy = jy * ir;
     // second-order terms from the products j_x u_x, j_y u_y and j_x u_y

@@ -119,6 +119,22 @@ def test_tgv_4d_reduced_precision(prec, layout, tgv4d_ref):
         assert rel_l2(sv["mean"], ref["stats"]["vel"]["mean"], scale=rms) < tol
         assert rel_l2(sv["coeffs"], ref["stats"]["vel"]["coeffs"], scale=rms) < tol
         assert rel_l2(sv["var"], ref["stats"]["vel"]["var"]) < tol
+        # storage: FP16S holds the shifted populations times 2^s as halves,
+        # BF16S holds them unscaled as bfloat16, FP32 as floats
+        inf = job.info()
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+        t = job.populations(1) - w
+        t = t[np.abs(t) > 1e-12]  # where w + f~ is exact in double
+        if prec == "fp16s":
+            assert inf.scale_exp > 0
+            v = t * 2.0 ** inf.scale_exp
+            assert np.array_equal(v.astype(np.float16).astype(np.float64), v)
+        else:
+            assert inf.scale_exp == 0
+            f32 = t.astype(np.float32)
+            assert np.array_equal(f32.astype(np.float64), t)
+            if prec == "bf16s":
+                assert not (f32.view(np.uint32) & 0xFFFF).any()
 
 
 def test_tgv_monte_carlo_fp32():
