@@ -1113,11 +1113,15 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     using T = typename PR::T;
     constexpr int RG = N - 1;
     constexpr int NR = N > 1 ? N - 1 : 1;
-    constexpr int CW = 64 * K * M + 2;
     // LDS rings of the level below, by the row a direction group pulls from:
-    // c_y = -1 (row y + 1) and c_y = 0 (row y): 2 rows; c_y = +1 (row y - 1):
-    // 3 rows. Row r sits in slot (r + 12) mod 2 or mod 3.
-    __shared__ C ra[NR][2][3][CW], rb[NR][2][3][CW], rc[NR][3][3][CW];
+    // c_y = -1 (row y + 1, slots 0-1) and c_y = 0 (row y, slots 2-3): 2 rows;
+    // c_y = +1 (row y - 1, slots 4-6): 3 rows. Row r sits in slot (r + 12)
+    // mod 2 or mod 3 of its group. Rows are padded to a multiple of 64
+    // values, so that the three rows of a slot, and the same slot of the first
+    // two groups, lie a multiple of 64 words apart: the compiler pairs those
+    // accesses into ds_read2st64 / ds_write2st64.
+    constexpr int CW = 64 * K * M + 64;
+    __shared__ C rg[NR][7][3][CW];
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -1172,9 +1176,9 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int g = GJd[i];
-                if (CYd[i] < 0) ra[L][sa][g][col] = v[i];
-                else if (CYd[i] == 0) rb[L][sb][g][col] = v[i];
-                else rc[L][sc3][g][col] = v[i];
+                if (CYd[i] < 0) rg[L][sa][g][col] = v[i];
+                else if (CYd[i] == 0) rg[L][2 + sb][g][col] = v[i];
+                else rg[L][4 + sc3][g][col] = v[i];
             }
         };
         // collide the lane's M nodes of row y and hand each on to the next
@@ -1250,7 +1254,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     for (int i = 0; i < 9; ++i) {
                         if (CYd[i] < 0) continue;
                         const int g = GJd[i], cl = c[m] + 1 - CXd[i];
-                        q[m][n++] = CYd[i] == 0 ? rb[L][sb][g][cl] : rc[L][sc3][g][cl];
+                        q[m][n++] = CYd[i] == 0 ? rg[L][2 + sb][g][cl] : rg[L][4 + sc3][g][cl];
                     }
                 }
             };
@@ -1272,7 +1276,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
 #pragma unroll
                             for (int i = 0; i < 9; ++i) {
                                 if (CYd[i] < 0)
-                                    f[m][i] = ra[L][sa][GJd[i]][c[m] + 1 - CXd[i]];
+                                    f[m][i] = rg[L][sa][GJd[i]][c[m] + 1 - CXd[i]];
                                 else
                                     f[m][i] = pre[k][m][n++];
                             }
@@ -2065,7 +2069,7 @@ static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
 
 // Shapes of the full-row kernels: K waves per level of M columns per lane,
 // N K <= 16 waves, and (N - 1) LDS rings of ROWS direction-rows (21 on the
-// periodic lattice, 30 on the channel) of 64 K M + 2 compute values within
+// periodic lattice, 30 on the channel) of about 64 K M compute values within
 // 160 KB. The shape used for a lattice nx wide: the fewest columns per lane
 // (M = 1, else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
 static constexpr int RING_ROWS_TGV = 21, RING_ROWS_CH = 30;
@@ -2078,9 +2082,13 @@ static constexpr bool rows_regs_fit(int prec, int waves, int M) {
     return prec == UQ_FP64 ? waves <= (M == 2 ? 8 : 12) : (M == 2 ? waves <= 12 : true);
 }
 
+// values per LDS row: the periodic kernel pads its rows to a multiple of 64
+// values, the channel kernel keeps the two end columns only
+static constexpr int ring_cols(int rows, int K, int M) { return 64 * K * M + (rows == RING_ROWS_TGV ? 64 : 2); }
+
 static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
     return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M) &&
-           (int64_t)(n - 1) * rows * (64 * K * M + 2) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
+           (int64_t)(n - 1) * rows * ring_cols(rows, K, M) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
 }
 
 static int rows_shape(int prec, int n, int rows, int nx, int *K, int *M) {
