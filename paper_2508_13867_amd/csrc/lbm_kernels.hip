@@ -1102,9 +1102,10 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
 // The sliding window over whole rows: K waves per time level, M columns per
 // lane, cover the nx <= 64 K M columns of a row, so on a periodic lattice no
 // column is computed twice (only a chunk's row halo is). Each LDS row holds
-// its nx columns at 1..nx plus copies of the last and the first column at 0
-// and nx + 1, so that every pull from the row below is a fixed offset from
-// the lane's own column. N K waves in one workgroup, one barrier per row.
+// one direction of the nx columns at 1..nx, already shifted by the
+// direction's c_x (periodic wrap included), so that every pull from the row
+// below reads the lane's own column. N K waves in one workgroup, one barrier
+// per row.
 template <int P, int N, int K, int M, int D>
 __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H, int chunks, int64_t nwork,
                                                       bool nt) {
@@ -1135,13 +1136,15 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     // lane reads, compute the same values and write them to the same places
     // (the same bits), so no lane needs a guard and the compiler keeps the
     // collisions and the LDS reads that feed them unconditional.
-    int c[M], vo0[M], vom[M], vop[M];
+    int c[M], vo0[M], vom[M], vop[M], wp[M], wm[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         c[m] = min(((wave - (lvl - 1) * K) * M + m) * 64 + lane, nx - 1);
         vo0[m] = c[m] * (int)sizeof(T);
         vom[m] = (c[m] == 0 ? nx - 1 : c[m] - 1) * (int)sizeof(T);
         vop[m] = (c[m] == nx - 1 ? 0 : c[m] + 1) * (int)sizeof(T);
+        wp[m] = (c[m] == nx - 1 ? 0 : c[m] + 1) + 1;  // LDS columns of the c_x = +1 and -1 pushes
+        wm[m] = (c[m] == 0 ? nx - 1 : c[m] - 1) + 1;
     }
     const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
     const int64_t G = gridDim.x;
@@ -1171,13 +1174,17 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     f[m][i] = BufLd<P>::raw(rsrc, vo, i * plane_b + ro);
                 }
         };
-        auto put = [&](int L, int y, int col, const C *v) {
-            const int sa = (y + 12) & 1, sb = sa, sc3 = (y + 12) % 3;
+        // a level hands direction i of its column c on to LDS column
+        // ((c + c_ix) mod nx) + 1, where the level above pulls it: every pull
+        // then reads the puller's own column, and the periodic wrap costs no
+        // extra copies
+        auto put = [&](int L, int y, int m, const C *v) {
+            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const int g = GJd[i];
+                const int g = GJd[i], col = CXd[i] > 0 ? wp[m] : (CXd[i] < 0 ? wm[m] : c[m] + 1);
                 if (CYd[i] < 0) rg[L][sa][g][col] = v[i];
-                else if (CYd[i] == 0) rg[L][2 + sb][g][col] = v[i];
+                else if (CYd[i] == 0) rg[L][2 + sa][g][col] = v[i];
                 else rg[L][4 + sc3][g][col] = v[i];
             }
         };
@@ -1195,9 +1202,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     C v[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
-                    put(lvl - 1, y, c[m] + 1, v);
-                    if (c[m] == nx - 1) put(lvl - 1, y, 0, v);   // left copy of the last column
-                    if (c[m] == 0) put(lvl - 1, y, nx + 1, v);   // right copy of the first column
+                    put(lvl - 1, y, m, v);
                 } else if (nt) {
                     const int own = y * (int)j.pitch + c[m];
 #pragma unroll
@@ -1253,8 +1258,8 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         if (CYd[i] < 0) continue;
-                        const int g = GJd[i], cl = c[m] + 1 - CXd[i];
-                        q[m][n++] = CYd[i] == 0 ? rg[L][2 + sb][g][cl] : rg[L][4 + sc3][g][cl];
+                        const int g = GJd[i], x = c[m] + 1;
+                        q[m][n++] = CYd[i] == 0 ? rg[L][2 + sb][g][x] : rg[L][4 + sc3][g][x];
                     }
                 }
             };
@@ -1268,22 +1273,35 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                     if (y == y_lo - 1) {
                         ahead(pre[k ^ 1], y + 1);  // the first row's
                     } else if (y >= y_lo && y < y_hi) {
-                        const int sa = (y + 13) & 1;
+                        // row y + 1 of the level below: this row's c_y = -1
+                        // pulls and the next row's c_y = 0 pulls (slots of the
+                        // same index, two apart); row y: the next row's c_y = +1
+                        // pulls. All at the lane's own column, 64-word multiples
+                        // apart (ds_read2st64 pairs). Past the last row the
+                        // values read ahead are not used.
+                        const int sa = (y + 13) & 1, sc3 = (y + 12) % 3;
                         C f[M][9];
+                        C (*q)[6] = pre[k ^ 1];
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
-                            int n = 0;
-#pragma unroll
-                            for (int i = 0; i < 9; ++i) {
-                                if (CYd[i] < 0)
-                                    f[m][i] = rg[L][sa][GJd[i]][c[m] + 1 - CXd[i]];
-                                else
-                                    f[m][i] = pre[k][m][n++];
-                            }
+                            const int x = c[m] + 1;  // the lane's LDS column
+                            f[m][4] = rg[L][sa][0][x];       // (0, -1)
+                            f[m][7] = rg[L][sa][1][x];       // (-1, -1)
+                            f[m][8] = rg[L][sa][2][x];       // (1, -1)
+                            q[m][0] = rg[L][2 + sa][0][x];   // (0, 0)
+                            q[m][1] = rg[L][2 + sa][1][x];   // (1, 0)
+                            q[m][3] = rg[L][2 + sa][2][x];   // (-1, 0)
+                            q[m][2] = rg[L][4 + sc3][0][x];  // (0, 1)
+                            q[m][4] = rg[L][4 + sc3][1][x];  // (1, 1)
+                            q[m][5] = rg[L][4 + sc3][2][x];  // (-1, 1)
+                            // this row's c_y >= 0 pulls, read a step ago
+                            f[m][0] = pre[k][m][0];
+                            f[m][1] = pre[k][m][1];
+                            f[m][2] = pre[k][m][2];
+                            f[m][3] = pre[k][m][3];
+                            f[m][5] = pre[k][m][4];
+                            f[m][6] = pre[k][m][5];
                         }
-                        // after this row's own reads; past the last row the
-                        // values are read but not used
-                        ahead(pre[k ^ 1], y + 1);
                         finish(f, y);
                     }
                     __syncthreads();
