@@ -1178,15 +1178,19 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
         // ((c + c_ix) mod nx) + 1, where the level above pulls it: every pull
         // then reads the puller's own column, and the periodic wrap costs no
         // extra copies
+        // (the c_y = -1 and c_y = 0 groups use slots of the same index, two
+        // apart: their writes of equal c_x go in pairs, ds_write2st64)
         auto put = [&](int L, int y, int m, const C *v) {
-            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int g = GJd[i], col = CXd[i] > 0 ? wp[m] : (CXd[i] < 0 ? wm[m] : c[m] + 1);
-                if (CYd[i] < 0) rg[L][sa][g][col] = v[i];
-                else if (CYd[i] == 0) rg[L][2 + sa][g][col] = v[i];
-                else rg[L][4 + sc3][g][col] = v[i];
-            }
+            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3, x = c[m] + 1;
+            rg[L][sa][0][x] = v[4];
+            rg[L][2 + sa][0][x] = v[0];
+            rg[L][sa][1][wm[m]] = v[7];
+            rg[L][2 + sa][2][wm[m]] = v[3];
+            rg[L][sa][2][wp[m]] = v[8];
+            rg[L][2 + sa][1][wp[m]] = v[1];
+            rg[L][4 + sc3][0][x] = v[2];
+            rg[L][4 + sc3][1][wp[m]] = v[5];
+            rg[L][4 + sc3][2][wm[m]] = v[6];
         };
         // collide the lane's M nodes of row y and hand each on to the next
         // level
