@@ -125,6 +125,8 @@ def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
     (17, 9, 7, 8, 64),     # 7 levels
     (5, 3, 8, 8, 64),      # 8 levels on 3 rows: rows wrap more than once
     (70, 13, 4, 8, 128),   # two waves of columns
+    (1, 4, 6, 8, 64),      # one column: every direction lands on it
+    (4, 1, 5, 8, 64),      # one row: every pull wraps to it
 ])
 def test_row_pipeline_schedule(nx, ny, n_lvl, rows, lanes):
     assert run_schedule(nx, ny, n_lvl, rows, lanes) < 1e-14
