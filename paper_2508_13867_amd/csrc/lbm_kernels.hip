@@ -1334,9 +1334,14 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *
     using T = typename PR::T;
     constexpr int RG = N - 1;
     constexpr int NR = N > 1 ? N - 1 : 1;
-    constexpr int CW = 64 * K * M + 2;
+    // one LDS array for the three rings (c_y = -1: slots 0-2, c_y = 0: 3-5,
+    // c_y = +1: 6-9), rows padded to a multiple of 64 values: the rows of a
+    // slot, and the slots of equal index of the first two groups, lie 64-word
+    // multiples apart, and the compiler pairs those accesses (ds_read2st64 /
+    // ds_write2st64)
+    constexpr int CW = 64 * K * M + 64;
     constexpr uint32_t BB_BITS = 0x1FFu << M_BB, OPEN_BITS = 0x1FFu << M_OPEN;
-    __shared__ C ra[NR][3][3][CW], rb[NR][3][3][CW], rc[NR][4][3][CW];
+    __shared__ C rq[NR][10][3][CW];
     const int64_t t0 = *d_t + k0;
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
@@ -1397,15 +1402,17 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *
 #pragma unroll
             for (int m = 0; m < M; ++m) mm[m] = __builtin_amdgcn_raw_buffer_load_b32(mrsrc, mvo[m], mo, 0);
         };
-        auto put = [&](int L, int y, int col, const C *v) {
+        auto put = [&](int L, int y, int col, const C *v) {  // by direction-row, c_y = -1 and 0 in pairs
             const int s3 = (y + 12) % 3, s4 = (y + 12) & 3;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int g = GJd[i];
-                if (CYd[i] < 0) ra[L][s3][g][col] = v[i];
-                else if (CYd[i] == 0) rb[L][s3][g][col] = v[i];
-                else rc[L][s4][g][col] = v[i];
-            }
+            rq[L][s3][0][col] = v[4];
+            rq[L][3 + s3][0][col] = v[0];
+            rq[L][s3][1][col] = v[7];
+            rq[L][3 + s3][1][col] = v[1];
+            rq[L][s3][2][col] = v[8];
+            rq[L][3 + s3][2][col] = v[3];
+            rq[L][6 + s4][0][col] = v[2];
+            rq[L][6 + s4][1][col] = v[5];
+            rq[L][6 + s4][2][col] = v[6];
         };
         // the open-column rule, then collide, then hand on or store
         auto finish = [&](C (*f)[9], const uint32_t *mm, int y) {
@@ -1487,21 +1494,21 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *
 #pragma unroll
                         for (int i = 0; i < 9; ++i) {
                             const int g = GJd[i], cl = lc - CXd[i];
-                            f[m][i] = CYd[i] < 0 ? ra[L][pa][g][cl]
-                                                 : (CYd[i] == 0 ? rb[L][pb][g][cl] : rc[L][pc][g][cl]);
+                            f[m][i] = CYd[i] < 0 ? rq[L][pa][g][cl]
+                                                 : (CYd[i] == 0 ? rq[L][3 + pb][g][cl] : rq[L][6 + pc][g][cl]);
                         }
                         if (mb[k][m] & BB_BITS) {
                             // this node's populations of the level below, by direction
                             C own[9];
-                            own[0] = rb[L][pb][0][lc];
-                            own[1] = rb[L][pb][1][lc];
-                            own[3] = rb[L][pb][2][lc];
-                            own[2] = rc[L][oc][0][lc];
-                            own[5] = rc[L][oc][1][lc];
-                            own[6] = rc[L][oc][2][lc];
-                            own[4] = ra[L][oa][0][lc];
-                            own[7] = ra[L][oa][1][lc];
-                            own[8] = ra[L][oa][2][lc];
+                            own[0] = rq[L][3 + pb][0][lc];
+                            own[1] = rq[L][3 + pb][1][lc];
+                            own[3] = rq[L][3 + pb][2][lc];
+                            own[2] = rq[L][6 + oc][0][lc];
+                            own[5] = rq[L][6 + oc][1][lc];
+                            own[6] = rq[L][6 + oc][2][lc];
+                            own[4] = rq[L][oa][0][lc];
+                            own[7] = rq[L][oa][1][lc];
+                            own[8] = rq[L][oa][2][lc];
 #pragma unroll
                             for (int i = 0; i < 9; ++i)
                                 f[m][i] = ((mb[k][m] >> (M_BB + i)) & 1u) ? own[OPPd[i]] : f[m][i];
@@ -2104,9 +2111,9 @@ static constexpr bool rows_regs_fit(int prec, int waves, int M) {
     return prec == UQ_FP64 ? waves <= (M == 2 ? 8 : 12) : (M == 2 ? waves <= 12 : true);
 }
 
-// values per LDS row: the periodic kernel pads its rows to a multiple of 64
-// values, the channel kernel keeps the two end columns only
-static constexpr int ring_cols(int rows, int K, int M) { return 64 * K * M + (rows == RING_ROWS_TGV ? 64 : 2); }
+// values per LDS row: padded to a multiple of 64 (the columns, two end
+// columns on the channel, and the padding)
+static constexpr int ring_cols(int, int K, int M) { return 64 * K * M + 64; }
 
 static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
     return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M) &&
