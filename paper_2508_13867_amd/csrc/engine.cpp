@@ -4,6 +4,7 @@
 // serves every replay).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <string>
 
@@ -89,7 +90,8 @@ int Job::fused_n() const {
 // state of step u lives in slab u & 1. A launch of N fused steps reads the
 // current slab and writes the other one: for odd N that is the slab of step
 // u + N; even N go in pairs (there and back), so that the invariant holds
-// after each pair. Steps left over run one per launch.
+// after each pair. Steps left over go in single fused launches of an odd
+// number (3 or more, at most N) of steps, largest first, then one per launch.
 hipError_t Job::enqueue_steps(int k0, int64_t n) {
     hipError_t e = hipSuccess;
     int64_t &enqueued = pending_launches;
@@ -105,6 +107,16 @@ hipError_t Job::enqueue_steps(int k0, int64_t n) {
                 e = launch_fused(jd, N, !odd, shape.fty, shape.fwin, shape.nt != 0, d_t, (int)(k0 + k + N), stream);
                 ++enqueued;
             }
+        }
+        // fewer steps than a block: a shape that runs N steps runs fewer
+        for (int64_t r = n - k; r >= 3 && e == hipSuccess; r = n - k) {
+            int m = (int)std::min<int64_t>(r, N);
+            if (!(m & 1)) --m;
+            if (m < 3) break;
+            const bool odd = ((t + k0 + k) & 1) != 0;
+            e = launch_fused(jd, m, odd, shape.fty, shape.fwin, shape.nt != 0, d_t, (int)(k0 + k), stream);
+            ++enqueued;
+            k += m;
         }
     }
     for (; k < n && e == hipSuccess; ++k) {
