@@ -666,6 +666,27 @@ def test_full_row_kernel_seven_and_eight_steps(prec, nx, ny, rows, n, monkeypatc
         assert np.abs(res[str(n)] - ref).max() < 1e-6
 
 
+@pytest.mark.parametrize("steps, launches", [(3, 1), (5, 1), (7, 3), (8, 2), (13, 3), (20, 4), (25, 5)])
+def test_steps_left_over_run_as_odd_fused_launches(steps, launches, monkeypatch):
+    # 6 steps per launch in pairs (12); what is left goes in odd fused
+    # launches of 5 or 3 steps, then single steps (7 = 5 + 1 + 1,
+    # 8 = 5 + 3, 13 = 12 + 1, 20 = 12 + 5 + 3, 25 = 24 + 1): bit for bit the
+    # single-step result, and the launch count says which kernels ran
+    monkeypatch.setenv("UQ_FUSE_TY", "16")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    monkeypatch.setenv("UQ_GRAPH_STEPS", "0")
+    spec = W.scaled(TGV_RAGGED, layout="ab", precision="fp32")
+    say("case leftover steps", steps)
+    res = {}
+    for fuse in ("0", "6"):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        with Job(spec) as job:
+            job.run(steps)
+            res[fuse] = (job.populations(4), job.info().step_launches)
+    assert np.array_equal(res["0"][0], res["6"][0])
+    assert res["0"][1] == steps and res["6"][1] == launches
+
+
 def test_full_row_kernel_eight_steps_refused_where_rows_are_too_wide(monkeypatch):
     # 256 columns need two columns per lane: 16 waves of those do not fit the
     # registers, so 8 steps over whole rows fall back to single steps
