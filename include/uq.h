@@ -285,9 +285,10 @@ typedef struct {
     int32_t nt_store;   /* 1 if AB stores bypass the caches            */
     int32_t plane_pad;  /* padding elements after each population plane */
     int32_t bx;         /* step-kernel workgroup width (height 256/bx) */
-    int32_t fused;      /* steps per launch of the fused periodic AB
-                           kernel (2..4; up to 8 over whole rows), 0
-                           if not fused                                */
+    int32_t fused;      /* steps per launch of the fused AB kernel
+                           (tiles and strips 2..4, whole periodic rows
+                           2..8, whole channel rows 2..4), 0 if not
+                           fused                                       */
     int32_t fused_rows; /* its tile height (rows of 64 nodes), or the
                            window kernel's chunk height               */
     int64_t step_launches; /* step-kernel launches so far (a fused launch
@@ -309,9 +310,15 @@ uq_status uq_create(const uq_problem *p, const uq_device *dev, uq_job **out);
  * be NULL; S and d are returned through the pointers if not NULL. */
 uq_status uq_samples(const uq_job *job, double *xi, double *a, int64_t *S, int32_t *d);
 
-/* Advance all samples by `steps` LBM steps (fused stream + collide with the
- * boundaries inline, one launch per step). Asynchronous on the job's stream;
- * steps >= 0. */
+/* Advance all samples by `steps` LBM steps (stream + collide with the
+ * boundaries inline). Every launch advances all samples: one step per launch,
+ * or, in the fused shapes the tuner picks for periodic lattices and simple
+ * channels in the AB layout, N = 2..8 steps per launch (temporal blocking).
+ * Whole blocks of fused launches are replayed from a captured hipGraph; the
+ * steps left over run as launches of an odd number (3 or more, at most N) of
+ * fused steps, largest first, and the last one or two as single steps, so
+ * the state after `steps` steps does not depend on N. Asynchronous on the
+ * job's stream; steps >= 0. */
 uq_status uq_run(uq_job *job, int64_t steps);
 
 /* uq_run followed by a wait, with the elapsed device time of the step
@@ -378,7 +385,7 @@ typedef struct {
                            its steps, so for those it exceeds the traffic)      */
     double ms_per_step; /* its average step duration                           */
     int32_t n_candidates;
-    int32_t fused;      /* steps per launch of the best if fused (2..6), else 0 */
+    int32_t fused;      /* steps per launch of the best if fused (2..8), else 0 */
     int32_t fused_rows; /* its tile height (window: chunk height)              */
     int32_t fused_window; /* 0 tiles, 1 window strips, 2 window over whole rows */
 } uq_tune_result;

@@ -96,17 +96,50 @@ __global__ void k_w1_finish(const double *partial, int nblocks, double *out) {
 
 }  // namespace
 
-// sorted values and cumulative weights of one job's law; buffers from job a
-static uq_status build_law(Job *owner, Job *src, int qoi, double scale, double **x_sorted, double **P, int64_t *n) {
+// Device buffers of one W_1 evaluation, taken from job `owner`. Whatever is
+// still held when the guard goes out of scope (every early return) is given
+// back after the owner's stream has drained, so no error path leaks a block
+// or frees one that a queued kernel still reads.
+struct W1Buffers {
+    Job *owner;
+    std::vector<void *> held;
+    explicit W1Buffers(Job *o) : owner(o) {}
+    W1Buffers(const W1Buffers &) = delete;
+    W1Buffers &operator=(const W1Buffers &) = delete;
+    void *take(size_t bytes) {
+        void *p = owner->dalloc(bytes);
+        if (p) held.push_back(p);
+        return p;
+    }
+    void give_back(void *p) {  // caller has ordered the stream already
+        for (size_t i = 0; i < held.size(); ++i)
+            if (held[i] == p) {
+                owner->dfree(p);
+                held.erase(held.begin() + (long)i);
+                return;
+            }
+    }
+    ~W1Buffers() {
+        if (held.empty()) return;
+        (void)hipStreamSynchronize(owner->stream);
+        (void)hipGetLastError();
+        for (void *p : held) owner->dfree(p);
+    }
+};
+
+// sorted values and cumulative weights of one job's law, in buffers of `buf`
+static uq_status build_law(W1Buffers &buf, Job *src, int qoi, double scale, double **x_sorted, double **P,
+                           int64_t *n) {
+    Job *owner = buf.owner;
     const double *M;
     int64_t n_out, ld;
     uq_status st = src->sample_values(qoi, &M, &n_out, &ld);
     if (st != UQ_OK) return st;
     const int64_t L = src->S * n_out;
     if (L >= ((int64_t)1 << 31)) return fail(UQ_EINVAL, "law too large for one sort");
-    double *a_dev = (double *)owner->dalloc(sizeof(double) * src->S);
-    double *k0 = (double *)owner->dalloc(sizeof(double) * L), *w0 = (double *)owner->dalloc(sizeof(double) * L);
-    double *k1 = (double *)owner->dalloc(sizeof(double) * L), *w1 = (double *)owner->dalloc(sizeof(double) * L);
+    double *a_dev = (double *)buf.take(sizeof(double) * src->S);
+    double *k0 = (double *)buf.take(sizeof(double) * L), *w0 = (double *)buf.take(sizeof(double) * L);
+    double *k1 = (double *)buf.take(sizeof(double) * L), *w1 = (double *)buf.take(sizeof(double) * L);
     if (!a_dev || !k0 || !w0 || !k1 || !w1) return fail(UQ_ENOMEM, "out of device memory for the W1 sort");
     hipStream_t s = owner->stream;
     // values are produced on src's stream; order owner's stream after it
@@ -119,15 +152,12 @@ static uq_status build_law(Job *owner, Job *src, int qoi, double scale, double *
     size_t tb = 0, tb2 = 0;
     UQ_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, k1, w0, w1, (int)L, 0, 64, s));
     UQ_HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, w1, w0, (int)L, s));
-    void *tmp = owner->dalloc(std::max(tb, tb2));
+    void *tmp = buf.take(std::max(tb, tb2));
     if (!tmp) return fail(UQ_ENOMEM, "out of device memory for the W1 sort");
     UQ_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, k1, w0, w1, (int)L, 0, 64, s));
     UQ_HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tb2, w1, w0, (int)L, s));
     UQ_HIP_TRY(hipStreamSynchronize(s));  // host copy of a_j must stay alive until here
-    owner->dfree(tmp);
-    owner->dfree(a_dev);
-    owner->dfree(k0);
-    owner->dfree(w1);
+    for (void *p : {tmp, (void *)a_dev, (void *)k0, (void *)w1}) buf.give_back(p);
     *x_sorted = k1;  // sorted values
     *P = w0;         // cumulative weights
     *n = L;
@@ -155,26 +185,29 @@ extern "C" uq_status uq_wasserstein1(uq_job *a, uq_job *b, int32_t qoi, double s
     }
     double *xa = nullptr, *Pa = nullptr, *xb = nullptr, *Pb = nullptr;
     int64_t na = 0, nb = 0;
-    st = build_law(a, a, qoi, scale_a, &xa, &Pa, &na);
-    if (st == UQ_OK) st = build_law(a, b, qoi, scale_b, &xb, &Pb, &nb);
-    if (st != UQ_OK) return st;
-    // W_1 is symmetric: the larger law takes the outer loop, so each thread
-    // meets about one interval of the other
-    if (nb > na) {
-        std::swap(xa, xb);
-        std::swap(Pa, Pb);
-        std::swap(na, nb);
+    {
+        W1Buffers buf(a);  // every buffer below goes back to job a on return
+        st = build_law(buf, a, qoi, scale_a, &xa, &Pa, &na);
+        if (st == UQ_OK) st = build_law(buf, b, qoi, scale_b, &xb, &Pb, &nb);
+        if (st != UQ_OK) return st;
+        // W_1 is symmetric: the larger law takes the outer loop, so each
+        // thread meets about one interval of the other
+        if (nb > na) {
+            std::swap(xa, xb);
+            std::swap(Pa, Pb);
+            std::swap(na, nb);
+        }
+        const int nblocks = (int)std::min<int64_t>((na + 255) / 256, 4096);
+        double *partial = (double *)buf.take(sizeof(double) * (2 * nblocks + 1));
+        if (!partial) return fail(UQ_ENOMEM, "out of device memory");
+        k_w1_overlap<<<nblocks, 256, 0, a->stream>>>(xa, Pa, na, xb, Pb, nb, partial);
+        UQ_HIP_TRY(hipGetLastError());
+        k_w1_finish<<<1, 64, 0, a->stream>>>(partial, nblocks, partial + 2 * nblocks);
+        UQ_HIP_TRY(hipGetLastError());
+        UQ_HIP_TRY(hipMemcpyAsync(w1, partial + 2 * nblocks, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+        UQ_HIP_TRY(hipStreamSynchronize(a->stream));
+        for (void *p : {(void *)xa, (void *)Pa, (void *)xb, (void *)Pb, (void *)partial}) buf.give_back(p);
     }
-    const int nblocks = (int)std::min<int64_t>((na + 255) / 256, 4096);
-    double *partial = (double *)a->dalloc(sizeof(double) * (2 * nblocks + 1));
-    if (!partial) return fail(UQ_ENOMEM, "out of device memory");
-    k_w1_overlap<<<nblocks, 256, 0, a->stream>>>(xa, Pa, na, xb, Pb, nb, partial);
-    UQ_HIP_TRY(hipGetLastError());
-    k_w1_finish<<<1, 64, 0, a->stream>>>(partial, nblocks, partial + 2 * nblocks);
-    UQ_HIP_TRY(hipGetLastError());
-    UQ_HIP_TRY(hipMemcpyAsync(w1, partial + 2 * nblocks, sizeof(double), hipMemcpyDeviceToHost, a->stream));
-    UQ_HIP_TRY(hipStreamSynchronize(a->stream));
-    for (void *p : {(void *)xa, (void *)Pa, (void *)xb, (void *)Pb, (void *)partial}) a->dfree(p);
     st = a->leave();
     if (st == UQ_OK && b != a) {
         // b's stream must not run ahead of the reads of its fields
