@@ -341,6 +341,25 @@ uq_status uq_qoi_samples(uq_job *job, int32_t qoi, double *out, int64_t *n_out);
  * UQ_EUNSTABLE if any sample holds a non-finite value. */
 uq_status uq_moments(uq_job *job, int32_t qoi, uq_moments_out *out);
 
+/* uq_moments without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same results
+ * (bit for bit) as uq_moments, with their intermediates -- per-sample scalar
+ * QoIs, per-sample fields of a field QoI, the moment outputs and a flag -- in
+ * a fixed array of UQ_NOALLOC_SCRATCH_BYTES that the library keeps on every
+ * GPU it runs on until the process ends, instead of buffers the job would
+ * allocate on its first statistics call. The job's own device memory is
+ * untouched (uq_job_info.device_bytes stays the same). The need is
+ *   256-byte-rounded 8 * (4 S + S + 1 + (K + 3) n_out)  [+ 8 * 4 nx ny S for
+ *   a field QoI];
+ * larger requests fail with UQ_EINVAL and a message naming both sizes (use
+ * uq_moments then). Calls on one GPU share its array: the library runs them
+ * one at a time (each holds the GPU's lock until its results are on the
+ * host), so calls from several threads are safe but do not overlap. Same
+ * arguments, outputs, errors and blocking behaviour as uq_moments. */
+#define UQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+uq_status uq_moments_noalloc(uq_job *job, int32_t qoi, uq_moments_out *out);
+
 /* Populations f_i(x, t) of one sample in natural order [9][ny][nx], unshifted
  * and in double, for inspection and tests (solid nodes hold 0). Blocking. */
 uq_status uq_populations(uq_job *job, int64_t sample, double *out);

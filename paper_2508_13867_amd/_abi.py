@@ -117,6 +117,7 @@ SIGNATURES = {
     "uq_sync": (C.c_int, [_P]),
     "uq_qoi_samples": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int64)]),
     "uq_moments": (C.c_int, [_P, C.c_int32, C.POINTER(MomentsOut)]),
+    "uq_moments_noalloc": (C.c_int, [_P, C.c_int32, C.POINTER(MomentsOut)]),
     "uq_populations": (C.c_int, [_P, C.c_int64, _P]),
     "uq_job_get_info": (C.c_int, [_P, C.POINTER(JobInfo)]),
     "uq_destroy": (None, [_P]),
@@ -331,7 +332,8 @@ class Job:
         check(lib().uq_qoi_samples(self.h, QOI[qoi], out.ctypes.data, C.byref(n)))
         return out
 
-    def moments(self, qoi: str) -> dict:
+    def moments(self, qoi: str, noalloc: bool = False) -> dict:
+        """uq_moments, or uq_moments_noalloc (no device allocation) if asked."""
         n = C.c_int64()
         check(lib().uq_qoi_samples(self.h, QOI[qoi], None, C.byref(n)))
         n = n.value
@@ -344,7 +346,8 @@ class Job:
             alpha = np.zeros((self.K, self.d), np.int32)
             m.coeffs, m.alpha = coeffs.ctypes.data, alpha.ctypes.data
             res["coeffs"], res["alpha"] = coeffs, alpha
-        check(lib().uq_moments(self.h, QOI[qoi], C.byref(m)))
+        fn = lib().uq_moments_noalloc if noalloc else lib().uq_moments
+        check(fn(self.h, QOI[qoi], C.byref(m)))
         return res
 
     def populations(self, sample: int) -> np.ndarray:

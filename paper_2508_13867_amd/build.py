@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libuqlbm.so")
 SOURCES = ["sampler.cpp", "uq_api.cpp", "engine.cpp", "tuner.cpp", "server.cpp", "lbm_kernels.hip",
-           "wasserstein.hip"]
+           "wasserstein.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

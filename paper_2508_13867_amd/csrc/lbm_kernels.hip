@@ -1852,6 +1852,25 @@ __global__ void k_advance(int64_t *d_t, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *d_t += n;
 }
 
+// out[0] = smallest s < S with qoi[4s + 3] != 0 (non-finite values in sample
+// s), else S. One workgroup of 256: strided scan, then an LDS min-reduction.
+__global__ __launch_bounds__(256) void k_first_bad(const double *qoi, int64_t S, int64_t *out) {
+    __shared__ int64_t red[256];
+    int64_t first = S;
+    for (int64_t s = threadIdx.x; s < S; s += blockDim.x)
+        if (qoi[4 * s + 3] != 0.0) {
+            first = s;
+            break;
+        }
+    red[threadIdx.x] = first;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // which: UQ_QOI_KE -> KE; UQ_QOI_CD / UQ_QOI_CL -> 2 F/(u_peak^2 D) with the
 // sample's peak inflow velocity and rho0 = 1
 __global__ void k_select(const double *qoi, const SampleDev *smp, int64_t S, int which, double dia, double u_fac,
@@ -2251,6 +2270,11 @@ hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s) {
 
 hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s) {
     k_select<<<(unsigned)((j.S + 255) / 256), 256, 0, s>>>(qoi, j.smp, j.S, which, j.dia, j.u_fac, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_bad(const double *qoi, int64_t S, int64_t *out, hipStream_t s) {
+    k_first_bad<<<1, 256, 0, s>>>(qoi, S, out);
     return hipGetLastError();
 }
 

@@ -109,7 +109,8 @@ static void arena_free_cb(void *p, void *ctx) { ((Arena *)ctx)->release(p); }
 static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 
 // Device bytes a job takes in the server (AA layout, scalar moments): slab,
-// per-sample records, step counter, boundary mask, basis table, QoI buffers.
+// per-sample records, step counter, boundary mask, basis table, QoI buffers
+// and the non-finite flag.
 int64_t job_footprint(const uq_problem &p, int64_t S, int K) {
     const int64_t pitch = row_pitch(p.nx);
     const int64_t plane = (int64_t)p.ny * pitch + 64;
@@ -117,7 +118,7 @@ int64_t job_footprint(const uq_problem &p, int64_t S, int K) {
     b += up256(sizeof(SampleDev) * S) + 256;
     if (p.geometry == UQ_GEOM_CHANNEL) b += up256(sizeof(uint32_t) * p.ny * pitch);
     if (K > 0) b += up256(sizeof(double) * S * K) + up256(sizeof(double) * S);
-    b += up256(sizeof(double) * 4 * S) + up256(sizeof(double) * S) + up256(sizeof(double) * (K + 3));
+    b += up256(sizeof(double) * 4 * S) + up256(sizeof(double) * S) + up256(sizeof(double) * (K + 3)) + 256;
     return (int64_t)b;
 }
 

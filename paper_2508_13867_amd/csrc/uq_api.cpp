@@ -150,7 +150,8 @@ uq_status Job::ensure_stats_buffers(int64_t n_out_max) {
     if (!d_qoi) {
         d_qoi = (double *)dalloc(sizeof(double) * 4 * S);
         d_M = (double *)dalloc(sizeof(double) * S);
-        if (!d_qoi || !d_M) return fail(UQ_ENOMEM, "out of device memory for QoI buffers");
+        d_flag = (int64_t *)dalloc(sizeof(int64_t));
+        if (!d_qoi || !d_M || !d_flag) return fail(UQ_ENOMEM, "out of device memory for QoI buffers");
     }
     if (n_out_max > out_cap) {
         const int64_t per = (int64_t)(K > 0 ? K : 0) + 3;
@@ -167,6 +168,34 @@ uq_status Job::ensure_fields() {
         d_fields = (double *)dalloc(sizeof(double) * 4 * cells * S);
         if (!d_fields) return fail(UQ_ENOMEM, "out of device memory for per-sample fields");
     }
+    return UQ_OK;
+}
+
+int64_t qoi_width(const uq_problem &p, int qoi) {
+    const int64_t cells = (int64_t)p.nx * p.ny;
+    switch (qoi) {
+        case UQ_QOI_KE:
+        case UQ_QOI_CD:
+        case UQ_QOI_CL: return 1;
+        case UQ_QOI_VEL: return 2 * cells;
+        case UQ_QOI_RHO:
+        case UQ_QOI_SPEED: return cells;
+        default: return 0;
+    }
+}
+
+uq_status Job::own_stat_bufs(int qoi, StatBufs *b) {
+    uq_status st = ensure_stats_buffers(qoi_width(p, qoi));
+    if (st != UQ_OK) return st;
+    if (qoi_width(p, qoi) > 1) {
+        st = ensure_fields();
+        if (st != UQ_OK) return st;
+    }
+    b->qoi = d_qoi;
+    b->M = d_M;
+    b->fields = d_fields;
+    b->out = d_out;
+    b->flag = d_flag;
     return UQ_OK;
 }
 
@@ -402,40 +431,66 @@ extern "C" uq_status uq_sync(uq_job *j) {
 
 namespace uqi {
 
-// Per-sample values of one QoI into d_M-like storage. Returns the device
-// pointer, number of values per sample and the row stride.
-uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld) {
+// Per-sample values of one QoI in the buffers b. Returns the device pointer,
+// number of values per sample and the row stride. Blocking (one flag read).
+uq_status Job::sample_values_in(const StatBufs &b, int qoi, const double **M, int64_t *n_out, int64_t *ld) {
     const uq_problem &P = p;
     const int64_t cells = (int64_t)P.nx * P.ny;
-    const bool field1 = qoi == UQ_QOI_RHO || qoi == UQ_QOI_SPEED;
-    uq_status st = ensure_stats_buffers(qoi == UQ_QOI_VEL ? 2 * cells : (field1 ? cells : 1));
-    if (st != UQ_OK) return st;
-    UQ_HIP_TRY(launch_qoi_scalars(jd, t, d_qoi, stream));
-    std::vector<double> h((size_t)(4 * S));
-    UQ_HIP_TRY(hipMemcpyAsync(h.data(), d_qoi, sizeof(double) * 4 * S, hipMemcpyDeviceToHost, stream));
+    if (qoi_width(P, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
+    if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (P.geometry != UQ_GEOM_CHANNEL || (P.D <= 0 && P.cyl_bc != UQ_CYL_BOUZIDI)))
+        return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
+    UQ_HIP_TRY(launch_qoi_scalars(jd, t, b.qoi, stream));
+    UQ_HIP_TRY(launch_first_bad(b.qoi, S, b.flag, stream));
+    int64_t bad = S;
+    UQ_HIP_TRY(hipMemcpyAsync(&bad, b.flag, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     UQ_HIP_TRY(hipStreamSynchronize(stream));
-    for (int64_t s = 0; s < S; ++s)
-        if (h[(size_t)(4 * s + 3)] != 0.0)
-            return fail(UQ_EUNSTABLE, "sample " + std::to_string(s) + " holds a non-finite value at step " + std::to_string(t));
-    if (qoi == UQ_QOI_KE || qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) {
-        if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (P.geometry != UQ_GEOM_CHANNEL || (P.D <= 0 && P.cyl_bc != UQ_CYL_BOUZIDI)))
-            return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
-        UQ_HIP_TRY(launch_select_scalar(jd, d_qoi, qoi, d_M, stream));
-        *M = d_M;
+    if (bad < S)
+        return fail(UQ_EUNSTABLE, "sample " + std::to_string(bad) + " holds a non-finite value at step " + std::to_string(t));
+    if (qoi_width(P, qoi) == 1) {
+        UQ_HIP_TRY(launch_select_scalar(jd, b.qoi, qoi, b.M, stream));
+        *M = b.M;
         *n_out = 1;
         *ld = 1;
         return UQ_OK;
     }
-    if (qoi == UQ_QOI_VEL || field1) {
-        st = ensure_fields();
-        if (st != UQ_OK) return st;
-        UQ_HIP_TRY(launch_fields(jd, t, d_fields, stream));
-        *M = qoi == UQ_QOI_VEL ? d_fields : d_fields + (qoi == UQ_QOI_RHO ? 2 : 3) * cells;
-        *n_out = qoi == UQ_QOI_VEL ? 2 * cells : cells;
-        *ld = 4 * cells;
-        return UQ_OK;
-    }
-    return fail(UQ_EINVAL, "unknown QoI");
+    UQ_HIP_TRY(launch_fields(jd, t, b.fields, stream));
+    *M = qoi == UQ_QOI_VEL ? b.fields : b.fields + (qoi == UQ_QOI_RHO ? 2 : 3) * cells;
+    *n_out = qoi_width(P, qoi);
+    *ld = 4 * cells;
+    return UQ_OK;
+}
+
+uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld) {
+    if (qoi_width(p, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
+    StatBufs b;
+    uq_status st = own_stat_bufs(qoi, &b);
+    if (st != UQ_OK) return st;
+    return sample_values_in(b, qoi, M, n_out, ld);
+}
+
+uq_status Job::moments_in(const StatBufs &b, int qoi, uq_moments_out *out) {
+    const double *M;
+    int64_t n, ld;
+    uq_status st = enter();
+    if (st != UQ_OK) return st;
+    st = sample_values_in(b, qoi, &M, &n, &ld);
+    if (st != UQ_OK) return st;
+    double *d_mean = b.out, *d_var = b.out + n, *d_alt = b.out + 2 * n, *d_coef = b.out + 3 * n;
+    if (K > 0)
+        UQ_HIP_TRY(launch_moments_sc(M, S, n, ld, d_wphi, d_a, K, d_coef, d_mean, d_var, d_alt, stream));
+    else
+        UQ_HIP_TRY(launch_moments_mc(M, S, n, ld, d_mean, d_var, d_alt, stream));
+    out->n_out = n;
+    out->K = K;
+    out->d = rule.d;
+    if (out->mean) UQ_HIP_TRY(hipMemcpyAsync(out->mean, d_mean, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    if (out->var) UQ_HIP_TRY(hipMemcpyAsync(out->var, d_var, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    if (out->var_alt) UQ_HIP_TRY(hipMemcpyAsync(out->var_alt, d_alt, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    if (out->coeffs && K > 0)
+        UQ_HIP_TRY(hipMemcpyAsync(out->coeffs, d_coef, sizeof(double) * n * K, hipMemcpyDeviceToHost, stream));
+    UQ_HIP_TRY(hipStreamSynchronize(stream));
+    if (out->alpha && K > 0) std::memcpy(out->alpha, rule.alpha.data(), sizeof(int32_t) * rule.alpha.size());
+    return UQ_OK;
 }
 
 }  // namespace uqi
@@ -443,9 +498,8 @@ uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t 
 extern "C" uq_status uq_qoi_samples(uq_job *j, int32_t qoi, double *out, int64_t *n_out) {
     if (!j) return fail(UQ_EINVAL, "null job");
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
-    const int64_t cells = (int64_t)j->p.nx * j->p.ny;
-    int64_t n = qoi == UQ_QOI_VEL ? 2 * cells : ((qoi == UQ_QOI_RHO || qoi == UQ_QOI_SPEED) ? cells : 1);
-    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_SPEED) return fail(UQ_EINVAL, "unknown QoI");
+    int64_t n = qoi_width(j->p, qoi);
+    if (n == 0) return fail(UQ_EINVAL, "unknown QoI");
     if (n_out) *n_out = n;
     if (!out) return UQ_OK;
     const double *M;
@@ -463,30 +517,11 @@ extern "C" uq_status uq_qoi_samples(uq_job *j, int32_t qoi, double *out, int64_t
 extern "C" uq_status uq_moments(uq_job *j, int32_t qoi, uq_moments_out *out) {
     if (!j || !out) return fail(UQ_EINVAL, "null argument");
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
-    if (qoi < UQ_QOI_KE || qoi > UQ_QOI_SPEED) return fail(UQ_EINVAL, "unknown QoI");
-    const double *M;
-    int64_t n, ld;
-    uq_status st = j->enter();
+    if (qoi_width(j->p, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
+    StatBufs b;
+    uq_status st = j->own_stat_bufs(qoi, &b);
     if (st != UQ_OK) return st;
-    st = j->sample_values(qoi, &M, &n, &ld);
-    if (st != UQ_OK) return st;
-    const int K = j->K;
-    double *d_mean = j->d_out, *d_var = j->d_out + n, *d_alt = j->d_out + 2 * n, *d_coef = j->d_out + 3 * n;
-    if (K > 0)
-        UQ_HIP_TRY(launch_moments_sc(M, j->S, n, ld, j->d_wphi, j->d_a, K, d_coef, d_mean, d_var, d_alt, j->stream));
-    else
-        UQ_HIP_TRY(launch_moments_mc(M, j->S, n, ld, d_mean, d_var, d_alt, j->stream));
-    out->n_out = n;
-    out->K = K;
-    out->d = j->rule.d;
-    if (out->mean) UQ_HIP_TRY(hipMemcpyAsync(out->mean, d_mean, sizeof(double) * n, hipMemcpyDeviceToHost, j->stream));
-    if (out->var) UQ_HIP_TRY(hipMemcpyAsync(out->var, d_var, sizeof(double) * n, hipMemcpyDeviceToHost, j->stream));
-    if (out->var_alt) UQ_HIP_TRY(hipMemcpyAsync(out->var_alt, d_alt, sizeof(double) * n, hipMemcpyDeviceToHost, j->stream));
-    if (out->coeffs && K > 0)
-        UQ_HIP_TRY(hipMemcpyAsync(out->coeffs, d_coef, sizeof(double) * n * K, hipMemcpyDeviceToHost, j->stream));
-    UQ_HIP_TRY(hipStreamSynchronize(j->stream));
-    if (out->alpha && K > 0) std::memcpy(out->alpha, j->rule.alpha.data(), sizeof(int32_t) * j->rule.alpha.size());
-    return UQ_OK;
+    return j->moments_in(b, qoi, out);
 }
 
 extern "C" uq_status uq_populations(uq_job *j, int64_t sample, double *out) {

@@ -169,6 +169,9 @@ void tile_counts(const JobDev &j, int cpt, int *tiles_x, int *tiles_y);
 hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s);
 // per-sample scalar QoIs at time t: out[S][4] = {KE, Fx, Fy, nonfinite}
 hipError_t launch_qoi_scalars(const JobDev &j, int64_t t, double *out, hipStream_t s);
+// out[0] = the first sample s whose scalars above flag a non-finite value,
+// or S if none (one workgroup; overwrites out[0], nothing to clear)
+hipError_t launch_first_bad(const double *qoi, int64_t S, int64_t *out, hipStream_t s);
 // M[s] = KE, C_D or C_L of sample s from the scalars above
 hipError_t launch_select_scalar(const JobDev &j, const double *qoi, int which, double *M, hipStream_t s);
 // per-sample fields at time t: out[S][4][ny][nx] = {ux, uy, rho, |u|}

@@ -18,6 +18,18 @@ StepShape choose_shape(const uq_problem &p, int64_t S);
 // tuned shape for a problem class, if one was measured in this process
 bool tuned_shape(const uq_problem &p, int64_t S, StepShape *out);
 
+// Device buffers of one statistics evaluation (uq_qoi_samples, uq_moments
+// and its allocation-free variant): per-sample scalar QoIs qoi[S][4], the
+// selected scalar M[S], per-sample fields fields[S][4][ny][nx] (field QoIs
+// only, else null), the outputs out[(K + 3) n_out] and one int64 flag.
+struct StatBufs {
+    double *qoi = nullptr, *M = nullptr, *fields = nullptr, *out = nullptr;
+    int64_t *flag = nullptr;
+};
+
+// values per sample of a QoI (1, nx ny or 2 nx ny); 0 for an unknown QoI
+int64_t qoi_width(const uq_problem &p, int qoi);
+
 struct Job {
     uq_problem p{};
     uq_device dev{};
@@ -46,6 +58,7 @@ struct Job {
     int64_t bytes_held = 0;
     double *d_qoi = nullptr, *d_M = nullptr, *d_out = nullptr, *d_fields = nullptr;
     double *d_wphi = nullptr, *d_a = nullptr, *d_export = nullptr;
+    int64_t *d_flag = nullptr;
     int64_t out_cap = 0;
 
     // hipGraph of `graph_len` steps starting at an even step
@@ -60,7 +73,13 @@ struct Job {
     void dfree_all();
     uq_status ensure_stats_buffers(int64_t n_out_max);
     uq_status ensure_fields();
+    // the job's own statistics buffers for `qoi`, allocated on first use
+    uq_status own_stat_bufs(int qoi, StatBufs *b);
+    // per-sample values of `qoi` in b (M: value o of sample s at M[s*ld + o])
+    uq_status sample_values_in(const StatBufs &b, int qoi, const double **M, int64_t *n_out, int64_t *ld);
     uq_status sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld);
+    // statistics of `qoi` computed in b and copied to out (blocking)
+    uq_status moments_in(const StatBufs &b, int qoi, uq_moments_out *out);
     uq_status advance(int64_t steps);
     hipError_t enqueue_steps(int k0, int64_t n);
     int fused_n() const;
