@@ -388,6 +388,14 @@ def study_cylinder_paper(U, W, log, steps=40000, n_mc=1000):
             run(spec, f"resolution_D{D}_{scheme}")
     # the literal reading: peak inflow in Re and in C_D
     run(W.scaled(base, nu=0.06, force_ref="peak", rule=dict(kind="gl", n=1, order=0)), "literal_peak_reading")
+    # sensitivity of the deterministic drag to set-up details the paper
+    # leaves open: the channel height (4.1 D instead of 4 D, circle centred)
+    # and the lattice Mach number (mean inflow 0.03 instead of 0.04, nu and
+    # the step count scaled to keep Re = 20 and the physical time)
+    det = dict(rule=dict(kind="gl", n=1, order=0))
+    run(W.scaled(base, ny=82, cyl_y=40.5, **det), "height_4.1D")
+    run(W.scaled(base, u_peak=0.045, nu=0.03, steps=int(steps * 4 / 3), ramp=int(base["ramp"] * 4 / 3),
+                 dists=[("u_peak", 0.036, 0.054)], **det), "mach_0.75x")
     return out
 
 

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import gpu_available, rel_l2
+from helpers import assert_stats, assert_stats_given_samples, gpu_available, rel_l2
 from paper_2508_13867_amd import Job, Server, UQError
 from paper_2508_13867_amd import _abi as A
 from paper_2508_13867_amd import workloads as W
@@ -79,11 +79,16 @@ def test_drag_lift_moments_match_oracle(variant, prec):
             st = job.moments(q)
             for k in ("mean", "coeffs"):
                 assert rel_l2(st[k], ref["stats"][q][k]) < TOL[prec], (q, k)
-            # variance: sample errors e_j with rms(e) <= tol rms(M) move it by
-            # at most 2 sqrt(var) rms(e) <= tol (mean^2 + 2 var); relative to
-            # var alone that is loose when the QoI barely varies (the lift)
-            m, v = ref["stats"][q]["mean"][0], ref["stats"][q]["var"][0]
-            assert abs(st["var"][0] - v) <= TOL[prec] * (m * m + 2 * v), (q, st["var"][0], v)
+            if prec == "fp64":
+                # mean, var, var_alt and the k >= 1 coefficients (which carry
+                # the variance) each on their own norm
+                assert_stats(st, ref["stats"][q], TOL[prec], q + " " + prec)
+            else:
+                # FP32: the reduction of the device's own samples pinned at
+                # FP64, and the statistics within what the per-sample
+                # errors allow (bounds in the helper)
+                r = dict(ref, samples_q=ref["samples"][q], stats_q=ref["stats"][q])
+                assert_stats_given_samples(st, got, r, TOL[prec], q + " " + prec)
         vel = job.qoi_samples("vel")
         assert rel_l2(vel, ref["samples"]["vel"].reshape(4, -1)) < TOL[prec]
 

@@ -620,3 +620,51 @@ def test_interpolated_cylinder_symmetric_and_drag_converges_in_time():
     assert abs(a["cl"]) < 1e-10 and a["cd"] > 1.0
     assert np.allclose(a["ux"], a["ux"][::-1], rtol=0, atol=1e-13)
     assert np.allclose(a["uy"], -a["uy"][::-1], rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- cylinder drag vs the paper
+
+def _paper_drag_table():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "cylinder_drag_table.txt")):
+        if line.strip() and not line.startswith("#"):
+            name, mean, std = line.split()
+            rows[name] = (float(mean), float(std))
+    return rows
+
+
+def test_cylinder_drag_of_the_papers_setup_pins_force_normalisation_and_reynolds_map():
+    # Table tab:uq_results: deterministic C_D = 5.63208 for the cylinder at
+    # n_x = 20 nodes per diameter (Sec. "Flow past a circular cylinder with
+    # uncertain inlet velocity"). The oracle runs that set-up (22D x 4D
+    # channel, exact circle, interpolated bounce-back, finite-difference
+    # inlet/outlet) at the nominal Reynolds number 20, given as a
+    # Reynolds-number input so that nu comes from the oracle's map
+    # nu = U D/Re, and C_D from its normalisation 2F/(rho0 U^2 D). With U the
+    # mean inflow (reading R29) the drag must land within 3 % of the paper's
+    # (the set-up details the paper leaves open move it by about 2 %); the
+    # literal reading, U the peak of the parabola in both Re and C_D, lands
+    # near 3.2 and must fail the same bar. 20000 steps (steady to 0.2 %);
+    # the two runs go in parallel threads (the oracle releases the GIL).
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2508_13867_amd import workloads as W
+
+    paper_cd = _paper_drag_table()["deterministic"][0]
+    assert paper_cd == 5.63208
+
+    def spec(force_ref):
+        return W.scaled(W.CYLINDER_PAPER_FP32, precision="fp64", steps=20000, nu=0.0, force_ref=force_ref,
+                        dists=[("re", 16.0, 24.0)], rule=dict(kind="gl", n=1, order=0))
+
+    # the map itself: Re = 20 at xi = 0, U = 2/3 of the 0.06 peak, D = 20
+    assert abs(O.sample_params(spec("mean"), [0.0])["nu"] - 0.04) < 1e-15
+    assert abs(O.sample_params(spec("peak"), [0.0])["nu"] - 0.06) < 1e-15
+    with ThreadPoolExecutor(2) as ex:
+        runs = {ref: ex.submit(O.run_problem, spec(ref), None, ["cd", "cl"]) for ref in ("mean", "peak")}
+        res = {ref: f.result()["samples"] for ref, f in runs.items()}
+    cd_mean, cd_peak = float(res["mean"]["cd"][0]), float(res["peak"]["cd"][0])
+    assert abs(cd_mean - paper_cd) / paper_cd < 0.03, cd_mean
+    assert abs(cd_peak - paper_cd) / paper_cd > 0.3, cd_peak
+    # the circle is centred between the walls: no lift
+    assert abs(float(res["mean"]["cl"][0])) < 1e-9 and abs(float(res["peak"]["cl"][0])) < 1e-9
