@@ -130,6 +130,82 @@ def serving(U, W, n_jobs, load, log):
     return out
 
 
+def _replay(U, jobs, arrivals, mode, budget_gb, log, max_jobs=256):
+    """Submit `jobs` at the given arrival times (seconds from the start) to a
+    fresh server and wait for all of them: results and server statistics."""
+    with U.Server(memory_budget_gb=budget_gb, max_jobs=max_jobs, steps_per_tick=96, mode=mode) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for arrival, spec in zip(arrivals, jobs):
+            dt = arrival - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(spec))
+        results = []
+        for k, t in enumerate(tickets):
+            results.append(srv.wait(t, 1800))
+            if (k + 1) % 50 == 0:
+                log(f"bench: serving {mode}: {k + 1} of {len(tickets)} jobs done")
+        st = srv.stats()
+    return results, st
+
+
+def _serving_summary(results, st, arrivals):
+    lat = sorted(r["latency_s"] for r in results)
+    return {"jobs": len(results), "failed": sum(r["status"] != 0 for r in results),
+            "solves_per_hour": round(st["solves_per_hour"], 1), "mlups": round(st["mlups"], 1),
+            "p50_s": round(st["latency_p50_s"], 4), "p99_s": round(st["latency_p99_s"], 4),
+            "mean_latency_s": round(st["latency_mean_s"], 4), "max_latency_s": round(lat[-1], 4),
+            "makespan_s": round(st["elapsed_s"], 3), "last_arrival_s": round(max(arrivals), 3),
+            "arena_peak_gb": round(st["arena_peak_bytes"] / 2 ** 30, 2)}
+
+
+def study_serving(U, W, log, n_jobs=200, max_work=5.0e10, loads=(0.8, 1.5), n_plain=12, budget_gb=200):
+    """The serving mix at full scale (W.serving_mix: 200 seeded jobs, vortex
+    64^2..1024^2, cylinder D 10..40, 1..4 inputs, 5..256 collocation nodes
+    or 256..4096 Monte Carlo samples, FP32, at most max_work node updates per
+    job). (1) Batched capacity: every job submitted at once. (2) Poisson
+    arrivals at 0.8x and 1.5x that capacity: latency percentiles, solves per
+    hour, aggregate MLUPS. (3) Plain mode (one job at a time, one sample per
+    launch, no graph) against batched on the same subset of jobs submitted at
+    once, with their results compared bit for bit."""
+    jobs = W.serving_mix(n_jobs, max_work=max_work)
+    work = sum(j["work"] for j in jobs)
+    out = {"jobs": n_jobs, "max_work_per_job": max_work, "trace_seed": W.SEED, "work_node_updates": work,
+           "budget_gb": budget_gb}
+    log(f"bench: serving mix of {n_jobs} jobs, {work:.3g} node updates: capacity run")
+    res, st = _replay(U, jobs, [0.0] * n_jobs, "batched", budget_gb, log)
+    cap = work / st["elapsed_s"]
+    out["capacity"] = dict(_serving_summary(res, st, [0.0]), node_updates_per_s=cap)
+    log(f"bench: capacity {out['capacity']}")
+    ref = {j["name"]: (r["mean"], r["var"]) for j, r in zip(jobs, res)}
+    for load in loads:
+        arr = W.poisson_arrivals(jobs, cap, load)
+        res, st = _replay(U, jobs, arr, "batched", budget_gb, log)
+        out[f"load_{load}"] = _serving_summary(res, st, arr)
+        # a job's result does not depend on what ran beside it
+        out[f"load_{load}"]["bitwise_same_as_capacity_run"] = all(
+            (r["mean"], r["var"]) == ref[j["name"]] for j, r in zip(jobs, res))
+        log(f"bench: load {load}: {out[f'load_{load}']}")
+    # plain vs batched on the first jobs whose one-sample-per-launch run is
+    # short (launch-bound: about 5 us per launch, or the lattice's bytes at
+    # 5 TB/s)
+    est = [j["work"] / (j["nx"] * j["ny"]) * max(5e-6, j["nx"] * j["ny"] * 36 / 5e12) for j in jobs]
+    sub = [j for j, e in zip(jobs, est) if e < 6.0][:n_plain]
+    sw = sum(j["work"] for j in sub)
+    out["plain_subset"] = {"jobs": [j["name"] for j in sub], "work_node_updates": sw}
+    pres = {}
+    for mode in ("plain", "batched"):
+        log(f"bench: subset of {len(sub)} jobs, {mode}")
+        res, st = _replay(U, sub, [0.0] * len(sub), mode, budget_gb, log)
+        out["plain_subset"][mode] = _serving_summary(res, st, [0.0])
+        pres[mode] = [(r["mean"], r["var"]) for r in res]
+    out["plain_subset"]["bitwise_batched_equals_plain"] = pres["plain"] == pres["batched"]
+    out["plain_subset"]["speedup_solves_per_hour"] = round(
+        out["plain_subset"]["batched"]["solves_per_hour"] / out["plain_subset"]["plain"]["solves_per_hour"], 2)
+    return out
+
+
 def study_precision(U, W, log, oracle_samples=8):
     """Monte Carlo workload (128^2 vortex, 4-D inputs, 4096 samples, 2000
     steps) in FP64, FP32, FP16- and BF16-storage: throughput and roofline per
@@ -452,7 +528,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the copy-bandwidth probe")
     ap.add_argument("--tune-steps", type=int, default=40, help="steps per candidate of the launch-shape tuner")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-trace comparison")
-    ap.add_argument("--study", choices=["precision", "cylinder", "samplers", "wasserstein", "cylinder_paper"], default=None,
+    ap.add_argument("--study", choices=["precision", "cylinder", "samplers", "wasserstein", "cylinder_paper", "serving"],
+                    default=None,
                     help="run a measurement study instead of the benchmark and print its JSON")
     ap.add_argument("--study-precision", default="fp32", choices=["fp64", "fp32"],
                     help="storage precision of the wasserstein study")
@@ -502,6 +579,9 @@ def main():
         return
     if args.study == "cylinder_paper":
         print(json.dumps(study_cylinder_paper(U, W, log)), flush=True)
+        return
+    if args.study == "serving":
+        print(json.dumps(study_serving(U, W, log)), flush=True)
         return
     if args.study == "wasserstein":
         print(json.dumps(study_wasserstein(U, W, log, prec=args.study_precision)), flush=True)

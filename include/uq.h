@@ -415,19 +415,30 @@ uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, 
  * come, first served while their device footprint fits in the server's
  * memory arena (allocated once at creation; serving itself never calls
  * hipMalloc/hipFree) and fewer than max_jobs are live. In BATCHED mode every
- * sample of every live job advances in one fused launch per step (jobs of
- * different lattices, geometries, sample counts and step parities share the
- * launch; AA layout), in hipGraph replays of steps_per_tick steps while the
- * job set is unchanged. PLAIN mode runs one job at a time and one sample per
- * launch per step, with no graph: the same kernels and arithmetic, for
- * comparison. All jobs of a server share its precision. Results are one
- * scalar QoI per job (KE, CD or CL): its statistics as in uq_moments. */
+ * sample of every live job advances together, in ticks of a multiple of 48
+ * steps (steps_per_tick rounded to the nearest, at least 48) replayed from
+ * one captured hipGraph while the live set is unchanged: periodic vortex
+ * lattices and channels with half-way walls, cylinder and Zou-He, wall or
+ * periodic ends in single-precision storage run in the AB layout, N steps
+ * per launch over whole rows (N from the launch-shape tuner's measurement of
+ * the job's class when it has one, else the largest that fits: vortex 8, 6
+ * or 4, channel 4, 3 or 2), one launch for all jobs that share a kernel
+ * instance; the other jobs (FP64, rows too wide) run in the AA layout, one
+ * launch per step for all of them. Jobs of different lattices, geometries,
+ * sample counts and step parities share launches. A job with fewer steps
+ * left than a tick takes its last steps in launches of its own. PLAIN mode
+ * runs one job at a time and one sample per launch per step (AA), with no
+ * graph. Fused and single steps give bit for bit the same populations, so a
+ * job's result is the same in either mode, alone or in any mix. All jobs of
+ * a server share its precision. Results are one scalar QoI per job (KE, CD
+ * or CL): its statistics as in uq_moments. */
 typedef enum { UQ_SERVE_BATCHED = 0, UQ_SERVE_PLAIN = 1 } uq_serve_mode;
 
 typedef struct {
     int64_t memory_budget;  /* bytes of device memory for resident jobs        */
     int32_t max_jobs;       /* live jobs at once (1..4096)                     */
-    int32_t steps_per_tick; /* steps between admission checks (even, >= 2)     */
+    int32_t steps_per_tick; /* steps between admission checks (>= 2; BATCHED:
+                               rounded to a multiple of 48)                   */
     int32_t mode;           /* uq_serve_mode                                   */
     int32_t use_graph;      /* capture each tick of the batched mode           */
     int32_t precision;      /* uq_precision of every job                       */
@@ -460,8 +471,17 @@ typedef struct {
 
 typedef struct uq_server uq_server;
 
-/* Start a server on `device` (its arena is allocated here). */
-uq_status uq_server_create(const uq_server_config *cfg, int32_t device, uq_server **out);
+/* Start a server on dev->device (dev may be NULL: device 0, hipMalloc,
+ * the null stream). Its arena of cfg->memory_budget bytes is allocated here,
+ * through dev->alloc when the caller gives allocator callbacks (e.g. torch's
+ * caching allocator, as the job API does) and else with hipMalloc; it holds
+ * every resident job and the batching tables, and goes back through
+ * dev->free at uq_server_destroy. dev->stream orders the server against the
+ * caller: the loop's first work waits for what the caller had queued on it
+ * (the arena's allocation), and uq_server_destroy makes it wait for the
+ * loop's last work before the arena is freed. The loop itself runs on a
+ * stream of its own. */
+uq_status uq_server_create(const uq_server_config *cfg, const uq_device *dev, uq_server **out);
 /* Queue a job; never blocks. UQ_ENOMEM if it can never fit the arena. The
  * problem is copied. *ticket identifies the result. */
 uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t steps, int32_t qoi, uint64_t *ticket);

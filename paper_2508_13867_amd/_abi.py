@@ -123,7 +123,7 @@ SIGNATURES = {
     "uq_destroy": (None, [_P]),
     "uq_last_error": (C.c_char_p, []),
     "uq_autotune": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.c_int64, C.POINTER(TuneResult)]),
-    "uq_server_create": (C.c_int, [C.POINTER(ServerConfig), C.c_int32, C.POINTER(_P)]),
+    "uq_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(Device), C.POINTER(_P)]),
     "uq_server_submit": (C.c_int, [_P, C.POINTER(Problem), C.c_int64, C.c_int32, C.POINTER(C.c_uint64)]),
     "uq_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Result)]),
     "uq_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(Result)]),
@@ -386,7 +386,11 @@ class Server:
     """A continuous-batching UQ server (uq_server_*) on one GPU."""
 
     def __init__(self, memory_budget_gb: float = 16.0, max_jobs: int = 64, steps_per_tick: int = 64,
-                 mode: str = "batched", use_graph: bool = True, precision: str = "fp32", device: int = 0):
+                 mode: str = "batched", use_graph: bool = True, precision: str = "fp32", device: int = 0,
+                 stream=None, torch_memory: bool = True):
+        # the arena comes from torch's caching allocator (or hipMalloc), and
+        # torch's current stream orders the server against the caller
+        self._dev, self._keep = torch_device(device, stream, torch_memory)
         cfg = ServerConfig()
         cfg.memory_budget = int(memory_budget_gb * (1 << 30))
         cfg.max_jobs = max_jobs
@@ -395,7 +399,7 @@ class Server:
         cfg.use_graph = 1 if use_graph else 0
         cfg.precision = PRECISION[precision]
         h = C.c_void_p()
-        check(lib().uq_server_create(C.byref(cfg), device, C.byref(h)))
+        check(lib().uq_server_create(C.byref(cfg), C.byref(self._dev), C.byref(h)))
         self.h = h
 
     def submit(self, spec: dict, steps: int | None = None, qoi: str | None = None) -> int:

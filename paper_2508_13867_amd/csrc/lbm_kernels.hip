@@ -1102,27 +1102,36 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
 // The sliding window over whole rows: K waves per time level, M columns per
 // lane, cover the nx <= 64 K M columns of a row, so on a periodic lattice no
 // column is computed twice (only a chunk's row halo is). Each LDS row holds
-// one direction of the nx columns at 1..nx, already shifted by the
+// one direction of the nx columns at 0..nx-1, already shifted by the
 // direction's c_x (periodic wrap included), so that every pull from the row
 // below reads the lane's own column. N K waves in one workgroup, one barrier
 // per row.
+// LDS rings of the level below, by the row a direction group pulls from:
+// c_y = -1 (row y + 1, slots 0-1) and c_y = 0 (row y, slots 2-3): 2 rows;
+// c_y = +1 (row y - 1, slots 4-6): 3 rows. Row r sits in slot (r + 12)
+// mod 2 or mod 3 of its group. A row holds 64 K M values (no padding:
+// the shifted writes wrap inside the row), so the three rows of a slot, and
+// the same slot of the first two groups, lie a multiple of 64 words apart:
+// the compiler pairs those accesses into ds_read2st64 / ds_write2st64.
+template <int P, int N, int K, int M>
+struct RowsRing {
+    static constexpr int NR = N > 1 ? N - 1 : 1;
+    static constexpr int CW = 64 * K * M;
+    using Array = typename Prec<P>::C[NR][7][3][CW];
+};
+
+// One work item of the full-row pipeline: rows [chunk H, chunk H + H) of
+// sample smp (with the halo rows the levels need), N steps, from the slab
+// src2 names to the other one. Every wave of the workgroup passes the same
+// number of barriers, the last one after the item's final row step, so the
+// rings may be reused by the next item at once.
 template <int P, int N, int K, int M, int D>
-__global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H, int chunks, int64_t nwork,
-                                                      bool nt) {
+__device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, int64_t smp, int chunk, bool nt,
+                                           typename RowsRing<P, N, K, M>::Array &rg) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int RG = N - 1;
-    constexpr int NR = N > 1 ? N - 1 : 1;
-    // LDS rings of the level below, by the row a direction group pulls from:
-    // c_y = -1 (row y + 1, slots 0-1) and c_y = 0 (row y, slots 2-3): 2 rows;
-    // c_y = +1 (row y - 1, slots 4-6): 3 rows. Row r sits in slot (r + 12)
-    // mod 2 or mod 3 of its group. Rows are padded to a multiple of 64
-    // values, so that the three rows of a slot, and the same slot of the first
-    // two groups, lie a multiple of 64 words apart: the compiler pairs those
-    // accesses into ds_read2st64 / ds_write2st64.
-    constexpr int CW = 64 * K * M + 64;
-    __shared__ C rg[NR][7][3][CW];
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -1143,17 +1152,14 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
         vo0[m] = c[m] * (int)sizeof(T);
         vom[m] = (c[m] == 0 ? nx - 1 : c[m] - 1) * (int)sizeof(T);
         vop[m] = (c[m] == nx - 1 ? 0 : c[m] + 1) * (int)sizeof(T);
-        wp[m] = (c[m] == nx - 1 ? 0 : c[m] + 1) + 1;  // LDS columns of the c_x = +1 and -1 pushes
-        wm[m] = (c[m] == 0 ? nx - 1 : c[m] - 1) + 1;
+        wp[m] = c[m] == nx - 1 ? 0 : c[m] + 1;  // LDS columns of the c_x = +1 and -1 pushes
+        wm[m] = c[m] == 0 ? nx - 1 : c[m] - 1;
     }
     const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
-    const int64_t G = gridDim.x;
     constexpr int B = D + 1;
     using R = typename BufLd<P>::R;
     R buf[B][M][9];
-    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const int64_t smp = wk / chunks;
-        const int chunk = (int)(wk - smp * chunks);
+    {
         const int yb = chunk * H, ye = min(ny, yb + H);
         const T *src = src_all + smp * 9 * (int64_t)plane;
         T *dst = dst_all + smp * 9 * (int64_t)plane;
@@ -1175,13 +1181,13 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                 }
         };
         // a level hands direction i of its column c on to LDS column
-        // ((c + c_ix) mod nx) + 1, where the level above pulls it: every pull
+        // (c + c_ix) mod nx, where the level above pulls it: every pull
         // then reads the puller's own column, and the periodic wrap costs no
         // extra copies
         // (the c_y = -1 and c_y = 0 groups use slots of the same index, two
         // apart: their writes of equal c_x go in pairs, ds_write2st64)
         auto put = [&](int L, int y, int m, const C *v) {
-            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3, x = c[m] + 1;
+            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3, x = c[m];
             rg[L][sa][0][x] = v[4];
             rg[L][2 + sa][0][x] = v[0];
             rg[L][sa][1][wm[m]] = v[7];
@@ -1262,7 +1268,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         if (CYd[i] < 0) continue;
-                        const int g = GJd[i], x = c[m] + 1;
+                        const int g = GJd[i], x = c[m];
                         q[m][n++] = CYd[i] == 0 ? rg[L][2 + sb][g][x] : rg[L][4 + sc3][g][x];
                     }
                 }
@@ -1288,7 +1294,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
                         C (*q)[6] = pre[k ^ 1];
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
-                            const int x = c[m] + 1;  // the lane's LDS column
+                            const int x = c[m];  // the lane's LDS column
                             f[m][4] = rg[L][sa][0][x];       // (0, -1)
                             f[m][7] = rg[L][sa][1][x];       // (-1, -1)
                             f[m][8] = rg[L][sa][2][x];       // (1, -1)
@@ -1315,6 +1321,46 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
     }
 }
 
+template <int P, int N, int K, int M, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H, int chunks, int64_t nwork,
+                                                      bool nt) {
+    __shared__ typename RowsRing<P, N, K, M>::Array rg;
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / chunks;
+        stepR_item<P, N, K, M, D>(j, src2, H, smp, (int)(wk - smp * chunks), nt, rg);
+    }
+}
+
+// Job of work item wk in a batched table (work0 ascending, job 0 at 0).
+__device__ inline int fused_job_of(const FusedJob *jobs, int njobs, int64_t wk) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].work0 <= wk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched form: every chunk of every sample of every job in the table, N
+// steps per launch; launch number `launch` of a tick reads the slab of
+// parity par ^ (launch & 1) of its job (the state of step t + launch N;
+// even N go in pairs, as in the single-job schedule).
+template <int P, int N, int K, int M, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepR_multi(const FusedJob *jobs, int njobs, int64_t nwork,
+                                                            int launch, bool nt) {
+    __shared__ typename RowsRing<P, N, K, M>::Array rg;
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const JobDev j = q.j;
+        const int64_t local = wk - q.work0;
+        const int64_t smp = local / q.chunks;
+        stepR_item<P, N, K, M, D>(j, ((q.par ^ launch) & 1) != 0, q.H, smp, (int)(local - smp * q.chunks), nt, rg);
+    }
+}
+
 // ------------------------------------------------------------------ fused channel steps, full rows
 // The full-row pipeline on the channel with half-way bounce-back walls and
 // cylinder and Zou-He inlet / outlet (no interpolated rules): the same wall
@@ -1326,22 +1372,29 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR(JobDev j, bool src2, int H
 // along x the end columns are open, walls or periodic, as the node masks
 // say. Solid nodes are skipped.
 // Level L of a launch computes step t0 + L - 1 (the inflow ramp).
+// one LDS array for the three rings (c_y = -1: slots 0-2, c_y = 0: 3-5,
+// c_y = +1: 6-9), rows padded to a multiple of 64 values: the rows of a
+// slot, and the slots of equal index of the first two groups, lie 64-word
+// multiples apart, and the compiler pairs those accesses (ds_read2st64 /
+// ds_write2st64)
+template <int P, int N, int K, int M>
+struct RowsRingCh {
+    static constexpr int NR = N > 1 ? N - 1 : 1;
+    static constexpr int CW = 64 * K * M + 64;
+    using Array = typename Prec<P>::C[NR][10][3][CW];
+};
+
+// One work item of the channel pipeline: rows [chunk H, chunk H + H) of
+// sample smp, steps t0 .. t0 + N - 1 (t0 = *d_t + k0), from the slab src2
+// names to the other one; ends with a barrier, like stepR_item.
 template <int P, int N, int K, int M, int D>
-__global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *d_t, int k0, bool src2, int H,
-                                                       int chunks, int64_t nwork) {
+__device__ __forceinline__ void stepRC_item(const JobDev &j, const int64_t *d_t, int k0, bool src2, int H,
+                                            int64_t smp, int chunk, typename RowsRingCh<P, N, K, M>::Array &rq) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int RG = N - 1;
-    constexpr int NR = N > 1 ? N - 1 : 1;
-    // one LDS array for the three rings (c_y = -1: slots 0-2, c_y = 0: 3-5,
-    // c_y = +1: 6-9), rows padded to a multiple of 64 values: the rows of a
-    // slot, and the slots of equal index of the first two groups, lie 64-word
-    // multiples apart, and the compiler pairs those accesses (ds_read2st64 /
-    // ds_write2st64)
-    constexpr int CW = 64 * K * M + 64;
     constexpr uint32_t BB_BITS = 0x1FFu << M_BB, OPEN_BITS = 0x1FFu << M_OPEN;
-    __shared__ C rq[NR][10][3][CW];
     const int64_t t0 = *d_t + k0;
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
@@ -1367,14 +1420,11 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *
     }
     const __amdgpu_buffer_rsrc_t mrsrc = make_rsrc(j.mask, ny * (int)j.pitch * 4);
     const int span = RG - (lvl - 1);
-    const int64_t G = gridDim.x;
     constexpr int B = D + 1;
     using R = typename BufLd<P>::R;
     R buf[B][M][9];
     uint32_t mb[B][M];
-    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const int64_t smp = wk / chunks;
-        const int chunk = (int)(wk - smp * chunks);
+    {
         const int yb = chunk * H, ye = min(ny, yb + H);
         const int lo = max(0, yb - span), hi = min(ny, ye + span);  // this level's rows
         const T *src = src_all + smp * 9 * (int64_t)plane;
@@ -1519,6 +1569,34 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *
                 __syncthreads();
             }
         }
+    }
+}
+
+template <int P, int N, int K, int M, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepRC(JobDev j, const int64_t *d_t, int k0, bool src2, int H,
+                                                       int chunks, int64_t nwork) {
+    __shared__ typename RowsRingCh<P, N, K, M>::Array rq;
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / chunks;
+        stepRC_item<P, N, K, M, D>(j, d_t, k0, src2, H, smp, (int)(wk - smp * chunks), rq);
+    }
+}
+
+// Batched form (see k_stepR_multi); launch number `launch` of a tick runs
+// steps t + launch N .. of each job, t its step count at the tick's start.
+template <int P, int N, int K, int M, int D>
+__global__ __launch_bounds__(64 * N * K) void k_stepRC_multi(const FusedJob *jobs, int njobs, int64_t nwork,
+                                                             int launch) {
+    __shared__ typename RowsRingCh<P, N, K, M>::Array rq;
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const JobDev j = q.j;
+        const int64_t local = wk - q.work0;
+        const int64_t smp = local / q.chunks;
+        stepRC_item<P, N, K, M, D>(j, q.d_t, launch * N, ((q.par ^ launch) & 1) != 0, q.H, smp,
+                                   (int)(local - smp * q.chunks), rq);
     }
 }
 
@@ -2122,20 +2200,24 @@ static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
 // (M = 1, else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
 static constexpr int RING_ROWS_TGV = 21, RING_ROWS_CH = 30;
 
-// Registers: a lane colliding two columns needs about 165 VGPRs in single
-// precision (twice as many in double), so such shapes keep to 12 waves (3 per
-// SIMD, 168 VGPRs each; FP64: 8 waves, 256); one column per lane fits 128
-// (FP64: 168), the budget of 16 waves, in single precision only.
-static constexpr bool rows_regs_fit(int prec, int waves, int M) {
-    return prec == UQ_FP64 ? waves <= (M == 2 ? 8 : 12) : (M == 2 ? waves <= 12 : true);
+// Registers: in single precision a lane of the periodic kernel colliding two
+// columns fits 128 VGPRs (4 waves per SIMD: up to 16 waves), the channel
+// kernel's about 165 (12 waves, 3 per SIMD); in double precision two columns
+// keep to 8 waves (256 VGPRs) and one column to 12 (168). One column per
+// lane fits 128 in single precision. (__launch_bounds__ holds the compiler to
+// the budget of the workgroup size, so these limits only keep out shapes
+// that would spill.)
+static constexpr bool rows_regs_fit(int prec, int waves, int M, bool channel) {
+    return prec == UQ_FP64 ? waves <= (M == 2 ? 8 : 12) : (M == 2 && channel ? waves <= 12 : true);
 }
 
-// values per LDS row: padded to a multiple of 64 (the columns, two end
-// columns on the channel, and the padding)
-static constexpr int ring_cols(int, int K, int M) { return 64 * K * M + 64; }
+// values per LDS row: the periodic kernel's rows hold its 64 K M columns
+// (shifted writes wrap inside the row); the channel's also two end columns,
+// padded to a multiple of 64
+static constexpr int ring_cols(int rows, int K, int M) { return 64 * K * M + (rows == RING_ROWS_CH ? 64 : 0); }
 
 static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
-    return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M) &&
+    return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M, rows == RING_ROWS_CH) &&
            (int64_t)(n - 1) * rows * ring_cols(rows, K, M) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
 }
 
@@ -2204,6 +2286,89 @@ static void stepRC_p(const JobDev &j, const int64_t *d_t, int k, bool src2, int 
     UQ_ROWS_CASES(UQ_ROWS_CASE)
 #undef UQ_ROWS_CASE
 }
+
+// ------------------------------------------------------------------ batched fused launches
+// One launch of a batched full-row instance (kind 0: periodic, k_stepR_multi;
+// kind 1: channel, k_stepRC_multi): every work item of the table's jobs. The
+// server keeps to N in {4, 6, 8} (periodic) and {2, 3, 4} (channel) and to
+// single precision storage (FP32, FP16S, BF16S), so that a tick of 48 steps
+// holds a whole number of launch pairs of every instance.
+int rows_instance(int kind, int prec, int n, int nx, int *K, int *M) {
+    return rows_shape(prec, n, kind == 0 ? RING_ROWS_TGV : RING_ROWS_CH, nx, K, M);
+}
+
+template <int P, int N, int K, int M>
+static void multi_k(int kind, const FusedJob *jobs, int njobs, int64_t nwork, int launch, hipStream_t s) {
+    const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
+    if (kind == 0) {
+        if constexpr (rows_fit(P, N, RING_ROWS_TGV, K, M))
+            k_stepR_multi<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(jobs, njobs, nwork, launch, false);
+    } else {
+        if constexpr (N <= 4 && rows_fit(P, N, RING_ROWS_CH, K, M))
+            k_stepRC_multi<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(jobs, njobs, nwork, launch);
+    }
+}
+
+template <int P, int N>
+static bool multi_n(int kind, int K, int M, const FusedJob *jobs, int njobs, int64_t nwork, int launch,
+                    hipStream_t s) {
+#define UQ_MULTI_CASE(kk, mm)                                         \
+    if (K == kk && M == mm) {                                         \
+        multi_k<P, N, kk, mm>(kind, jobs, njobs, nwork, launch, s);   \
+        return true;                                                  \
+    }
+    UQ_ROWS_CASES(UQ_MULTI_CASE)
+#undef UQ_MULTI_CASE
+    return false;
+}
+
+template <int P>
+static bool multi_p(int kind, int n, int K, int M, const FusedJob *jobs, int njobs, int64_t nwork, int launch,
+                    hipStream_t s) {
+    if (kind == 0) {
+        if (n == 4) return multi_n<P, 4>(0, K, M, jobs, njobs, nwork, launch, s);
+        if (n == 6) return multi_n<P, 6>(0, K, M, jobs, njobs, nwork, launch, s);
+        if (n == 8) return multi_n<P, 8>(0, K, M, jobs, njobs, nwork, launch, s);
+        return false;
+    }
+    if (n == 2) return multi_n<P, 2>(1, K, M, jobs, njobs, nwork, launch, s);
+    if (n == 3) return multi_n<P, 3>(1, K, M, jobs, njobs, nwork, launch, s);
+    if (n == 4) return multi_n<P, 4>(1, K, M, jobs, njobs, nwork, launch, s);
+    return false;
+}
+
+bool fused_multi_supported(int kind, int prec, int n, int K, int M) {
+    if (prec == UQ_FP64) return false;
+    if (kind == 0 ? (n != 4 && n != 6 && n != 8) : (n < 2 || n > 4)) return false;
+    return rows_fit(prec, n, kind == 0 ? RING_ROWS_TGV : RING_ROWS_CH, K, M);
+}
+
+hipError_t launch_fused_multi(int kind, int prec, int n, int K, int M, const FusedJob *jobs, int njobs,
+                              int64_t nwork, int launch, hipStream_t s) {
+    if (njobs <= 0 || nwork <= 0) return hipSuccess;
+    if (!fused_multi_supported(kind, prec, n, K, M)) return hipErrorInvalidValue;
+    bool ok = false;
+    switch (prec) {
+        case UQ_FP32: ok = multi_p<UQ_FP32>(kind, n, K, M, jobs, njobs, nwork, launch, s); break;
+        case UQ_FP16S: ok = multi_p<UQ_FP16S>(kind, n, K, M, jobs, njobs, nwork, launch, s); break;
+        default: ok = multi_p<UQ_BF16S>(kind, n, K, M, jobs, njobs, nwork, launch, s); break;
+    }
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// *d_t[q] += n for every job of a table (one thread per job)
+__global__ void k_advance_ptrs(int64_t *const *d_t, int njobs, int64_t n) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < njobs) *d_t[q] += n;
+}
+
+hipError_t launch_advance_ptrs(int64_t *const *d_t, int njobs, int64_t n, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_advance_ptrs<<<(unsigned)((njobs + 63) / 64), 64, 0, s>>>(d_t, njobs, n);
+    return hipGetLastError();
+}
+
 #undef UQ_ROWS_CASES
 
 template <int P>

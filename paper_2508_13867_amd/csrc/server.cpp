@@ -1,10 +1,14 @@
 // Continuous-batching UQ server: a request loop on its own host thread that
 // admits jobs of different lattices and sample counts by device-memory
 // footprint, keeps their populations resident, and advances every sample of
-// every live job in one fused launch per step (the non-intrusive UQ algorithm
-// of OpenLB-UQ, Algorithm alg:uq_openlb, with the per-sample solve loop of
-// all concurrent requests batched). A "plain" mode runs the same kernels one
-// job at a time and one sample per launch, for comparison.
+// every live job together (the non-intrusive UQ algorithm of OpenLB-UQ,
+// Algorithm alg:uq_openlb, with the per-sample solve loop of all concurrent
+// requests batched). Periodic vortex lattices and channels with node-local
+// boundary rules run temporally blocked: N steps per launch over whole rows,
+// one batched launch per kernel instance for all jobs that share it; other
+// jobs advance one step per launch in one batched launch per step. A "plain"
+// mode runs the same arithmetic one job at a time and one sample per launch,
+// for comparison.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,9 +18,11 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "uq_job.h"
@@ -29,18 +35,28 @@ namespace uqi {
 // calls hipMalloc or hipFree (hipFree would synchronise the device).
 class Arena {
    public:
-    uq_status init(size_t bytes) {
+    // from the caller's allocator if it has one, else hipMalloc
+    uq_status init(size_t bytes, const uq_device &dev) {
         cap_ = (bytes + 255) / 256 * 256;
-        if (hipMalloc(&base_, cap_) != hipSuccess) {
+        dev_ = dev;
+        if (dev_.alloc) {
+            base_ = (char *)dev_.alloc(cap_, dev_.ctx);
+        } else if (hipMalloc(&base_, cap_) != hipSuccess) {
             (void)hipGetLastError();
             base_ = nullptr;
-            return fail(UQ_ENOMEM, "server arena of " + std::to_string(cap_) + " B does not fit on the device");
         }
+        if (!base_) return fail(UQ_ENOMEM, "server arena of " + std::to_string(cap_) + " B does not fit on the device");
         free_[0] = cap_;
         return UQ_OK;
     }
+    // (the caller makes sure no work on the arena is pending)
     ~Arena() {
-        if (base_) (void)hipFree(base_);
+        if (!base_) return;
+        if (dev_.alloc) {
+            if (dev_.free) dev_.free(base_, dev_.ctx);
+        } else {
+            (void)hipFree(base_);
+        }
     }
     void *alloc(size_t n) {
         std::lock_guard<std::mutex> lk(mu_);
@@ -98,6 +114,7 @@ class Arena {
 
    private:
     char *base_ = nullptr;
+    uq_device dev_{};
     size_t cap_ = 0, in_use_ = 0, peak_ = 0;
     std::map<size_t, size_t> free_, used_;
     std::mutex mu_;
@@ -108,13 +125,63 @@ static void arena_free_cb(void *p, void *ctx) { ((Arena *)ctx)->release(p); }
 
 static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 
-// Device bytes a job takes in the server (AA layout, scalar moments): slab,
-// per-sample records, step counter, boundary mask, basis table, QoI buffers
-// and the non-finite flag.
-int64_t job_footprint(const uq_problem &p, int64_t S, int K) {
+// The batched instance that carries a job: periodic vortex lattices (kind
+// 0) and channels whose boundary rules are node-local (kind 1: half-way
+// walls and cylinder, Zou-He or wall or periodic ends) advance N steps per
+// launch over whole rows of H-row chunks in the AB layout; kind -1: one step
+// per launch in the AA layout (the batched single-step kernel). A shape the
+// launch-shape tuner measured for the job's class is taken when it is a
+// batched instance; otherwise N is the largest of the instance's choices
+// whose LDS rings fit the row width (vortex 8, 6, 4; channel 4, 3, 2), the
+// vortex takes chunks of 256 rows, and the channel cuts its rows into
+// chunks so that its samples fill the GPU (at most 8, as the tuner tries).
+struct ServeShape {
+    int kind = -1, N = 0, K = 0, M = 0, H = 0;
+};
+
+static ServeShape serve_shape(const uq_problem &p, int64_t S) {
+    ServeShape sh;
+    if (p.precision == UQ_FP64) return sh;
+    const int64_t b = storage_bytes(p.precision);
+    const int64_t plane = (int64_t)p.ny * row_pitch(p.nx) + 64;
+    if (9 * plane * b >= ((int64_t)1 << 31) || plane * 4 >= ((int64_t)1 << 31)) return sh;
+    int kind = -1;
+    if (p.geometry == UQ_GEOM_TGV) kind = 0;
+    else if (p.geometry == UQ_GEOM_CHANNEL && !needs_ab(p) && p.cyl_bc == UQ_CYL_HALFWAY) kind = 1;
+    if (kind < 0) return sh;
+    const int pref[2][3] = {{8, 6, 4}, {4, 3, 2}};
+    StepShape tuned;
+    const bool have = tuned_shape(p, S, &tuned) && tuned.fwin == 2 && tuned.fuse >= 2;
+    for (int c = -1; c < 3; ++c) {
+        const int n = c < 0 ? (have ? tuned.fuse : 0) : pref[kind][c];
+        int K = 0, M = 0;
+        if (n < 2 || !rows_instance(kind, p.precision, n, p.nx, &K, &M) ||
+            !fused_multi_supported(kind, p.precision, n, K, M))
+            continue;
+        sh.kind = kind;
+        sh.N = n;
+        sh.K = K;
+        sh.M = M;
+        if (c < 0) {
+            sh.H = std::max(8, std::min(tuned.fty, p.ny));
+        } else if (kind == 0) {
+            sh.H = std::max(8, std::min(256, p.ny));
+        } else {
+            const int chunks = (int)std::min<int64_t>(8, std::max<int64_t>(1, (256 + S - 1) / S));
+            sh.H = std::max(8, (p.ny + chunks - 1) / chunks);
+        }
+        return sh;
+    }
+    return sh;
+}
+
+// Device bytes a job takes in the server (scalar moments): slab (two in the
+// AB layout), per-sample records, step counter, boundary mask, basis table,
+// QoI buffers and the non-finite flag.
+int64_t job_footprint(const uq_problem &p, int64_t S, int K, bool ab) {
     const int64_t pitch = row_pitch(p.nx);
     const int64_t plane = (int64_t)p.ny * pitch + 64;
-    size_t b = up256((size_t)(S * 9 * plane * storage_bytes(p.precision)));
+    size_t b = up256((size_t)(S * 9 * plane * storage_bytes(p.precision))) * (ab ? 2 : 1);
     b += up256(sizeof(SampleDev) * S) + 256;
     if (p.geometry == UQ_GEOM_CHANNEL) b += up256(sizeof(uint32_t) * p.ny * pitch);
     if (K > 0) b += up256(sizeof(double) * S * K) + up256(sizeof(double) * S);
@@ -129,6 +196,7 @@ struct Request {
     int32_t qoi = 0;
     int64_t S = 0;
     int K = 0;
+    ServeShape shape;  // kind -1 in PLAIN mode
     int64_t footprint = 0;
     double t_submit = 0.0;
 };
@@ -140,11 +208,30 @@ struct Live {
     int tiles_x = 0, tiles_y = 0;
 };
 
+// Jobs of the live set that share one batched instance; their table entries
+// are fused[first .. first + count).
+struct Group {
+    int kind = 0, N = 0, K = 0, M = 0;
+    int first = 0, count = 0;
+    int64_t nwork = 0;
+};
+
+// Steps per tick of the batched mode: a multiple of 48, which holds a whole
+// number of launch pairs of every instance (2N divides 48 for N = 2, 3, 4,
+// 6, 8), so that every job's state is in the slab of its step's parity
+// between ticks and one captured graph serves every tick while the live set
+// is unchanged.
+static int64_t batched_tick(int64_t steps_per_tick) {
+    return std::max<int64_t>(48, (steps_per_tick + 24) / 48 * 48);
+}
+
 struct Server {
     uq_server_config cfg{};
+    uq_device dev{};
     int device = 0;
     Arena arena;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the loop's stream
+    hipEvent_t ev = nullptr;
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -162,9 +249,16 @@ struct Server {
     double node_updates = 0.0, busy_s = 0.0;
     std::vector<double> latencies;
 
-    // continuous-batching table
+    // batching tables of the live set (device copies in d_tables, one block
+    // the size of max_jobs entries of each kind): single-step jobs, the
+    // batched fused instances, and every job's step counter
+    void *d_tables = nullptr;
     MultiJob *d_table = nullptr;
+    FusedJob *d_fused = nullptr;
+    int64_t **d_tptrs = nullptr;
     int table_cap = 0;
+    int n_single = 0, n_fused = 0, n_all = 0;
+    std::vector<Group> groups;
     bool dirty = true;
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
@@ -176,6 +270,7 @@ struct Server {
     void loop();
     void admit();
     uq_status rebuild_table();
+    uq_status enqueue_tick(int64_t T);
     uq_status tick(int64_t K);
     void finish(Live &l);
     void release_graph() {
@@ -208,10 +303,17 @@ void Server::admit() {
         dv.free = arena_free_cb;
         dv.ctx = &arena;
         StepShape sh;
-        sh.layout = UQ_LAYOUT_AA;
         sh.cpt = 1;
         sh.pad = 64;
         sh.nt = 0;
+        if (r.shape.kind >= 0) {
+            sh.layout = UQ_LAYOUT_AB;
+            sh.fuse = r.shape.N;
+            sh.fwin = 2;
+            sh.fty = r.shape.H;
+        } else {
+            sh.layout = UQ_LAYOUT_AA;
+        }
         uq_job *j = nullptr;
         uq_status st = create_job(r.p, &dv, &sh, &j);
         if (st == UQ_ENOMEM) {  // fragmentation: retry when memory frees up
@@ -220,6 +322,8 @@ void Server::admit() {
             continue;
         }
         if (st == UQ_OK && hipStreamSynchronize(j->stream) != hipSuccess) st = UQ_EDEVICE;
+        if (st == UQ_OK && r.shape.kind >= 0 && j->fused_n() != r.shape.N)
+            st = fail(UQ_ESTATE, "server job did not take its batched shape");
         if (st != UQ_OK) {
             uq_result res{};
             res.ticket = r.ticket;
@@ -246,12 +350,52 @@ void Server::admit() {
     }
 }
 
+// Tables of the jobs in `live` that take part in the next ticks.
 uq_status Server::rebuild_table() {
-    std::vector<MultiJob> h(live.size());
+    std::vector<MultiJob> single;
+    std::vector<FusedJob> fused;
+    std::vector<int64_t *> tptrs;
     int64_t tile = 0;
-    for (size_t q = 0; q < live.size(); ++q) {
-        Live &l = live[q];
-        MultiJob &m = h[q];
+    // batched instances: jobs sorted by instance, each instance contiguous
+    std::vector<size_t> order;
+    for (size_t q = 0; q < live.size(); ++q)
+        if (live[q].r.shape.kind >= 0) order.push_back(q);
+    auto key = [&](size_t q) {
+        const ServeShape &h = live[q].r.shape;
+        return std::make_tuple(h.kind, h.N, h.K, h.M);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
+    groups.clear();
+    for (size_t q : order) {
+        const Live &l = live[q];
+        const ServeShape &h = l.r.shape;
+        if (groups.empty() || key(q) != std::make_tuple(groups.back().kind, groups.back().N, groups.back().K,
+                                                        groups.back().M)) {
+            Group g;
+            g.kind = h.kind;
+            g.N = h.N;
+            g.K = h.K;
+            g.M = h.M;
+            g.first = (int)fused.size();
+            groups.push_back(g);
+        }
+        Group &g = groups.back();
+        FusedJob f;
+        std::memset(&f, 0, sizeof f);
+        f.j = l.job->jd;
+        f.d_t = l.job->d_t;
+        f.H = h.H;
+        f.chunks = (l.r.p.ny + h.H - 1) / h.H;
+        f.work0 = g.nwork;
+        f.par = (int32_t)(l.job->t & 1);
+        g.nwork += l.job->S * f.chunks;
+        ++g.count;
+        fused.push_back(f);
+        tptrs.push_back(l.job->d_t);
+    }
+    for (Live &l : live) {
+        if (l.r.shape.kind >= 0) continue;
+        MultiJob m;
         std::memset(&m, 0, sizeof m);
         m.j = l.job->jd;
         m.t = l.job->t;
@@ -260,19 +404,47 @@ uq_status Server::rebuild_table() {
         m.tiles_x = l.tiles_x;
         m.tiles_y = l.tiles_y;
         tile += (int64_t)l.job->S * l.tiles_x * l.tiles_y;
+        single.push_back(m);
+        tptrs.push_back(l.job->d_t);
     }
     total_tiles = tile;
-    if ((int)h.size() > table_cap) return fail(UQ_ESTATE, "more live jobs than the table holds");
-    if (!h.empty()) {
-        UQ_HIP_TRY(hipMemcpyAsync(d_table, h.data(), sizeof(MultiJob) * h.size(), hipMemcpyHostToDevice, stream));
-        UQ_HIP_TRY(hipStreamSynchronize(stream));
-    }
+    if ((int)tptrs.size() > table_cap) return fail(UQ_ESTATE, "more live jobs than the table holds");
+    n_single = (int)single.size();
+    n_fused = (int)fused.size();
+    n_all = (int)tptrs.size();
+    if (n_single)
+        UQ_HIP_TRY(hipMemcpyAsync(d_table, single.data(), sizeof(MultiJob) * single.size(), hipMemcpyHostToDevice,
+                                  stream));
+    if (n_fused)
+        UQ_HIP_TRY(hipMemcpyAsync(d_fused, fused.data(), sizeof(FusedJob) * fused.size(), hipMemcpyHostToDevice,
+                                  stream));
+    if (n_all)
+        UQ_HIP_TRY(hipMemcpyAsync(d_tptrs, tptrs.data(), sizeof(int64_t *) * tptrs.size(), hipMemcpyHostToDevice,
+                                  stream));
+    UQ_HIP_TRY(hipStreamSynchronize(stream));  // the host vectors go out of scope
     release_graph();
     dirty = false;
     return UQ_OK;
 }
 
-// Advance every live job by K steps (jobs that reach their target stop).
+// T steps of every job in the tables: each batched instance in T/N launches
+// (launch k reads the slab of parity t ^ k of each of its jobs), the
+// single-step jobs in T launches, then every job's step counter.
+uq_status Server::enqueue_tick(int64_t T) {
+    for (const Group &g : groups)
+        for (int k = 0; k < (int)(T / g.N); ++k)
+            UQ_HIP_TRY(launch_fused_multi(g.kind, cfg.precision, g.N, g.K, g.M, d_fused + g.first, g.count, g.nwork,
+                                          k, stream));
+    if (n_single) {
+        for (int k = 0; k < (int)T; ++k)
+            UQ_HIP_TRY(launch_step_multi(d_table, n_single, total_tiles, k, cfg.precision, stream));
+        UQ_HIP_TRY(launch_advance_multi(d_table, n_single, T, stream));
+    }
+    UQ_HIP_TRY(launch_advance_ptrs(d_tptrs, n_all, T, stream));
+    return UQ_OK;
+}
+
+// Advance every job of the tables by K steps (batched: K is the tick).
 uq_status Server::tick(int64_t K) {
     if (cfg.mode == UQ_SERVE_PLAIN) {
         // one job, one sample per launch, no graph
@@ -295,31 +467,26 @@ uq_status Server::tick(int64_t K) {
         j->t += K;
         return UQ_OK;
     }
-    const int nj = (int)live.size();
-    const int prec = cfg.precision;
-    const bool graph_tick = cfg.use_graph && K == cfg.steps_per_tick;
-    if (graph_tick && !gexec) {
+    if (cfg.use_graph && !gexec) {
         UQ_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < K && e == hipSuccess; ++k) e = launch_step_multi(d_table, nj, total_tiles, k, prec, stream);
-        if (e == hipSuccess) e = launch_advance_multi(d_table, nj, K, stream);
+        uq_status st = enqueue_tick(K);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
+        if (st != UQ_OK || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return fail(UQ_EDEVICE, "server graph capture failed");
         }
         graph = g;
         UQ_HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     }
-    if (graph_tick) {
+    if (cfg.use_graph) {
         UQ_HIP_TRY(hipGraphLaunch(gexec, stream));
     } else {
-        for (int k = 0; k < K; ++k) UQ_HIP_TRY(launch_step_multi(d_table, nj, total_tiles, k, prec, stream));
-        UQ_HIP_TRY(launch_advance_multi(d_table, nj, K, stream));
+        uq_status st = enqueue_tick(K);
+        if (st != UQ_OK) return st;
     }
     UQ_HIP_TRY(hipStreamSynchronize(stream));
-    for (Live &l : live) l.job->t = std::min<int64_t>(l.job->t + K, l.r.steps);
+    for (Live &l : live) l.job->t += K;
     return UQ_OK;
 }
 
@@ -373,6 +540,12 @@ void Server::finish(Live &l) {
 
 void Server::loop() {
     (void)hipSetDevice(device);
+    auto die = [&](const std::string &msg) {
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = msg;
+        stop = true;
+        cv_done.notify_all();
+    };
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -386,51 +559,46 @@ void Server::loop() {
             cv_work.wait_for(lk, std::chrono::milliseconds(5));
             continue;
         }
-        if (cfg.mode != UQ_SERVE_PLAIN && dirty) {
-            uq_status st = rebuild_table();
-            if (st != UQ_OK) {
+        const bool plain = cfg.mode == UQ_SERVE_PLAIN;
+        int64_t K = plain ? std::min<int64_t>(cfg.steps_per_tick, live.front().r.steps - live.front().job->t)
+                          : batched_tick(cfg.steps_per_tick);
+        // batched: jobs with fewer steps left than a tick leave the tables
+        // and take their last steps in launches of their own (the same
+        // arithmetic: fused and single steps agree bit for bit)
+        std::vector<Live> ending;
+        if (!plain) {
+            std::vector<Live> keep;
+            for (Live &l : live) (l.r.steps - l.job->t < K ? ending : keep).push_back(l);
+            if (!ending.empty()) {
                 std::lock_guard<std::mutex> lk(mu);
-                fatal = uq_last_error();
-                stop = true;
-                cv_done.notify_all();
-                return;
+                live.swap(keep);
+                dirty = true;
+            }
+            if (dirty && !live.empty()) {
+                uq_status st = rebuild_table();
+                if (st != UQ_OK) return die(uq_last_error());
             }
         }
-        int64_t K = cfg.steps_per_tick;
-        for (Live &l : live) K = std::min<int64_t>(K, l.r.steps - l.job->t);
-        if (cfg.mode != UQ_SERVE_PLAIN && K < cfg.steps_per_tick && K > 0 && cfg.use_graph) {
-            // a job ends inside this tick: run the full graph anyway if most
-            // jobs have further to go; the finished job's tiles are skipped
-            int64_t Kmax = 0;
-            for (Live &l : live) Kmax = std::max<int64_t>(Kmax, l.r.steps - l.job->t);
-            if (Kmax >= cfg.steps_per_tick) K = cfg.steps_per_tick;
-        }
         const double tb = now();
-        uq_status st = K > 0 ? tick(K) : UQ_OK;
-        const double te = now();
-        if (st != UQ_OK) {
-            std::lock_guard<std::mutex> lk(mu);
-            fatal = uq_last_error();
-            stop = true;
-            cv_done.notify_all();
-            return;
+        for (Live &l : ending) {
+            Job *j = l.job;
+            uq_status st = j->enter();
+            if (st == UQ_OK) st = j->advance(l.r.steps - j->t);
+            if (st != UQ_OK) return die(uq_last_error());
         }
+        uq_status st = (!live.empty() && K > 0) ? tick(K) : UQ_OK;
+        if (st != UQ_OK) return die(uq_last_error());
+        for (Live &l : ending) finish(l);
+        const double te = now();
         {
             std::lock_guard<std::mutex> lk(mu);
             busy_s += te - tb;
         }
-        std::vector<Live> keep;
-        for (Live &l : live) {
-            if (l.job->t >= l.r.steps) {
-                finish(l);
-                std::lock_guard<std::mutex> lk(mu);
-                dirty = true;
-            } else {
-                keep.push_back(l);
-            }
+        if (plain && live.front().job->t >= live.front().r.steps) {
+            finish(live.front());
+            std::lock_guard<std::mutex> lk(mu);
+            live.clear();
         }
-        std::lock_guard<std::mutex> lk(mu);
-        live.swap(keep);
     }
 }
 
@@ -440,23 +608,38 @@ using namespace uqi;
 
 struct uq_server : public uqi::Server {};
 
-extern "C" uq_status uq_server_create(const uq_server_config *cfg, int32_t device, uq_server **out) {
+extern "C" uq_status uq_server_create(const uq_server_config *cfg, const uq_device *dev, uq_server **out) {
     if (!cfg || !out) return fail(UQ_EINVAL, "null argument");
     *out = nullptr;
     if (cfg->memory_budget <= 0 || cfg->max_jobs < 1 || cfg->max_jobs > 4096 || cfg->steps_per_tick < 2 ||
         (cfg->mode != UQ_SERVE_BATCHED && cfg->mode != UQ_SERVE_PLAIN) || cfg->precision < UQ_FP64 ||
         cfg->precision > UQ_BF16S)
         return fail(UQ_EINVAL, "invalid server configuration");
+    if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr)))
+        return fail(UQ_EINVAL, "uq_device needs both alloc and free, or neither");
     std::unique_ptr<uq_server> s(new uq_server());
     s->cfg = *cfg;
     s->cfg.steps_per_tick &= ~1;
-    s->device = device;
-    UQ_HIP_TRY(hipSetDevice(device));
-    uq_status st = s->arena.init((size_t)cfg->memory_budget);
-    if (st != UQ_OK) return st;
+    if (dev) s->dev = *dev;
+    s->device = s->dev.device;
+    UQ_HIP_TRY(hipSetDevice(s->device));
     UQ_HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    UQ_HIP_TRY(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
+    uq_status st = s->arena.init((size_t)cfg->memory_budget, s->dev);
+    if (st != UQ_OK) return st;
+    // the arena (from the caller's allocator on the caller's stream) is
+    // ready for the loop once the caller's stream has reached this point
+    UQ_HIP_TRY(hipEventRecord(s->ev, (hipStream_t)s->dev.stream));
+    UQ_HIP_TRY(hipStreamWaitEvent(s->stream, s->ev, 0));
     s->table_cap = cfg->max_jobs;
-    UQ_HIP_TRY(hipMalloc(&s->d_table, sizeof(MultiJob) * s->table_cap));
+    const size_t tb = up256(sizeof(MultiJob) * s->table_cap) + up256(sizeof(FusedJob) * s->table_cap) +
+                      up256(sizeof(int64_t *) * s->table_cap);
+    s->d_tables = s->arena.alloc(tb);
+    if (!s->d_tables) return fail(UQ_ENOMEM, "server memory budget too small for its job tables");
+    char *t = (char *)s->d_tables;
+    s->d_table = (MultiJob *)t;
+    s->d_fused = (FusedJob *)(t + up256(sizeof(MultiJob) * s->table_cap));
+    s->d_tptrs = (int64_t **)(t + up256(sizeof(MultiJob) * s->table_cap) + up256(sizeof(FusedJob) * s->table_cap));
     s->t0 = std::chrono::steady_clock::now();
     uq_server *raw = s.get();
     s->th = std::thread([raw] { raw->loop(); });
@@ -475,7 +658,7 @@ extern "C" uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t
         return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
     if (p->precision != s->cfg.precision) return fail(UQ_EINVAL, "job precision differs from the server's");
     if (needs_ab(*p))
-        return fail(UQ_EINVAL, "the server runs the in-place AA layout; interpolated boundaries need a job of their own");
+        return fail(UQ_EINVAL, "the server's kernels take node-local boundary rules; interpolated boundaries need a job of their own");
     Rule r;
     uq_status st = build_rule(*p, r);
     if (st != UQ_OK) return st;
@@ -485,7 +668,8 @@ extern "C" uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t
     q.qoi = qoi;
     q.S = r.S;
     q.K = r.K;
-    q.footprint = job_footprint(*p, r.S, r.K);
+    if (s->cfg.mode == UQ_SERVE_BATCHED) q.shape = serve_shape(*p, r.S);
+    q.footprint = job_footprint(*p, r.S, r.K, q.shape.kind >= 0);
     if ((size_t)q.footprint > s->arena.capacity())
         return fail(UQ_ENOMEM, "job needs " + std::to_string(q.footprint) + " B, more than the server's memory budget");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -576,7 +760,15 @@ extern "C" void uq_server_destroy(uq_server *s) {
         if (l.job) delete l.job;
     s->live.clear();
     s->release_graph();
-    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->stream) {
+        // the caller's stream waits for the loop's work before the arena
+        // goes back to the caller's allocator
+        (void)hipStreamSynchronize(s->stream);
+        if (s->ev && hipEventRecord(s->ev, s->stream) == hipSuccess)
+            (void)hipStreamWaitEvent((hipStream_t)s->dev.stream, s->ev, 0);
+    }
+    if (s->d_tables) s->arena.release(s->d_tables);
+    if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
-    delete s;
+    delete s;  // the arena's memory goes back
 }

@@ -118,6 +118,19 @@ struct alignas(16) MultiJob {
     int32_t tiles_x, tiles_y;
 };
 
+// A job of a batched fused launch (device table, continuous batching with
+// temporal blocking): every chunk of every sample of every job in the table
+// advances N steps per launch through one kernel instance. Jobs differ in
+// lattice (up to the instance's row width), sample count and step parity.
+struct alignas(16) FusedJob {
+    JobDev j;
+    const int64_t *d_t;  // the job's device step count (inflow ramp)
+    int64_t work0;       // first work item: the job has S * chunks of them
+    int32_t H, chunks;   // rows per chunk, chunks per sample
+    int32_t par;         // t & 1 of the job at the start of the tick
+    int32_t pad;
+};
+
 // ------------------------------------------------------------------ kernel launchers
 struct StepShape {
     int cpt = 1;        // rows per thread (1 or 2)
@@ -160,6 +173,19 @@ int channel_rows_max_nx(int prec, int n);
 // widest lattice the full-row kernel takes at this precision and N (0: none)
 int full_rows_max_nx(int prec, int n);
 bool fused_supported(const JobDev &j);
+// Batched full-row launches (continuous batching with temporal blocking).
+// kind 0: periodic lattice, kind 1: channel. rows_instance gives the waves
+// per level K and columns per lane M of the N-step instance for rows nx
+// wide (0 if none fits); fused_multi_supported says whether the batched
+// form of that instance exists (N in {4, 6, 8} periodic, {2, 3, 4} channel;
+// single-precision storage formats).
+int rows_instance(int kind, int prec, int n, int nx, int *K, int *M);
+bool fused_multi_supported(int kind, int prec, int n, int K, int M);
+// launch number `launch` of a tick: every work item of jobs[0..njobs)
+hipError_t launch_fused_multi(int kind, int prec, int n, int K, int M, const FusedJob *jobs, int njobs,
+                              int64_t nwork, int launch, hipStream_t s);
+// *d_t[q] += n for q < njobs
+hipError_t launch_advance_ptrs(int64_t *const *d_t, int njobs, int64_t n, hipStream_t s);
 // one step of every job in a table (AA layout, one row per thread); all jobs
 // must share precision `prec`
 hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s);

@@ -123,6 +123,66 @@ def serving_trace(n_jobs=16, seed=SEED, load=1.2, rate_nodes_per_s=5.0e10, max_S
     return [(float(a), j) for a, j in zip(t, jobs)]
 
 
+def serving_mix(n_jobs=200, seed=SEED, max_work=2.0e11, steps_range=(1000, 20000)):
+    """The serving mix at full scale: seeded UQ jobs, 60 % Taylor-Green
+    vortices on 64^2..1024^2 lattices and 40 % cylinder channels of diameter
+    10..40 (22D x 4.1D lattice, Zou-He inlet/outlet, half-way walls and
+    cylinder), 1- to 4-D (vortex) or 1- to 2-D (channel) uniform inputs,
+    tensor Gauss-Legendre rules of 5..256 nodes or Monte Carlo with
+    256..4096 samples, FP32; steps log-uniform in steps_range, cut so that
+    no job exceeds max_work node updates. Returns [spec, ...] in arrival
+    order; arrival times are drawn by the caller (poisson_arrivals)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for q in range(n_jobs):
+        steps = int(round(np.exp(rng.uniform(np.log(steps_range[0]), np.log(steps_range[1])))))
+        mc = rng.random() < 0.5
+        if rng.random() < 0.6:
+            n = int(rng.choice([64, 128, 192, 256, 384, 512, 768, 1024]))
+            nx = ny = n
+            d = int(rng.integers(1, 5))
+            dists = FOUR_D_INPUTS[:d] if d > 1 else [("nu", 0.004, 0.006)]
+            per = {1: (5, 16), 2: (3, 16), 3: (2, 6), 4: (2, 4)}[d]
+            spec = dict(name=f"mix{q}_tgv{n}", geometry="tgv", precision="fp32", nx=nx, ny=ny, u0=0.02,
+                        nu=0.005, dists=dists)
+        else:
+            D = int(rng.choice([10, 14, 20, 28, 40]))
+            nx, ny = 22 * D, int(round(4.1 * D))
+            d = int(rng.integers(1, 3))
+            dists = [("re", 16.0, 24.0), ("u_peak", 0.045, 0.055)][:d]
+            per = {1: (5, 16), 2: (3, 16)}[d]
+            spec = dict(name=f"mix{q}_cyl{D}", geometry="channel", precision="fp32", nx=nx, ny=ny, u_peak=0.05,
+                        nu=0.05 * D / 20.0, D=D, cx=2 * D, cy=ny // 2, xbc="zouhe", dists=dists)
+        if mc:
+            S = int(rng.choice([256, 512, 1024, 2048, 4096]))
+            spec["rule"] = dict(kind="mc", N=S, seed=SEED + q)
+        else:
+            npd = int(rng.integers(per[0], per[1] + 1))
+            spec["rule"] = dict(kind="gl", n=npd, order=min(npd - 1, 3))
+            S = npd ** d
+        steps = max(2, min(steps, int(max_work / (S * nx * ny))))
+        spec["steps"] = steps
+        if spec["geometry"] == "channel":
+            spec["ramp"] = steps // 5
+        spec["work"] = float(S) * nx * ny * steps
+        jobs.append(spec)
+    return jobs
+
+
+def poisson_arrivals(jobs, rate_nodes_per_s, load, seed=SEED + 1):
+    """Seeded Poisson arrival times for `jobs` at an offered load of `load`
+    times a service rate of rate_nodes_per_s node updates per second: the
+    mean inter-arrival time is the mean job work / (load * rate)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    mean_service = sum(j["work"] for j in jobs) / len(jobs) / rate_nodes_per_s
+    gaps = rng.exponential(mean_service / load, size=len(jobs))
+    return [float(t) for t in np.cumsum(gaps) - gaps[0]]
+
+
 # 128^2 vortex, 4-D inputs, level-3 Smolyak sparse grid of nested
 # Clenshaw-Curtis rules (137 points, the paper's sparse-grid size), order 3
 TGV_SMOLYAK = dict(

@@ -30,6 +30,53 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(A.SIGNATURES), set(names) - set(A.SIGNATURES)
 
 
+def declared_signatures():
+    """{name: (return type, [parameter types])} of every function in uq.h."""
+    text = open(os.path.join(ROOT, "include", "uq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*((?:const\s+)?[a-z_0-9]+\s*\*?)\s*(uq_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text,
+                         flags=re.M):
+        params = [p.strip() for p in m.group(3).split(",") if p.strip() and p.strip() != "void"]
+        # drop each parameter's name (the identifier after the type)
+        types = [re.sub(r"\s+", " ", re.sub(r"(?<=[\s*])[A-Za-z_][A-Za-z_0-9]*$", "", p).strip()).replace(" *", "*")
+                 for p in params]
+        out[m.group(2)] = (m.group(1).strip(), types)
+    return out
+
+
+def test_binding_signatures_match_header():
+    # every parameter of every declared function has the C type the ctypes
+    # binding passes: structs by pointer to their mirror (or an untyped
+    # pointer for caller buffers), opaque handles as pointers, integers at
+    # their width, doubles as doubles
+    mirrors = {"uq_problem": A.Problem, "uq_device": A.Device, "uq_moments_out": A.MomentsOut,
+               "uq_job_info": A.JobInfo, "uq_tune_result": A.TuneResult, "uq_server_config": A.ServerConfig,
+               "uq_result": A.Result, "uq_server_stats": A.ServerStats}
+    scalars = {"int32_t": C.c_int32, "int64_t": C.c_int64, "uint64_t": C.c_uint64, "double": C.c_double}
+    opaque = {"uq_job", "uq_server"}
+
+    def ok(ctype, arg):
+        base = ctype.replace("const ", "").rstrip("*").strip()
+        if ctype.endswith("**"):
+            return arg in (C.c_void_p, C.POINTER(C.c_void_p))
+        if ctype.endswith("*"):
+            if base in opaque:
+                return arg is C.c_void_p
+            if base in mirrors:
+                return arg is C.POINTER(mirrors[base])
+            return arg is C.c_void_p or arg is C.POINTER(scalars[base])
+        return arg is scalars[base] or (base == "int32_t" and arg is C.c_int32)
+
+    sigs = declared_signatures()
+    assert "uq_server_create" in sigs and sigs["uq_server_create"][1][1] == "const uq_device*"
+    for name, (_, params) in sigs.items():
+        _, args = A.SIGNATURES[name]
+        assert len(args) == len(params), name
+        for k, (ctype, arg) in enumerate(zip(params, args)):
+            assert ok(ctype, arg), (name, k, ctype, arg)
+
+
 def test_struct_layout_matches_header(tmp_path):
     # the ctypes mirrors must have the C compiler's layout of uq.h
     import subprocess

@@ -644,13 +644,15 @@ def test_fused_kernel_matches_single_steps(prec, window, n, monkeypatch):
 
 
 @pytest.mark.parametrize("n", [7, 8])
-@pytest.mark.parametrize("nx, ny, rows", [(72, 40, 16), (128, 9, 64), (20, 12, 8), (3, 5, 8), (128, 128, 256)])
+@pytest.mark.parametrize("nx, ny, rows", [(72, 40, 16), (128, 9, 64), (20, 12, 8), (3, 5, 8), (128, 128, 256),
+                                           (200, 13, 8), (256, 24, 16)])
 @pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
 def test_full_row_kernel_seven_and_eight_steps(prec, nx, ny, rows, n, monkeypatch):
-    # 7 and 8 steps per launch: whole rows of at most 128 columns (one column
-    # per lane, 14 or 16 waves), single precision and 16-bit storage; bit for
-    # bit the single-step result, over counts that leave single steps after
-    # the fused blocks
+    # 7 and 8 steps per launch: whole rows of up to 128 columns at one
+    # column per lane and of 129..256 columns at two (14 or 16 waves; 200
+    # leaves lanes past the lattice), single precision and 16-bit storage;
+    # bit for bit the single-step result, over counts that leave single
+    # steps after the fused blocks
     monkeypatch.setenv("UQ_FUSE_TY", str(rows))
     monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
     spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision=prec)
@@ -694,17 +696,21 @@ def test_steps_left_over_run_as_odd_fused_launches(steps, launches, monkeypatch)
 
 
 def test_full_row_kernel_eight_steps_refused_where_rows_are_too_wide(monkeypatch):
-    # 256 columns need two columns per lane: 16 waves of those do not fit the
-    # registers, so 8 steps over whole rows fall back to single steps
+    # 320 columns need three waves of two columns per lane per level: 24
+    # waves for 8 levels, more than a workgroup holds, so 8 steps over whole
+    # rows fall back to single steps (256 columns fit: 16 waves)
     monkeypatch.setenv("UQ_FUSE", "8")
     monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
-    spec = W.scaled(TGV_RAGGED, nx=256, ny=16, layout="ab", precision="fp32")
+    spec = W.scaled(TGV_RAGGED, nx=320, ny=16, layout="ab", precision="fp32")
     with Job(spec) as job:
         assert job.info().fused == 0
+    with Job(W.scaled(spec, nx=256)) as job:
+        assert job.info().fused == 8
 
 
 @pytest.mark.parametrize("n, window, rows, nt", [(2, 0, 8, 1), (3, 0, 8, 1), (4, 1, 64, 0), (4, 2, 256, 0),
-                                                 (3, 2, 256, 0), (5, 2, 256, 0), (6, 2, 256, 0)])
+                                                 (3, 2, 256, 0), (5, 2, 256, 0), (6, 2, 256, 0), (7, 2, 256, 0),
+                                                 (8, 2, 256, 0)])
 def test_fused_kernel_full_size_sampled(n, window, rows, nt, monkeypatch):
     # the 256^2 x 256 benchmark lattice, fused, 120 steps, two samples
     # re-solved by the oracle

@@ -9,7 +9,7 @@ levels above pull from LDS rings of the level below:
 - c_y =  0 directions (row y):                2 slots, (r + 12) mod 2;
 - c_y = +1 directions (row y - 1):            3 slots, (r + 12) mod 3;
 
-a level writes direction i of column c at LDS column ((c + c_ix) mod nx) + 1,
+a level writes direction i of column c at LDS column (c + c_ix) mod nx,
 so every pull reads the puller's own column; the c_y >= 0 pulls of the next
 row are read one step ahead (for the first row, in the step before it), the
 c_y = -1 pulls in the row's own step. Lanes past the lattice take its last
@@ -71,7 +71,7 @@ def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
             def read(level, lane, c, i, r):
                 # pull of direction i for row r of `level`: row r - c_y of the
                 # level below, at the lane's own column
-                key = slot(level - 2, r - CY[i], i, c + 1)
+                key = slot(level - 2, r - CY[i], i, c)
                 assert tag.get(key) == (r - CY[i], (c - CX[i]) % nx, i), (level, it, lane, i, r)
                 reads.add(key)
                 return lds[key]
@@ -99,7 +99,7 @@ def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
                                                            for i in range(9) if CY[i] >= 0}
                     g = collide(f[:, None], omega)[:, 0]
                     if level < n_lvl:
-                        writes += [(slot(level - 1, y, i, (c + CX[i]) % nx + 1), (y, c, i), g[i])
+                        writes += [(slot(level - 1, y, i, (c + CX[i]) % nx), (y, c, i), g[i])
                                    for i in range(9)]
                     else:
                         assert 0 <= y < ny
