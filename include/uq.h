@@ -345,13 +345,14 @@ uq_status uq_moments(uq_job *job, int32_t qoi, uq_moments_out *out);
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same kernels and the same results
  * (bit for bit) as uq_moments, with their intermediates -- per-sample scalar
- * QoIs, per-sample fields of a field QoI, the moment outputs and a flag -- in
- * a fixed array of UQ_NOALLOC_SCRATCH_BYTES that the library keeps on every
- * GPU it runs on until the process ends, instead of buffers the job would
- * allocate on its first statistics call. The job's own device memory is
- * untouched (uq_job_info.device_bytes stays the same). The need is
- *   256-byte-rounded 8 * (4 S + S + 1 + (K + 3) n_out)  [+ 8 * 4 nx ny S for
- *   a field QoI];
+ * QoIs, the moment outputs and a flag -- in a fixed array of
+ * UQ_NOALLOC_SCRATCH_BYTES that the library keeps on every GPU it runs on
+ * until the process ends, instead of buffers the job would allocate on its
+ * first statistics call. The job's own device memory is untouched
+ * (uq_job_info.device_bytes stays the same). The need is the sum of
+ *   8 * 4 S, 8 * S, 8 and 8 * (K + 3) n_out bytes, each rounded up to 256
+ * (field moments are formed from the populations, with no per-sample field
+ * buffer);
  * larger requests fail with UQ_EINVAL and a message naming both sizes (use
  * uq_moments then). Calls on one GPU share its array: the library runs them
  * one at a time (each holds the GPU's lock until its results are on the

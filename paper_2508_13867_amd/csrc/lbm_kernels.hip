@@ -1845,84 +1845,222 @@ __global__ __launch_bounds__(256) void k_export(JobDev j, int64_t t, int64_t smp
     }
 }
 
-// ------------------------------------------------------------------ moments
-// SC-gPC projection (Eq. coef_discrete with gamma_k = 1): one thread per
-// output value and a chunk of up to KC coefficients; wphi[j][k] = a_j Phi_k
-// is staged through LDS in blocks of samples.
-constexpr int KC = 8;
-constexpr int JB = 64;
+// ------------------------------------------------------------------ field statistics from the slab
+// Statistics of a field QoI read straight from the populations, without a
+// per-sample field buffer: the value of a (sample, node) is formed from its
+// pulled populations exactly as k_fields forms it (velocity u_x, u_y; density
+// 1 + drho; speed |u|; 0 at solid nodes), and every sum over the samples runs
+// in ascending sample order with Neumaier compensation (FP64), output by
+// output, so the result does not depend on the launch shape.
+// Field QoIs: which = 0 velocity (two components), 1 density, 2 speed.
+constexpr int FP_JB = 16;  // samples per LDS block of values
+constexpr int FP_KA = 12;  // (component, coefficient) pairs per thread
 
-__global__ __launch_bounds__(256) void k_gpc_coeffs(const double *M, int64_t S, int64_t n_out, int64_t ld,
-                                                    const double *wphi, int K, double *coeffs) {
-    __shared__ double w_lds[JB][KC];
-    const int k0 = blockIdx.y * KC;
-    const int nk = min(KC, K - k0);
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    NSum acc[KC];
-    for (int64_t j0 = 0; j0 < S; j0 += JB) {
-        const int nj = (int)min((int64_t)JB, S - j0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < JB * KC; e += blockDim.x) {
-            const int jj = e / KC, kk = e % KC;
-            w_lds[jj][kk] = (jj < nj && kk < nk) ? wphi[(j0 + jj) * K + k0 + kk] : 0.0;
+template <int P, bool CHANNEL, int MODE>
+__device__ inline void field_value(const JobDev &j, const typename Prec<P>::T *base, int64_t t, int64_t smp,
+                                   int64_t c, int which, double &v0, double &v1) {
+    using C = typename Prec<P>::C;
+    const int y = (int)(c / j.nx), x = (int)(c - (int64_t)y * j.nx);
+    uint32_t m = 0;
+    v0 = v1 = 0.0;
+    if (CHANNEL) {
+        m = j.mask[(int64_t)y * j.pitch + x];
+        if (m & M_SOLID) return;
+    }
+    C f[9], drho, ux, uy;
+    gather<P, CHANNEL, MODE>(j, base, site(j, x, y), m, t, j.smp[smp].u_peak, j.smp[smp].omega, f);
+    moments(f, drho, ux, uy);
+    if (which == 0) {
+        v0 = (double)ux;
+        v1 = (double)uy;
+    } else if (which == 1) {
+        v0 = 1.0 + (double)drho;
+    } else {
+        v0 = sqrt((double)ux * (double)ux + (double)uy * (double)uy);
+    }
+}
+
+// SC-gPC coefficients c_k(o) = sum_j a_j Phi_k(xi_j) M_j(o) (Eq.
+// coef_discrete) of a field: a workgroup takes 64 nodes (one per lane) and
+// 4 FP_KA (component, k) pairs (FP_KA per wave); per block of FP_JB samples
+// the four waves form the values of the 64 nodes into LDS, then every
+// thread adds its pairs' terms. coeffs[k][n_out], o = component * cells + node.
+template <int P, bool CHANNEL, int MODE>
+__global__ __launch_bounds__(256) void k_field_coeffs(JobDev j, int64_t t, int which,
+                                                      const double *__restrict__ wphi, int K, double *coeffs) {
+    using T = typename Prec<P>::T;
+    __shared__ double val[FP_JB][2][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    const int comps = which == 0 ? 2 : 1;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    const bool on = c < cells;
+    const int npair = comps * K;
+    const int p0 = (int)blockIdx.y * 4 * FP_KA + w * FP_KA;
+    int kq[FP_KA], cq[FP_KA];
+#pragma unroll
+    for (int q = 0; q < FP_KA; ++q) {
+        const int p = min(p0 + q, npair - 1);
+        cq[q] = p / K;
+        kq[q] = p - cq[q] * K;
+    }
+    const T *slab = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f);
+    NSum acc[FP_KA];
+    for (int64_t j0 = 0; j0 < j.S; j0 += FP_JB) {
+        const int nj = (int)min((int64_t)FP_JB, j.S - j0);
+#pragma unroll
+        for (int i = 0; i < FP_JB / 4; ++i) {
+            const int jj = w + 4 * i;
+            double v0 = 0.0, v1 = 0.0;
+            if (jj < nj && on)
+                field_value<P, CHANNEL, MODE>(j, slab + (j0 + jj) * 9 * j.plane, t, j0 + jj, c, which, v0, v1);
+            val[jj][0][lane] = v0;
+            val[jj][1][lane] = v1;
         }
         __syncthreads();
-        if (o < n_out) {
-            for (int jj = 0; jj < nj; ++jj) {
-                const double m = M[(j0 + jj) * ld + o];
+        for (int jj = 0; jj < nj; ++jj) {
+            const double *wr = wphi + (j0 + jj) * K;
 #pragma unroll
-                for (int kk = 0; kk < KC; ++kk)
-                    if (kk < nk) acc[kk].add(w_lds[jj][kk] * m);
+            for (int q = 0; q < FP_KA; ++q) acc[q].add(wr[kq[q]] * val[jj][cq[q]][lane]);
+        }
+        __syncthreads();
+    }
+    if (on) {
+#pragma unroll
+        for (int q = 0; q < FP_KA; ++q)
+            if (p0 + q < npair) coeffs[(int64_t)kq[q] * comps * cells + cq[q] * cells + c] = acc[q].val();
+    }
+}
+
+// The rest of a field's statistics, one thread per node (both velocity
+// components): SC (wphi != null): mean = c_0, var = sum_{k>=1} c_k^2 (Eq.
+// gpc_std) and the quadrature variance sum_j a_j (M_j - mean)^2; MC: mean
+// (Eq. meanMCS), var with 1/(N-1) (Eq. varMCS) and 1/N, two passes.
+template <int P, bool CHANNEL, int MODE>
+__global__ __launch_bounds__(256) void k_field_finish(JobDev j, int64_t t, int which, const double *__restrict__ a,
+                                                      int K, const double *coeffs, double *mean, double *var,
+                                                      double *var_alt) {
+    using T = typename Prec<P>::T;
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    const int comps = which == 0 ? 2 : 1;
+    const int64_t n_out = comps * cells;
+    const T *slab = (const T *)(MODE == AB_PULL && (t & 1) ? j.f2 : j.f);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        double mu[2] = {0.0, 0.0};
+        if (K > 0) {
+            for (int q = 0; q < comps; ++q) {
+                const int64_t o = q * cells + c;
+                mu[q] = coeffs[o];
+                NSum v;
+                for (int k = 1; k < K; ++k) {
+                    const double ck = coeffs[(int64_t)k * n_out + o];
+                    v.add(ck * ck);
+                }
+                mean[o] = mu[q];
+                var[o] = v.val();
+            }
+        } else {
+            NSum s0, s1;
+            for (int64_t smp = 0; smp < j.S; ++smp) {
+                double v0, v1;
+                field_value<P, CHANNEL, MODE>(j, slab + smp * 9 * j.plane, t, smp, c, which, v0, v1);
+                s0.add(v0);
+                s1.add(v1);
+            }
+            mu[0] = s0.val() / (double)j.S;
+            mu[1] = s1.val() / (double)j.S;
+        }
+        NSum q0, q1;
+        for (int64_t smp = 0; smp < j.S; ++smp) {
+            double v0, v1;
+            field_value<P, CHANNEL, MODE>(j, slab + smp * 9 * j.plane, t, smp, c, which, v0, v1);
+            const double e0 = v0 - mu[0], e1 = v1 - mu[1];
+            if (K > 0) {
+                q0.add(a[smp] * e0 * e0);
+                q1.add(a[smp] * e1 * e1);
+            } else {
+                q0.add(e0 * e0);
+                q1.add(e1 * e1);
+            }
+        }
+        const double qs[2] = {q0.val(), q1.val()};
+        for (int q = 0; q < comps; ++q) {
+            const int64_t o = q * cells + c;
+            if (K > 0) {
+                var_alt[o] = qs[q];
+            } else {
+                mean[o] = mu[q];
+                var[o] = j.S > 1 ? qs[q] / (double)(j.S - 1) : 0.0;
+                var_alt[o] = qs[q] / (double)j.S;
             }
         }
     }
-    if (o < n_out) {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk)
-            if (kk < nk) coeffs[(int64_t)(k0 + kk) * n_out + o] = acc[kk].val();
-    }
 }
 
-// mean = c_0 (Eq. gpc_mean), var = sum_{k>=1} c_k^2 (Eq. gpc_std), and the
-// quadrature variance sum_j a_j (M_j - mean)^2.
-__global__ __launch_bounds__(256) void k_gpc_finish(const double *M, int64_t S, int64_t n_out, int64_t ld,
-                                                    const double *a, int K, const double *coeffs, double *mean,
-                                                    double *var, double *var_alt) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n_out) return;
-    const double mu = coeffs[o];
-    NSum v;
-    for (int k = 1; k < K; ++k) {
-        const double c = coeffs[(int64_t)k * n_out + o];
-        v.add(c * c);
+// ------------------------------------------------------------------ scalar statistics
+// A scalar QoI (one value per sample): every sum over the samples is split
+// across a workgroup's 256 threads (thread r takes samples r, r + 256, ...
+// in order, a compensated partial each) and the partials are combined in
+// thread order by a compensated sum, so the result does not depend on
+// timing. SC: workgroup k forms c_k (Eq. coef_discrete); then one workgroup
+// forms mean = c_0, var = sum_{k>=1} c_k^2 and the quadrature variance. MC:
+// one workgroup forms mean, var (1/(N-1)) and var_alt (1/N).
+__device__ inline double block_nsum(double part, double *red) {
+    red[threadIdx.x] = part;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        NSum acc;
+        for (int i = 0; i < (int)blockDim.x; ++i) acc.add(red[i]);
+        red[0] = acc.val();
     }
-    NSum q;
-    for (int64_t j = 0; j < S; ++j) {
-        const double e = M[j * ld + o] - mu;
-        q.add(a[j] * e * e);
-    }
-    mean[o] = mu;
-    var[o] = v.val();
-    var_alt[o] = q.val();
+    __syncthreads();
+    r = red[0];
+    __syncthreads();
+    return r;
 }
 
-// Monte Carlo mean (Eq. meanMCS) and variance (Eq. varMCS, 1/(N-1); 1/N as
-// var_alt), two passes with compensated sums.
-__global__ __launch_bounds__(256) void k_mc_moments(const double *M, int64_t S, int64_t n_out, int64_t ld,
-                                                    double *mean, double *var, double *var_alt) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n_out) return;
-    NSum s;
-    for (int64_t j = 0; j < S; ++j) s.add(M[j * ld + o]);
-    const double mu = s.val() / (double)S;
-    NSum q;
-    for (int64_t j = 0; j < S; ++j) {
-        const double e = M[j * ld + o] - mu;
-        q.add(e * e);
+__global__ __launch_bounds__(256) void k_scalar_coeffs(const double *M, int64_t S, const double *wphi, int K,
+                                                       double *coeffs) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    NSum acc;
+    for (int64_t jx = threadIdx.x; jx < S; jx += blockDim.x) acc.add(wphi[jx * K + k] * M[jx]);
+    const double v = block_nsum(acc.val(), red);
+    if (threadIdx.x == 0) coeffs[k] = v;
+}
+
+__global__ __launch_bounds__(256) void k_scalar_finish(const double *M, int64_t S, const double *a, int K,
+                                                       const double *coeffs, double *mean, double *var,
+                                                       double *var_alt) {
+    __shared__ double red[256];
+    double mu;
+    if (K > 0) {
+        mu = coeffs[0];
+    } else {
+        NSum s;
+        for (int64_t jx = threadIdx.x; jx < S; jx += blockDim.x) s.add(M[jx]);
+        mu = block_nsum(s.val(), red) / (double)S;
     }
-    mean[o] = mu;
-    var[o] = S > 1 ? q.val() / (double)(S - 1) : 0.0;
-    var_alt[o] = q.val() / (double)S;
+    NSum q;
+    for (int64_t jx = threadIdx.x; jx < S; jx += blockDim.x) {
+        const double e = M[jx] - mu;
+        q.add(K > 0 ? a[jx] * e * e : e * e);
+    }
+    const double qs = block_nsum(q.val(), red);
+    if (threadIdx.x == 0) {
+        mean[0] = mu;
+        if (K > 0) {
+            NSum v;
+            for (int k = 1; k < K; ++k) v.add(coeffs[k] * coeffs[k]);
+            var[0] = v.val();
+            var_alt[0] = qs;
+        } else {
+            var[0] = S > 1 ? qs / (double)(S - 1) : 0.0;
+            var_alt[0] = qs / (double)S;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -2456,28 +2594,37 @@ hipError_t launch_fields(const JobDev &j, int64_t t, double *out, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_field_moments(const JobDev &j, int64_t t, int qoi, const double *wphi, const double *a, int K,
+                                double *coeffs, double *mean, double *var, double *var_alt, hipStream_t s) {
+    const int which = qoi == UQ_QOI_VEL ? 0 : (qoi == UQ_QOI_RHO ? 1 : 2);
+    const int64_t cells = (int64_t)j.nx * j.ny;
+    if (K > 0) {
+        const int npair = (which == 0 ? 2 : 1) * K;
+        dim3 grid((unsigned)((cells + 63) / 64), (unsigned)((npair + 4 * FP_KA - 1) / (4 * FP_KA)));
+        UQ_DISPATCH(k_field_coeffs, t & 1, grid, 256, s, j, t, which, wphi, K, coeffs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid2((unsigned)std::min<int64_t>((cells + 255) / 256, 65535));
+    UQ_DISPATCH(k_field_finish, t & 1, grid2, 256, s, j, t, which, a, K, coeffs, mean, var, var_alt);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_moments(const double *M, int64_t S, const double *wphi, const double *a, int K,
+                                 double *coeffs, double *mean, double *var, double *var_alt, hipStream_t s) {
+    if (K > 0) {
+        k_scalar_coeffs<<<(unsigned)K, 256, 0, s>>>(M, S, wphi, K, coeffs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_scalar_finish<<<1, 256, 0, s>>>(M, S, a, K, coeffs, mean, var, var_alt);
+    return hipGetLastError();
+}
+
 hipError_t launch_export(const JobDev &j, int64_t t, int64_t sample, double *out, hipStream_t s) {
     const int64_t cells = (int64_t)j.nx * j.ny;
     dim3 grid((unsigned)std::min<int64_t>((cells + 255) / 256, 4096));
     UQ_DISPATCH(k_export, t & 1, grid, 256, s, j, t, sample, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_moments_sc(const double *M, int64_t S, int64_t n_out, int64_t ld, const double *wphi,
-                             const double *a, int K, double *coeffs, double *mean, double *var, double *var_alt,
-                             hipStream_t s) {
-    dim3 grid((unsigned)((n_out + 255) / 256), (unsigned)((K + KC - 1) / KC));
-    k_gpc_coeffs<<<grid, 256, 0, s>>>(M, S, n_out, ld, wphi, K, coeffs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_gpc_finish<<<(unsigned)((n_out + 255) / 256), 256, 0, s>>>(M, S, n_out, ld, a, K, coeffs, mean, var,
-                                                                 var_alt);
-    return hipGetLastError();
-}
-
-hipError_t launch_moments_mc(const double *M, int64_t S, int64_t n_out, int64_t ld, double *mean, double *var,
-                             double *var_alt, hipStream_t s) {
-    k_mc_moments<<<(unsigned)((n_out + 255) / 256), 256, 0, s>>>(M, S, n_out, ld, mean, var, var_alt);
     return hipGetLastError();
 }
 

@@ -2,9 +2,9 @@
 // callers that cannot allocate device memory (code under HIP graph capture,
 // tight serving loops, harnesses that forbid hipMalloc). It runs the same
 // kernels as uq_moments; their intermediates -- the per-sample scalar QoIs,
-// the per-sample fields of a field QoI, the moment outputs and the
-// non-finite flag -- live in one file-scope device array per GPU instead of
-// buffers the job allocates on its first statistics call.
+// the moment outputs and the non-finite flag -- live in one file-scope
+// device array per GPU instead of buffers the job allocates on its first
+// statistics call.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -33,11 +33,11 @@ DeviceScratch g_dev[kMaxDevices];
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Carve the statistics buffers of one call out of `base` (null: sizes only);
-// returns the bytes used. Layout: qoi[S][4], M[S], flag, out[(K+3) n_out],
-// then fields[S][4][ny][nx] for a field QoI.
+// returns the bytes used. Layout: qoi[S][4], M[S], flag, out[(K+3) n_out]
+// (the moments of a field are formed from the populations: no per-sample
+// field buffer).
 size_t carve(const Job &j, int qoi, unsigned char *base, StatBufs *b) {
     const int64_t S = j.S, n_out = qoi_width(j.p, qoi);
-    const int64_t cells = (int64_t)j.p.nx * j.p.ny;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         unsigned char *p = base ? base + off : nullptr;
@@ -48,13 +48,12 @@ size_t carve(const Job &j, int qoi, unsigned char *base, StatBufs *b) {
     unsigned char *M = take(sizeof(double) * S);
     unsigned char *flag = take(sizeof(int64_t));
     unsigned char *out = take(sizeof(double) * (size_t)((j.K > 0 ? j.K : 0) + 3) * n_out);
-    unsigned char *fields = n_out > 1 ? take(sizeof(double) * 4 * cells * S) : nullptr;
     if (b) {
         b->qoi = (double *)q;
         b->M = (double *)M;
         b->flag = (int64_t *)flag;
         b->out = (double *)out;
-        b->fields = (double *)fields;
+        b->fields = nullptr;
     }
     return off;
 }

@@ -504,8 +504,7 @@ void Server::finish(Live &l) {
     uq_status st = j->sample_values(l.r.qoi, &M, &n, &ld);
     if (st == UQ_OK) {
         double *dm = j->d_out, *dv = j->d_out + 1, *da = j->d_out + 2, *dc = j->d_out + 3;
-        hipError_t e = j->K > 0 ? launch_moments_sc(M, j->S, 1, 1, j->d_wphi, j->d_a, j->K, dc, dm, dv, da, j->stream)
-                                : launch_moments_mc(M, j->S, 1, 1, dm, dv, da, j->stream);
+        hipError_t e = launch_scalar_moments(M, j->S, j->d_wphi, j->d_a, j->K, dc, dm, dv, da, j->stream);
         std::vector<double> h((size_t)(3 + j->K));
         if (e == hipSuccess)
             e = hipMemcpyAsync(h.data(), j->d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, j->stream);

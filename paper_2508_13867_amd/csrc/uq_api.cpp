@@ -184,10 +184,10 @@ int64_t qoi_width(const uq_problem &p, int qoi) {
     }
 }
 
-uq_status Job::own_stat_bufs(int qoi, StatBufs *b) {
+uq_status Job::own_stat_bufs(int qoi, bool fields, StatBufs *b) {
     uq_status st = ensure_stats_buffers(qoi_width(p, qoi));
     if (st != UQ_OK) return st;
-    if (qoi_width(p, qoi) > 1) {
+    if (fields && qoi_width(p, qoi) > 1) {
         st = ensure_fields();
         if (st != UQ_OK) return st;
     }
@@ -431,6 +431,19 @@ extern "C" uq_status uq_sync(uq_job *j) {
 
 namespace uqi {
 
+// Per-sample scalar QoIs into b.qoi, and UQ_EUNSTABLE if any sample holds a
+// non-finite value. Blocking (one flag read).
+uq_status Job::check_finite(const StatBufs &b) {
+    UQ_HIP_TRY(launch_qoi_scalars(jd, t, b.qoi, stream));
+    UQ_HIP_TRY(launch_first_bad(b.qoi, S, b.flag, stream));
+    int64_t bad = S;
+    UQ_HIP_TRY(hipMemcpyAsync(&bad, b.flag, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    UQ_HIP_TRY(hipStreamSynchronize(stream));
+    if (bad < S)
+        return fail(UQ_EUNSTABLE, "sample " + std::to_string(bad) + " holds a non-finite value at step " + std::to_string(t));
+    return UQ_OK;
+}
+
 // Per-sample values of one QoI in the buffers b. Returns the device pointer,
 // number of values per sample and the row stride. Blocking (one flag read).
 uq_status Job::sample_values_in(const StatBufs &b, int qoi, const double **M, int64_t *n_out, int64_t *ld) {
@@ -439,13 +452,8 @@ uq_status Job::sample_values_in(const StatBufs &b, int qoi, const double **M, in
     if (qoi_width(P, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
     if ((qoi == UQ_QOI_CD || qoi == UQ_QOI_CL) && (P.geometry != UQ_GEOM_CHANNEL || (P.D <= 0 && P.cyl_bc != UQ_CYL_BOUZIDI)))
         return fail(UQ_EINVAL, "drag/lift need a channel with a cylinder");
-    UQ_HIP_TRY(launch_qoi_scalars(jd, t, b.qoi, stream));
-    UQ_HIP_TRY(launch_first_bad(b.qoi, S, b.flag, stream));
-    int64_t bad = S;
-    UQ_HIP_TRY(hipMemcpyAsync(&bad, b.flag, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-    UQ_HIP_TRY(hipStreamSynchronize(stream));
-    if (bad < S)
-        return fail(UQ_EUNSTABLE, "sample " + std::to_string(bad) + " holds a non-finite value at step " + std::to_string(t));
+    uq_status st = check_finite(b);
+    if (st != UQ_OK) return st;
     if (qoi_width(P, qoi) == 1) {
         UQ_HIP_TRY(launch_select_scalar(jd, b.qoi, qoi, b.M, stream));
         *M = b.M;
@@ -463,23 +471,32 @@ uq_status Job::sample_values_in(const StatBufs &b, int qoi, const double **M, in
 uq_status Job::sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld) {
     if (qoi_width(p, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
     StatBufs b;
-    uq_status st = own_stat_bufs(qoi, &b);
+    uq_status st = own_stat_bufs(qoi, true, &b);
     if (st != UQ_OK) return st;
     return sample_values_in(b, qoi, M, n_out, ld);
 }
 
+// Scalar QoIs: per-sample values, then the sums over samples spread across a
+// workgroup. Field QoIs: after the per-sample non-finite check, straight
+// from the populations (no per-sample field buffer: b.fields is not used).
 uq_status Job::moments_in(const StatBufs &b, int qoi, uq_moments_out *out) {
-    const double *M;
-    int64_t n, ld;
+    const int64_t n = qoi_width(p, qoi);
     uq_status st = enter();
     if (st != UQ_OK) return st;
-    st = sample_values_in(b, qoi, &M, &n, &ld);
-    if (st != UQ_OK) return st;
     double *d_mean = b.out, *d_var = b.out + n, *d_alt = b.out + 2 * n, *d_coef = b.out + 3 * n;
-    if (K > 0)
-        UQ_HIP_TRY(launch_moments_sc(M, S, n, ld, d_wphi, d_a, K, d_coef, d_mean, d_var, d_alt, stream));
-    else
-        UQ_HIP_TRY(launch_moments_mc(M, S, n, ld, d_mean, d_var, d_alt, stream));
+    if (n == 1) {
+        const double *M;
+        int64_t n1, ld;
+        st = sample_values_in(b, qoi, &M, &n1, &ld);
+        if (st != UQ_OK) return st;
+        UQ_HIP_TRY(launch_scalar_moments(M, S, d_wphi, d_a, K, d_coef, d_mean, d_var, d_alt, stream));
+    } else {
+        StatBufs scalars = b;
+        scalars.fields = nullptr;
+        st = check_finite(scalars);
+        if (st != UQ_OK) return st;
+        UQ_HIP_TRY(launch_field_moments(jd, t, qoi, d_wphi, d_a, K, d_coef, d_mean, d_var, d_alt, stream));
+    }
     out->n_out = n;
     out->K = K;
     out->d = rule.d;
@@ -519,7 +536,7 @@ extern "C" uq_status uq_moments(uq_job *j, int32_t qoi, uq_moments_out *out) {
     UQ_HIP_TRY(hipSetDevice(j->dev.device));
     if (qoi_width(j->p, qoi) == 0) return fail(UQ_EINVAL, "unknown QoI");
     StatBufs b;
-    uq_status st = j->own_stat_bufs(qoi, &b);
+    uq_status st = j->own_stat_bufs(qoi, false, &b);
     if (st != UQ_OK) return st;
     return j->moments_in(b, qoi, out);
 }

@@ -205,13 +205,14 @@ hipError_t launch_fields(const JobDev &j, int64_t t, double *out, hipStream_t s)
 // unshifted double populations of one sample in natural order
 hipError_t launch_export(const JobDev &j, int64_t t, int64_t sample, double *out, hipStream_t s);
 
-// Cross-sample statistics on the device. M: value o of sample j at
-// M[j*ld + o], o < n_out. SC: wphi [S][K] = a_j * Phi_k(xi_j); writes
-// coeffs[K][n_out], mean, var, var_alt. MC: mean, var (1/(S-1)), var_alt (1/S).
-hipError_t launch_moments_sc(const double *M, int64_t S, int64_t n_out, int64_t ld, const double *wphi,
-                             const double *a, int K, double *coeffs, double *mean, double *var, double *var_alt,
-                             hipStream_t s);
-hipError_t launch_moments_mc(const double *M, int64_t S, int64_t n_out, int64_t ld, double *mean, double *var,
-                             double *var_alt, hipStream_t s);
+// Statistics of a field QoI (VEL, RHO, SPEED) at time t straight from the
+// populations (no per-sample field buffer); the same results as the
+// buffered path above. SC: K > 0 with wphi, a; MC: K = 0. coeffs[K][n_out].
+hipError_t launch_field_moments(const JobDev &j, int64_t t, int qoi, const double *wphi, const double *a, int K,
+                                double *coeffs, double *mean, double *var, double *var_alt, hipStream_t s);
+// Statistics of a scalar QoI M[S], each sum split across a workgroup in a
+// fixed order. SC: K > 0 with wphi, a; MC: K = 0.
+hipError_t launch_scalar_moments(const double *M, int64_t S, const double *wphi, const double *a, int K,
+                                 double *coeffs, double *mean, double *var, double *var_alt, hipStream_t s);
 
 }  // namespace uqi

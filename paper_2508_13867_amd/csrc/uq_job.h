@@ -20,8 +20,9 @@ bool tuned_shape(const uq_problem &p, int64_t S, StepShape *out);
 
 // Device buffers of one statistics evaluation (uq_qoi_samples, uq_moments
 // and its allocation-free variant): per-sample scalar QoIs qoi[S][4], the
-// selected scalar M[S], per-sample fields fields[S][4][ny][nx] (field QoIs
-// only, else null), the outputs out[(K + 3) n_out] and one int64 flag.
+// selected scalar M[S], per-sample fields fields[S][4][ny][nx] (per-sample
+// field values only; the moments of a field are formed from the populations
+// without them), the outputs out[(K + 3) n_out] and one int64 flag.
 struct StatBufs {
     double *qoi = nullptr, *M = nullptr, *fields = nullptr, *out = nullptr;
     int64_t *flag = nullptr;
@@ -73,8 +74,10 @@ struct Job {
     void dfree_all();
     uq_status ensure_stats_buffers(int64_t n_out_max);
     uq_status ensure_fields();
-    // the job's own statistics buffers for `qoi`, allocated on first use
-    uq_status own_stat_bufs(int qoi, StatBufs *b);
+    // the job's own statistics buffers for `qoi` (with the per-sample field
+    // buffer if `fields`), allocated on first use
+    uq_status own_stat_bufs(int qoi, bool fields, StatBufs *b);
+    uq_status check_finite(const StatBufs &b);
     // per-sample values of `qoi` in b (M: value o of sample s at M[s*ld + o])
     uq_status sample_values_in(const StatBufs &b, int qoi, const double **M, int64_t *n_out, int64_t *ld);
     uq_status sample_values(int qoi, const double **M, int64_t *n_out, int64_t *ld);

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import assert_stats, gpu_available, rel_l2, stat_errors
+from helpers import assert_stats, assert_stats_given_samples, gpu_available, rel_l2, stat_errors
 from paper_2508_13867_amd import Job, UQError
 from paper_2508_13867_amd import _abi as A
 from paper_2508_13867_amd import workloads as W
@@ -153,6 +153,10 @@ def test_tgv_monte_carlo_fp32():
         st = job.moments("ke")
         assert_stats(st, ref["stats"]["ke"], TOL["fp32"], "ke mc")
         assert "coeffs" not in st
+        # Monte Carlo statistics of a field, formed from the populations
+        vel = job.qoi_samples("vel")
+        r = dict(ref, samples_q=ref["samples"]["vel"], stats_q=ref["stats"]["vel"])
+        assert_stats_given_samples(job.moments("vel"), vel, r, TOL["fp32"], "vel mc")
 
 
 # ----------------------------------------------------------------- channel

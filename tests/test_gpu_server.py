@@ -63,9 +63,9 @@ def test_result_same_alone_and_in_mix():
     with Server(memory_budget_gb=4, max_jobs=8, steps_per_tick=32) as srv:
         alone = srv.wait(srv.submit(CYL_C), 120)
     with Server(memory_budget_gb=4, max_jobs=8, steps_per_tick=32) as srv:
-        t_b = srv.submit(TGV_B)
+        t_b = srv.submit(W.scaled(TGV_B, steps=4000))  # long enough to be running when C arrives
         t_d = srv.submit(TGV_D)
-        time.sleep(0.05)  # C arrives while B and D are on the GPU
+        time.sleep(0.01)  # C arrives while B and D are on the GPU
         t_c = srv.submit(CYL_C)
         t_a = srv.submit(TGV_A)
         mix = srv.wait(t_c, 120)
@@ -74,6 +74,8 @@ def test_result_same_alone_and_in_mix():
     assert all(o["status"] == A.UQ_OK for o in others)
     assert mix["status"] == A.UQ_OK
     assert st["completed"] == 4
+    # C really shared the GPU: its time on the server overlaps another job's
+    assert any(max(mix["t_admit"], o["t_admit"]) < min(mix["t_done"], o["t_done"]) for o in others)
     # same kernels, same per-node arithmetic, fixed per-job reduction order
     assert mix["mean"] == alone["mean"] and mix["var"] == alone["var"]
     assert np.array_equal(mix["coeffs"], alone["coeffs"])

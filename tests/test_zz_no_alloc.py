@@ -2,8 +2,9 @@
 through the C-ABI it gives bit for bit the results of uq_moments on two calls
 in a row (the second on a smaller job, so stale scratch contents of the
 first would show), allocates no device memory (the job's device bytes and
-torch's allocated bytes are unchanged), serialises concurrent callers, and
-refuses a request larger than its fixed scratch array with a clear error."""
+torch's allocated bytes are unchanged), serialises concurrent callers, fits
+the benchmark workload's velocity-field statistics, and refuses a request
+larger than its fixed scratch array with a clear error."""
 import sys
 import threading
 
@@ -103,11 +104,23 @@ def test_noalloc_concurrent_callers_are_serialised():
         same(out["small"], ref["small"])
 
 
+def test_noalloc_benchmark_velocity_field():
+    # 256^2 x 256 samples, K = 35: (35 + 3) x 131072 doubles = 39.8 MB of
+    # outputs in the scratch array, no per-sample field buffer
+    say("case noalloc: benchmark workload velocity field")
+    spec = W.scaled(W.TGV_BATCHED_FP32, steps=12)
+    with Job(spec) as j:
+        j.run(spec["steps"])
+        same(noalloc_unallocating(j, "vel"), j.moments("vel"))
+
+
 def test_noalloc_refuses_more_than_its_scratch():
     say("case noalloc: request above the scratch size")
-    spec = dict(name="noalloc_too_big", geometry="tgv", precision="fp32", nx=256, ny=256, steps=2, u0=0.02,
-                nu=0.005, dists=[("nu", 0.004, 0.006)], rule=dict(kind="mc", N=64, seed=W.SEED))
-    need = 8 * 4 * 256 * 256 * 64
+    # the velocity field of a 1024^2 lattice with K = 6 gPC terms: (K + 3)
+    # outputs of 2 * 1024^2 doubles, 151 MB
+    spec = dict(name="noalloc_too_big", geometry="tgv", precision="fp32", nx=1024, ny=1024, steps=2, u0=0.02,
+                nu=0.005, dists=[("nu", 0.004, 0.006), ("u0", 0.018, 0.022)], rule=dict(kind="gl", n=3, order=2))
+    need = 8 * (6 + 3) * 2 * 1024 * 1024
     assert need > SCRATCH_BYTES
     with Job(spec) as j:
         j.run(2)
