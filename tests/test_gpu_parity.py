@@ -678,6 +678,35 @@ def test_full_row_kernel_seven_and_eight_steps(prec, nx, ny, rows, n, monkeypatc
         assert np.abs(res[str(n)] - ref).max() < 1e-6
 
 
+@pytest.mark.parametrize("nx, ny", [(384, 12), (512, 9), (450, 20)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16s"])
+def test_full_row_kernel_wide_rows(prec, nx, ny, monkeypatch):
+    # rows of 384..512 columns: three or four waves of two columns per lane
+    # per level, 4 steps per launch (16 waves); 450 leaves lanes past the
+    # lattice. Bit for bit the single-step result; FP32 also against the
+    # oracle on one sample
+    monkeypatch.setenv("UQ_FUSE_TY", "8")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision=prec)
+    say("case wide rows", prec, nx, ny)
+    steps = 4 * 3 + 3
+    res = {}
+    for fuse in ("0", "4"):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        with Job(spec) as job:
+            assert job.info().fused == (4 if fuse == "4" else 0)
+            assert fuse == "0" or job.info().fused_window == 2
+            job.run(steps)
+            res[fuse] = job.populations(3)
+    assert np.array_equal(res["0"], res["4"])
+    if prec == "fp32":
+        with Job(spec) as job:
+            xi, _ = job.samples()
+        p = O.sample_params(spec, xi[3])
+        ref = O.tgv_run(nx, ny, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+        assert np.abs(res["4"] - ref).max() < 1e-6
+
+
 @pytest.mark.parametrize("steps, launches", [(3, 1), (5, 1), (7, 3), (8, 2), (13, 3), (20, 4), (25, 5)])
 def test_steps_left_over_run_as_odd_fused_launches(steps, launches, monkeypatch):
     # 6 steps per launch in pairs (12); what is left goes in odd fused
