@@ -424,8 +424,10 @@ uq_status uq_autotune(const uq_problem *p, const uq_device *dev, int64_t steps, 
  * per launch over whole rows (N from the launch-shape tuner's measurement of
  * the job's class when it has one, else the largest that fits: vortex 8, 6
  * or 4, channel 4, 3 or 2), one launch for all jobs that share a kernel
- * instance; the other jobs (FP64, rows too wide) run in the AA layout, one
- * launch per step for all of them. Jobs of different lattices, geometries,
+ * instance; vortex lattices too wide for whole rows run 4 steps per launch
+ * in column strips when their two slabs take at most a quarter of the
+ * arena; the other jobs (FP64, wide channels, very large vortex jobs) run in
+ * the AA layout, one launch per step for all of them. Jobs of different lattices, geometries,
  * sample counts and step parities share launches. A job with fewer steps
  * left than a tick takes its last steps in launches of its own. PLAIN mode
  * runs one job at a time and one sample per launch per step (AA), with no

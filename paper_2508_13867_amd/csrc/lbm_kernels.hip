@@ -967,19 +967,31 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
 // chunks, against 45 % for the 8-row tiles above), and every address that
 // depends on the row is wave-uniform (scalar registers): a lane keeps one
 // column for the whole strip.
+// Between two levels each direction is read once, by the row that pulls it:
+// c_y = -1 directions one iteration after they are written (rows kept: 2),
+// c_y = 0 two iterations after (3), c_y = +1 three after (4). Rows are
+// offset by 12 (a multiple of 2, 3 and 4) to keep slots positive.
+template <int P, int N>
+struct WindowRings {
+    static constexpr int NR = N > 1 ? N - 1 : 1;
+    using C = typename Prec<P>::C;
+    C ra[NR][2][3][64], rb[NR][3][3][64], rc[NR][4][3][64];
+};
+
+// One work item of the strip window: strip `strip` (columns [strip W,
+// strip W + W)) of rows [chunk H, chunk H + H) of sample smp, N steps, from
+// the slab src2 names to the other one; the wave's level is lvl. Ends with
+// a barrier, so the rings may be reused by the next item at once.
 template <int P, int N, int D>
-__global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, int strips, int H, int chunks,
-                                                  int64_t nwork, bool nt) {
+__device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, int H, int64_t smp, int chunk,
+                                           int strip, bool nt, int lvl, WindowRings<P, N> &rings) {
     using PR = Prec<P>;
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int RG = N - 1;
-    // Between two levels each direction is read once, by the row that pulls
-    // it: c_y = -1 directions one iteration after they are written (rows
-    // kept: 2), c_y = 0 two iterations after (3), c_y = +1 three after (4).
-    // Rows are offset by 12 (a multiple of 2, 3 and 4) to keep slots positive.
-    constexpr int NR = N > 1 ? N - 1 : 1;
-    __shared__ C ra[NR][2][3][64], rb[NR][3][3][64], rc[NR][4][3][64];
+    auto &ra = rings.ra;
+    auto &rb = rings.rb;
+    auto &rc = rings.rc;
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -987,14 +999,7 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
     const int plane_b = plane * (int)sizeof(T), pitch_b = pitch * (int)sizeof(T);
     const float inv = j.inv_scale, sc = j.scale;
     const int lane = threadIdx.x & 63;
-    // level of this wave, rotated with the workgroup index so that the levels'
-    // different instruction mixes spread evenly over a CU's SIMDs
-    const int lvl = __builtin_amdgcn_readfirstlane((int)((threadIdx.x >> 6) + blockIdx.x) % N) + 1;  // 1..N
-    const int64_t G = gridDim.x;
-    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const int64_t smp = wk / ((int64_t)chunks * strips);
-        const int rem = (int)(wk - smp * chunks * strips);
-        const int chunk = rem / strips, strip = rem - chunk * strips;
+    {
         const int x0 = strip * W, w = min(W, nx - x0);
         const int yb = chunk * H, ye = min(ny, yb + H);
         const T *src = src_all + smp * 9 * (int64_t)plane;
@@ -1095,6 +1100,28 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
                 __syncthreads();
             }
         }
+    }
+}
+
+// level of a wave of the strip window, rotated with the workgroup index so
+// that the levels' different instruction mixes spread evenly over a CU's
+// SIMDs
+template <int N>
+__device__ inline int window_level() {
+    return __builtin_amdgcn_readfirstlane((int)((threadIdx.x >> 6) + blockIdx.x) % N) + 1;  // 1..N
+}
+
+template <int P, int N, int D>
+__global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, int strips, int H, int chunks,
+                                                  int64_t nwork, bool nt) {
+    __shared__ WindowRings<P, N> rings;
+    const int lvl = window_level<N>();
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const int64_t smp = wk / ((int64_t)chunks * strips);
+        const int rem = (int)(wk - smp * chunks * strips);
+        const int chunk = rem / strips;
+        stepW_item<P, N, D>(j, src2, W, H, smp, chunk, rem - chunk * strips, nt, lvl, rings);
     }
 }
 
@@ -1358,6 +1385,25 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR_multi(const FusedJob *jobs
         const int64_t local = wk - q.work0;
         const int64_t smp = local / q.chunks;
         stepR_item<P, N, K, M, D>(j, ((q.par ^ launch) & 1) != 0, q.H, smp, (int)(local - smp * q.chunks), nt, rg);
+    }
+}
+
+// Batched strip window (see k_stepR_multi): every strip of every row chunk
+// of every sample of every job in the table, N steps per launch.
+template <int P, int N, int D>
+__global__ __launch_bounds__(64 * N) void k_stepW_multi(const FusedJob *jobs, int njobs, int64_t nwork, int launch) {
+    __shared__ WindowRings<P, N> rings;
+    const int lvl = window_level<N>();
+    const int64_t G = gridDim.x;
+    for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
+        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const JobDev j = q.j;
+        const int64_t local = wk - q.work0;
+        const int64_t smp = local / ((int64_t)q.chunks * q.strips);
+        const int rem = (int)(local - smp * q.chunks * q.strips);
+        const int chunk = rem / q.strips;
+        stepW_item<P, N, D>(j, ((q.par ^ launch) & 1) != 0, q.W, q.H, smp, chunk, rem - chunk * q.strips, false, lvl,
+                            rings);
     }
 }
 
@@ -2306,11 +2352,18 @@ static void stepN_p(const JobDev &j, bool src2, int fty, hipStream_t s) {
     }
 }
 
+// strips of at most 64 - 2(N - 1) columns (a wave's 64 lanes less the ring
+// of N - 1 columns per side), balanced
+void window_strips(int nx, int n, int *W, int *strips) {
+    const int wmax = 64 - 2 * (n - 1);
+    *strips = (nx + wmax - 1) / wmax;
+    *W = (nx + *strips - 1) / *strips;
+}
+
 template <int P, int N>
 static void stepW_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {
-    const int wmax = 64 - 2 * (N - 1);
-    const int strips = (j.nx + wmax - 1) / wmax;
-    const int W = (j.nx + strips - 1) / strips;  // balanced strips
+    int W, strips;
+    window_strips(j.nx, N, &W, &strips);
     const int H = std::max(8, std::min(rows, j.ny));
     const int chunks = (j.ny + H - 1) / H;
     const int64_t nwork = (int64_t)j.S * strips * chunks;
@@ -2426,12 +2479,17 @@ static void stepRC_p(const JobDev &j, const int64_t *d_t, int k, bool src2, int 
 }
 
 // ------------------------------------------------------------------ batched fused launches
-// One launch of a batched full-row instance (kind 0: periodic, k_stepR_multi;
-// kind 1: channel, k_stepRC_multi): every work item of the table's jobs. The
-// server keeps to N in {4, 6, 8} (periodic) and {2, 3, 4} (channel) and to
-// single precision storage (FP32, FP16S, BF16S), so that a tick of 48 steps
-// holds a whole number of launch pairs of every instance.
+// One launch of a batched fused instance (kind 0: periodic rows,
+// k_stepR_multi; kind 1: channel rows, k_stepRC_multi; kind 2: periodic
+// strips, k_stepW_multi): every work item of the table's jobs. The server
+// keeps to N in {4, 6, 8} (periodic rows), {2, 3, 4} (channel) and 4 (strips)
+// and to single precision storage (FP32, FP16S, BF16S), so that a tick of 48
+// steps holds a whole number of launch pairs of every instance.
 int rows_instance(int kind, int prec, int n, int nx, int *K, int *M) {
+    if (kind == 2) {  // strips: any width
+        *K = *M = 0;
+        return 1;
+    }
     return rows_shape(prec, n, kind == 0 ? RING_ROWS_TGV : RING_ROWS_CH, nx, K, M);
 }
 
@@ -2463,6 +2521,12 @@ static bool multi_n(int kind, int K, int M, const FusedJob *jobs, int njobs, int
 template <int P>
 static bool multi_p(int kind, int n, int K, int M, const FusedJob *jobs, int njobs, int64_t nwork, int launch,
                     hipStream_t s) {
+    if (kind == 2) {
+        if (n != 4) return false;
+        const int64_t G = std::min<int64_t>(nwork, 0x7fffffff);
+        k_stepW_multi<P, 4, 3><<<(unsigned)G, 256, 0, s>>>(jobs, njobs, nwork, launch);
+        return true;
+    }
     if (kind == 0) {
         if (n == 4) return multi_n<P, 4>(0, K, M, jobs, njobs, nwork, launch, s);
         if (n == 6) return multi_n<P, 6>(0, K, M, jobs, njobs, nwork, launch, s);
@@ -2477,6 +2541,7 @@ static bool multi_p(int kind, int n, int K, int M, const FusedJob *jobs, int njo
 
 bool fused_multi_supported(int kind, int prec, int n, int K, int M) {
     if (prec == UQ_FP64) return false;
+    if (kind == 2) return n == 4;
     if (kind == 0 ? (n != 4 && n != 6 && n != 8) : (n < 2 || n > 4)) return false;
     return rows_fit(prec, n, kind == 0 ? RING_ROWS_TGV : RING_ROWS_CH, K, M);
 }

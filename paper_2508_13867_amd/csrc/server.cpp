@@ -128,8 +128,9 @@ static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 // The batched instance that carries a job: periodic vortex lattices (kind
 // 0) and channels whose boundary rules are node-local (kind 1: half-way
 // walls and cylinder, Zou-He or wall or periodic ends) advance N steps per
-// launch over whole rows of H-row chunks in the AB layout; kind -1: one step
-// per launch in the AA layout (the batched single-step kernel). A shape the
+// launch over whole rows of H-row chunks in the AB layout; vortex lattices
+// too wide for whole rows, 4 steps per launch in strips (kind 2); kind -1:
+// one step per launch in the AA layout (the batched single-step kernel). A shape the
 // launch-shape tuner measured for the job's class is taken when it is a
 // batched instance; otherwise N is the largest of the instance's choices
 // whose LDS rings fit the row width (vortex 8, 6, 4; channel 4, 3, 2), the
@@ -137,9 +138,12 @@ static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 // chunks so that its samples fill the GPU (at most 8, as the tuner tries).
 struct ServeShape {
     int kind = -1, N = 0, K = 0, M = 0, H = 0;
+    int W = 0, strips = 1;
 };
 
-static ServeShape serve_shape(const uq_problem &p, int64_t S) {
+int64_t job_footprint(const uq_problem &p, int64_t S, int K, bool ab);
+
+static ServeShape serve_shape(const uq_problem &p, int64_t S, int K, size_t arena) {
     ServeShape sh;
     if (p.precision == UQ_FP64) return sh;
     const int64_t b = storage_bytes(p.precision);
@@ -149,6 +153,7 @@ static ServeShape serve_shape(const uq_problem &p, int64_t S) {
     if (p.geometry == UQ_GEOM_TGV) kind = 0;
     else if (p.geometry == UQ_GEOM_CHANNEL && !needs_ab(p) && p.cyl_bc == UQ_CYL_HALFWAY) kind = 1;
     if (kind < 0) return sh;
+    sh.W = p.nx;
     const int pref[2][3] = {{8, 6, 4}, {4, 3, 2}};
     StepShape tuned;
     const bool have = tuned_shape(p, S, &tuned) && tuned.fwin == 2 && tuned.fuse >= 2;
@@ -171,6 +176,15 @@ static ServeShape serve_shape(const uq_problem &p, int64_t S) {
             sh.H = std::max(8, (p.ny + chunks - 1) / chunks);
         }
         return sh;
+    }
+    // vortex rows too wide for any whole-row instance: 4 steps per launch
+    // in strips, if the job's two slabs take at most a quarter of the arena
+    // (a larger job would hold back every other admission; it runs in AA)
+    if (kind == 0 && (size_t)job_footprint(p, S, K, true) <= arena / 4) {
+        sh.kind = 2;
+        sh.N = 4;
+        sh.H = std::max(8, std::min(64, p.ny));
+        window_strips(p.nx, sh.N, &sh.W, &sh.strips);
     }
     return sh;
 }
@@ -309,7 +323,7 @@ void Server::admit() {
         if (r.shape.kind >= 0) {
             sh.layout = UQ_LAYOUT_AB;
             sh.fuse = r.shape.N;
-            sh.fwin = 2;
+            sh.fwin = r.shape.kind == 2 ? 1 : 2;
             sh.fty = r.shape.H;
         } else {
             sh.layout = UQ_LAYOUT_AA;
@@ -386,9 +400,11 @@ uq_status Server::rebuild_table() {
         f.d_t = l.job->d_t;
         f.H = h.H;
         f.chunks = (l.r.p.ny + h.H - 1) / h.H;
+        f.W = h.W;
+        f.strips = h.strips;
         f.work0 = g.nwork;
         f.par = (int32_t)(l.job->t & 1);
-        g.nwork += l.job->S * f.chunks;
+        g.nwork += l.job->S * f.chunks * f.strips;
         ++g.count;
         fused.push_back(f);
         tptrs.push_back(l.job->d_t);
@@ -667,7 +683,7 @@ extern "C" uq_status uq_server_submit(uq_server *s, const uq_problem *p, int64_t
     q.qoi = qoi;
     q.S = r.S;
     q.K = r.K;
-    if (s->cfg.mode == UQ_SERVE_BATCHED) q.shape = serve_shape(*p, r.S);
+    if (s->cfg.mode == UQ_SERVE_BATCHED) q.shape = serve_shape(*p, r.S, r.K, s->arena.capacity());
     q.footprint = job_footprint(*p, r.S, r.K, q.shape.kind >= 0);
     if ((size_t)q.footprint > s->arena.capacity())
         return fail(UQ_ENOMEM, "job needs " + std::to_string(q.footprint) + " B, more than the server's memory budget");

@@ -125,8 +125,10 @@ struct alignas(16) MultiJob {
 struct alignas(16) FusedJob {
     JobDev j;
     const int64_t *d_t;  // the job's device step count (inflow ramp)
-    int64_t work0;       // first work item: the job has S * chunks of them
+    int64_t work0;       // first work item: the job has S * chunks * strips
     int32_t H, chunks;   // rows per chunk, chunks per sample
+    int32_t W, strips;   // strip window: columns per strip, strips per row
+                         // (whole rows: W = nx, strips = 1)
     int32_t par;         // t & 1 of the job at the start of the tick
     int32_t pad;
 };
@@ -173,14 +175,18 @@ int channel_rows_max_nx(int prec, int n);
 // widest lattice the full-row kernel takes at this precision and N (0: none)
 int full_rows_max_nx(int prec, int n);
 bool fused_supported(const JobDev &j);
-// Batched full-row launches (continuous batching with temporal blocking).
-// kind 0: periodic lattice, kind 1: channel. rows_instance gives the waves
-// per level K and columns per lane M of the N-step instance for rows nx
-// wide (0 if none fits); fused_multi_supported says whether the batched
-// form of that instance exists (N in {4, 6, 8} periodic, {2, 3, 4} channel;
-// single-precision storage formats).
+// Batched fused launches (continuous batching with temporal blocking).
+// kind 0: periodic lattice over whole rows, kind 1: channel over whole rows,
+// kind 2: periodic lattice in strips of at most 64 - 2(N - 1) columns (any
+// width). rows_instance gives the waves per level K and columns per lane M
+// of the N-step whole-row instance for rows nx wide (0 if none fits);
+// fused_multi_supported says whether the batched form of an instance exists
+// (N in {4, 6, 8} periodic rows, {2, 3, 4} channel rows, 4 strips; single-
+// precision storage formats). window_strips gives the strips per row and
+// their width for N steps.
 int rows_instance(int kind, int prec, int n, int nx, int *K, int *M);
 bool fused_multi_supported(int kind, int prec, int n, int K, int M);
+void window_strips(int nx, int n, int *W, int *strips);
 // launch number `launch` of a tick: every work item of jobs[0..njobs)
 hipError_t launch_fused_multi(int kind, int prec, int n, int K, int M, const FusedJob *jobs, int njobs,
                               int64_t nwork, int launch, hipStream_t s);

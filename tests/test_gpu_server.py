@@ -98,17 +98,20 @@ def test_plain_mode_agrees_with_batched():
 def test_batched_instances_equal_standalone_single_steps(prec):
     # jobs that land in different batched instances (vortex rows of 64, 200,
     # 256 and 384 columns: one or two columns per lane, 8 or 4 steps per
-    # launch; channels of 220 and 440 columns: 4 or 3 steps) and one that
-    # runs the single-step AA launch (a 640-column vortex), with step counts
-    # that leave the last steps to each job's own launches: every result is
-    # bitwise that of the job alone, one step per launch
+    # launch; a 640-column vortex in strips of 4 steps; channels of 220 and
+    # 440 columns: 4 or 3 steps) and one that runs the single-step AA launch
+    # (a 616-column channel), with step counts that leave the last steps to
+    # each job's own launches: every result is bitwise that of the job
+    # alone, one step per launch
     say("case batched instances", prec)
     tgv = dict(geometry="tgv", precision=prec, u0=0.02, nu=0.005, dists=[("nu", 0.004, 0.006), ("u0", 0.018, 0.022)],
                rule=dict(kind="gl", n=2, order=1))
     specs = [dict(tgv, name=f"v{n}", nx=n, ny=n // 2 + 3, steps=steps) for n, steps in
              ((64, 211), (200, 157), (256, 130), (384, 101), (640, 53))]
     specs += [dict(CYL_C, name="c220", precision=prec, steps=233),
-              dict(CYL_C, name="c440", precision=prec, nx=440, ny=82, D=20, cx=40, cy=41, steps=149, ramp=60)]
+              dict(CYL_C, name="c440", precision=prec, nx=440, ny=82, D=20, cx=40, cy=41, steps=149, ramp=60),
+              dict(CYL_C, name="c616", precision=prec, nx=616, ny=115, D=28, cx=56, cy=57, nu=0.07, steps=61,
+                   ramp=30)]
     with Server(memory_budget_gb=4, max_jobs=16, steps_per_tick=48, precision=prec) as srv:
         ts = [srv.submit(s) for s in specs]
         rs = [srv.wait(t, 120) for t in ts]
