@@ -92,35 +92,29 @@ def copy_probe(torch, nbytes=1207959552, reps=10):
 
 
 def serving(U, W, n_jobs, load, log):
-    """Replay one seeded Poisson trace of mixed UQ jobs through the
-    continuous-batching server and through the plain server (one job at a
-    time, one sample per launch, no graph; same kernels): solves/hour, job
-    latency percentiles (completion - arrival), aggregate MLUPS, and the
-    largest relative difference between the two modes' moments."""
-    trace = W.serving_trace(n_jobs=n_jobs, load=load)
-    out = {"jobs": n_jobs, "load": load, "trace_seed": W.SEED,
-           "trace_work_node_updates": sum(s["work"] for _, s in trace)}
+    """The light serving trace (W.serving_trace: vortices 64^2..256^2 and
+    channels D 10..20): first the batched server's capacity with every job
+    submitted at once, then one seeded Poisson arrival schedule at `load`
+    times that capacity replayed through the batched server and through the
+    plain one (one job at a time, one sample per launch, no graph; the same
+    arithmetic): solves/hour, job latency percentiles (completion -
+    arrival), aggregate MLUPS, and the largest relative difference between
+    the two modes' moments."""
+    trace = W.serving_trace(n_jobs=n_jobs)
+    jobs = [spec for _, spec in trace]
+    work = sum(s["work"] for s in jobs)
+    out = {"jobs": n_jobs, "load": load, "trace_seed": W.SEED, "trace_work_node_updates": work}
+    log("bench: serving trace, batched capacity (all jobs at once)")
+    res, st = _replay(U, jobs, [0.0] * n_jobs, "batched", 32, log, max_jobs=64)
+    cap = work / st["elapsed_s"]
+    out["batched_capacity"] = dict(_serving_summary(res, st, [0.0]), node_updates_per_s=round(cap, 1))
+    arrivals = W.poisson_arrivals(jobs, cap, load)
     means = {}
     for mode in ("batched", "plain"):
-        log(f"bench: serving trace, {mode} mode")
-        with U.Server(memory_budget_gb=32, max_jobs=64, steps_per_tick=64, mode=mode) as srv:
-            t0 = time.perf_counter()
-            tickets = []
-            for arrival, spec in trace:
-                dt = arrival - (time.perf_counter() - t0)
-                if dt > 0:
-                    time.sleep(dt)
-                tickets.append(srv.submit(spec))
-            results = [srv.wait(t, 900) for t in tickets]
-            st = srv.stats()
-        bad = [r for r in results if r["status"] != 0]
-        lat = sorted(r["latency_s"] for r in results)
-        means[mode] = [(r["mean"], r["var"]) for r in results]
-        out[mode] = {"solves_per_hour": round(st["solves_per_hour"], 1), "p50_s": round(st["latency_p50_s"], 4),
-                     "p99_s": round(st["latency_p99_s"], 4), "mean_latency_s": round(st["latency_mean_s"], 4),
-                     "mlups": round(st["mlups"], 1), "makespan_s": round(st["elapsed_s"], 3),
-                     "failed": len(bad), "arena_peak_gb": round(st["arena_peak_bytes"] / 2 ** 30, 3),
-                     "max_latency_s": round(lat[-1], 4)}
+        log(f"bench: serving trace at {load}x the batched capacity, {mode} mode")
+        res, st = _replay(U, jobs, arrivals, mode, 32, log, max_jobs=64)
+        means[mode] = [(r["mean"], r["var"]) for r in res]
+        out[mode] = _serving_summary(res, st, arrivals)
         log(f"bench: {mode}: {out[mode]}")
     diff = 0.0
     for (mb, vb), (mp, vp) in zip(means["batched"], means["plain"]):
@@ -534,7 +528,8 @@ def main():
     ap.add_argument("--study-precision", default="fp32", choices=["fp64", "fp32"],
                     help="storage precision of the wasserstein study")
     ap.add_argument("--serving-jobs", type=int, default=24)
-    ap.add_argument("--serving-load", type=float, default=1.2)
+    ap.add_argument("--serving-load", type=float, default=1.5, help="offered load of the serving trace, "
+                    "as a multiple of the batched capacity measured first")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip tuning (shapes then come from UQ_TUNE_CACHE or the defaults)")
     args = ap.parse_args()
