@@ -109,6 +109,17 @@ __device__ constexpr int OPPd[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // index of a direction among the three that share its c_y
 __device__ constexpr int GJd[9] = {0, 1, 0, 2, 0, 1, 2, 1, 2};
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, U - 1>) in order:
+// a loop body unrolled in the source, for bodies past the compiler's
+// unrolling budget whose constants (ring slots) depend on the index
+template <int U, int I = 0, class F>
+__device__ __forceinline__ void unrolled(F &&f) {
+    if constexpr (I < U) {
+        f(std::integral_constant<int, I>{});
+        unrolled<U, I + 1>(f);
+    }
+}
+
 template <typename C>
 __device__ inline C wgt(int i) {
     return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
@@ -968,14 +979,16 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
 // depends on the row is wave-uniform (scalar registers): a lane keeps one
 // column for the whole strip.
 // Between two levels each direction is read once, by the row that pulls it:
-// c_y = -1 directions one iteration after they are written (rows kept: 2),
-// c_y = 0 two iterations after (3), c_y = +1 three after (4). Rows are
-// offset by 12 (a multiple of 2, 3 and 4) to keep slots positive.
+// c_y = -1 directions one iteration after they are written (rows kept: 2,
+// slots 0-1), c_y = 0 two iterations after (3, slots 2-4), c_y = +1 three
+// after (4, slots 5-8). A row written in iteration s sits in slot s mod 2,
+// s mod 3 or s mod 4 of its group; the row loop turns over twelve
+// iterations, so in each unrolled iteration every slot is a constant.
 template <int P, int N>
 struct WindowRings {
     static constexpr int NR = N > 1 ? N - 1 : 1;
     using C = typename Prec<P>::C;
-    C ra[NR][2][3][64], rb[NR][3][3][64], rc[NR][4][3][64];
+    C r[NR][9][3][64];
 };
 
 // One work item of the strip window: strip `strip` (columns [strip W,
@@ -989,9 +1002,6 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int RG = N - 1;
-    auto &ra = rings.ra;
-    auto &rb = rings.rb;
-    auto &rc = rings.rc;
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -1016,6 +1026,19 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
         while (gc >= nx) gc -= nx;
         const int vo0 = gc * (int)sizeof(T), vom = (gc == 0 ? nx - 1 : gc - 1) * (int)sizeof(T),
                   vop = (gc == nx - 1 ? 0 : gc + 1) * (int)sizeof(T);
+        // LDS byte offsets: the lane's column in the ring this level writes
+        // (ring lvl - 1), and one column left of it in the ring it reads
+        // (ring lvl - 2), so that the pulls of column lc - c_x sit at
+        // non-negative constant offsets. Every access is one of the two plus
+        // a constant, the DS instructions' immediate offset; an empty asm
+        // once per turn of the row loop keeps the compiler from hoisting one
+        // address register per access out of the loop.
+        constexpr int GB = 64 * (int)sizeof(C), SB = 3 * GB, RB = 9 * SB;
+        char *const ring = reinterpret_cast<char *>(&rings.r);
+        int ow = (lvl - 1) * RB + lc * (int)sizeof(C), orr = (lvl - 2) * RB + (lc - 1) * (int)sizeof(C);
+        auto at = [&](int base, int slot, int g, int dx) -> C & {
+            return *reinterpret_cast<C *>(ring + base + slot * SB + g * GB + dx * (int)sizeof(C));
+        };
         // level 1 pulls row y + D while it collides row y: D rows of loads in
         // flight per strip. D + 1 register buffers in rotation: each step
         // collides one in place and refills the one the step before used, so
@@ -1039,18 +1062,14 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
         // collide a pulled row and hand it to the next level (or store it)
-        auto finish = [&](C *f, int y) {
+        auto finish = [&](C *f, int y, int u) {
             C drho, ux, uy;
             bgk(f, omega, drho, ux, uy);
             if (lvl < N) {
-                const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    const C v = PR::rt(f[i], sc, inv);
-                    const int g = GJd[i];
-                    if (CYd[i] < 0) ra[L][sa][g][lc] = v;
-                    else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
-                    else rc[L][sc3][g][lc] = v;
+                    const int slot = CYd[i] < 0 ? u % 2 : (CYd[i] == 0 ? 2 + u % 3 : 5 + u % 4);
+                    at(ow, slot, GJd[i], 0) = PR::rt(f[i], sc, inv);
                 }
             } else if (nt) {
                 const int own = y * pitch + x0 + lane;
@@ -1069,36 +1088,38 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
             for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
         }
         const int n_it = (ye - yb) + 3 * RG;
-        for (int it0 = 0; it0 < n_it; it0 += B) {
-#pragma unroll
-            for (int k = 0; k < B; ++k) {
-                const int it = it0 + k;
-                if (it >= n_it) break;
+        static_assert(12 % B == 0, "the row loop turns over twelve iterations");
+        for (int it0 = 0; it0 < n_it; it0 += 12) {
+            unrolled<12>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                const int it = it0 + u;
+                if (it >= n_it) return;
+                if constexpr (u == 0) asm("" : "+v"(ow), "+v"(orr));
                 const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
                 const bool row_on = y >= yb - span && y < ye + span;
                 if (lvl == 1) {
                     if (row_on) {
-                        pull(buf[(k + D) % B], min(y + D, y1_end - 1));
+                        pull(buf[(u + D) % B], min(y + D, y1_end - 1));
                         if (lane_on) {
                             C f[9];  // (buffers are written only by loads)
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][i], inv);
-                            finish(f, y);
+                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[u % B][i], inv);
+                            finish(f, y, u);
                         }
                     }
                 } else if (row_on && lane_on) {
+                    // rows written in iterations it - 1, it - 2 and it - 3
                     C f[9];
-                    const int L = lvl - 2;
-                    const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
-                        const int g = GJd[i], c = lc - CXd[i];
-                        f[i] = CYd[i] < 0 ? ra[L][sa][g][c] : (CYd[i] == 0 ? rb[L][sb][g][c] : rc[L][sc3][g][c]);
+                        const int slot =
+                            CYd[i] < 0 ? (u + 1) % 2 : (CYd[i] == 0 ? 2 + (u + 1) % 3 : 5 + (u + 1) % 4);
+                        f[i] = at(orr, slot, GJd[i], 1 - CXd[i]);
                     }
-                    finish(f, y);
+                    finish(f, y, u);
                 }
                 __syncthreads();
-            }
+            });
         }
     }
 }
@@ -1135,8 +1156,9 @@ __global__ __launch_bounds__(64 * N) void k_stepW(JobDev j, bool src2, int W, in
 // per row.
 // LDS rings of the level below, by the row a direction group pulls from:
 // c_y = -1 (row y + 1, slots 0-1) and c_y = 0 (row y, slots 2-3): 2 rows;
-// c_y = +1 (row y - 1, slots 4-6): 3 rows. Row r sits in slot (r + 12)
-// mod 2 or mod 3 of its group. A row holds 64 K M values (no padding:
+// c_y = +1 (row y - 1, slots 4-6): 3 rows. A row sits in slot s mod 2 or
+// s mod 3 of its group, s the row step it is written in. A row holds 64 K M
+// values (no padding:
 // the shifted writes wrap inside the row), so the three rows of a slot, and
 // the same slot of the first two groups, lie a multiple of 64 words apart:
 // the compiler pairs those accesses into ds_read2st64 / ds_write2st64.
@@ -1182,6 +1204,28 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
         wp[m] = c[m] == nx - 1 ? 0 : c[m] + 1;  // LDS columns of the c_x = +1 and -1 pushes
         wm[m] = c[m] == 0 ? nx - 1 : c[m] - 1;
     }
+    // LDS byte offsets of the lane's columns: x, wm, wp in the ring this
+    // level writes (ring lvl - 1), x in the ring it reads (ring lvl - 2).
+    // Every ring access is one of these plus a constant (slot and
+    // direction-row), which the DS instructions take as their immediate
+    // offset; the offsets pass through an empty asm once per turn of the row
+    // loops so that the compiler keeps them as the bases instead of hoisting
+    // one address register per access out of the loop.
+    constexpr int GB = RowsRing<P, N, K, M>::CW * (int)sizeof(C), SB = 3 * GB, RB = 7 * SB;
+    char *const ring = reinterpret_cast<char *>(&rg);
+    int ox[M], om[M], op[M], orx[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        ox[m] = (lvl - 1) * RB + c[m] * (int)sizeof(C);
+        om[m] = (lvl - 1) * RB + wm[m] * (int)sizeof(C);
+        op[m] = (lvl - 1) * RB + wp[m] * (int)sizeof(C);
+        orx[m] = (lvl - 2) * RB + c[m] * (int)sizeof(C);
+    }
+    auto at = [&](int base, int slot, int g) -> C & { return *reinterpret_cast<C *>(ring + base + slot * SB + g * GB); };
+    auto fresh = [&]() {
+#pragma unroll
+        for (int m = 0; m < M; ++m) asm("" : "+v"(ox[m]), "+v"(om[m]), "+v"(op[m]), "+v"(orx[m]));
+    };
     const int span = RG - (lvl - 1);  // rows beyond the chunk on each side
     constexpr int B = D + 1;
     using R = typename BufLd<P>::R;
@@ -1212,22 +1256,29 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
         // then reads the puller's own column, and the periodic wrap costs no
         // extra copies
         // (the c_y = -1 and c_y = 0 groups use slots of the same index, two
-        // apart: their writes of equal c_x go in pairs, ds_write2st64)
-        auto put = [&](int L, int y, int m, const C *v) {
-            const int sa = (y + 12) & 1, sc3 = (y + 12) % 3, x = c[m];
-            rg[L][sa][0][x] = v[4];
-            rg[L][2 + sa][0][x] = v[0];
-            rg[L][sa][1][wm[m]] = v[7];
-            rg[L][2 + sa][2][wm[m]] = v[3];
-            rg[L][sa][2][wp[m]] = v[8];
-            rg[L][2 + sa][1][wp[m]] = v[1];
-            rg[L][4 + sc3][0][x] = v[2];
-            rg[L][4 + sc3][1][wp[m]] = v[5];
-            rg[L][4 + sc3][2][wm[m]] = v[6];
+        // apart: their writes of equal c_x go in pairs, ds_write2st64).
+        // Slots are named by the row step a row is written in, the same
+        // count for every level: a row written in step it goes to slot
+        // it mod 2 of the first two groups and it mod 3 of the c_y = +1
+        // group, and is read in step it + 1 (c_y <= 0 groups) or it + 2
+        // (c_y = +1). The row loops advance six steps at a time, so for
+        // the unrolled step u (it = 6 n + u) every slot is a constant and
+        // each LDS address is the lane's column base plus an immediate.
+        auto put = [&](int u, int m, const C *v) {
+            const int sa = u & 1, sc3 = u % 3;
+            at(ox[m], sa, 0) = v[4];
+            at(ox[m], 2 + sa, 0) = v[0];
+            at(om[m], sa, 1) = v[7];
+            at(om[m], 2 + sa, 2) = v[3];
+            at(op[m], sa, 2) = v[8];
+            at(op[m], 2 + sa, 1) = v[1];
+            at(ox[m], 4 + sc3, 0) = v[2];
+            at(op[m], 4 + sc3, 1) = v[5];
+            at(om[m], 4 + sc3, 2) = v[6];
         };
         // collide the lane's M nodes of row y and hand each on to the next
         // level
-        auto finish = [&](C (*f)[9], int y) {
+        auto finish = [&](C (*f)[9], int y, int u) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 C drho, ux, uy;
@@ -1239,7 +1290,7 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
                     C v[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
-                    put(lvl - 1, y, m, v);
+                    put(u, m, v);
                 } else if (nt) {
                     const int own = y * (int)j.pitch + c[m];
 #pragma unroll
@@ -1253,24 +1304,27 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
         const int n_it = (ye - yb) + 3 * RG;
-        // Both loops below pass n_it barriers, one per row step.
+        // Both loops below pass n_it barriers, one per row step, six steps
+        // per turn (the slot period; also a multiple of the B load buffers).
+        static_assert(6 % B == 0, "the row loops turn over six steps");
         if (lvl == 1) {
 #pragma unroll
             for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
-            for (int it0 = 0; it0 < n_it; it0 += B) {
+            for (int it0 = 0; it0 < n_it; it0 += 6) {
 #pragma unroll
-                for (int k = 0; k < B; ++k) {
-                    const int it = it0 + k;
+                for (int u = 0; u < 6; ++u) {
+                    const int it = it0 + u;
                     if (it >= n_it) break;
                     const int y = yb - RG + it;
+                    if (u == 0) fresh();
                     if (y < ye + span) {
-                        pull(buf[(k + D) % B], min(y + D, y1_end - 1));
+                        pull(buf[(u + D) % B], min(y + D, y1_end - 1));
                         C f[M][9];
 #pragma unroll
                         for (int m = 0; m < M; ++m)
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) f[m][i] = BufLd<P>::cvt(buf[k][m][i], inv);
-                        finish(f, y);
+                            for (int i = 0; i < 9; ++i) f[m][i] = BufLd<P>::cvt(buf[u % B][m][i], inv);
+                        finish(f, y, u);
                     }
                     __syncthreads();
                 }
@@ -1285,30 +1339,31 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
             // y + 1, written in the previous step) wait at the start of the
             // step. What is read ahead never sits in LDS for more than one
             // step, hence the short rings.
-            const int L = lvl - 2;
             C pre[2][M][6];
-            auto ahead = [&](C (*q)[6], int y) {  // c_y >= 0 pulls of row y
-                const int sb = (y + 12) & 1, sc3 = (y + 11) % 3;
+            // step u reads the rows the level below wrote in steps u - 1
+            // (slot (u + 1) mod 2) and u - 2 (slot (u + 1) mod 3)
+            auto ahead = [&](C (*q)[6], int u) {  // c_y >= 0 pulls of the next row
+                const int sb = (u + 1) & 1, sc3 = (u + 1) % 3;
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     int n = 0;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         if (CYd[i] < 0) continue;
-                        const int g = GJd[i], x = c[m];
-                        q[m][n++] = CYd[i] == 0 ? rg[L][2 + sb][g][x] : rg[L][4 + sc3][g][x];
+                        q[m][n++] = at(orx[m], CYd[i] == 0 ? 2 + sb : 4 + sc3, GJd[i]);
                     }
                 }
             };
             const int y_lo = yb - span, y_hi = ye + span;  // this level's rows
-            for (int it0 = 0; it0 < n_it; it0 += 2) {
+            for (int it0 = 0; it0 < n_it; it0 += 6) {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int it = it0 + k;
+                for (int u = 0; u < 6; ++u) {
+                    const int it = it0 + u, k = u & 1;
                     if (it >= n_it) break;
                     const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
+                    if (u == 0) fresh();
                     if (y == y_lo - 1) {
-                        ahead(pre[k ^ 1], y + 1);  // the first row's
+                        ahead(pre[k ^ 1], u);  // the first row's
                     } else if (y >= y_lo && y < y_hi) {
                         // row y + 1 of the level below: this row's c_y = -1
                         // pulls and the next row's c_y = 0 pulls (slots of the
@@ -1316,21 +1371,21 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
                         // pulls. All at the lane's own column, 64-word multiples
                         // apart (ds_read2st64 pairs). Past the last row the
                         // values read ahead are not used.
-                        const int sa = (y + 13) & 1, sc3 = (y + 12) % 3;
+                        const int sa = (u + 1) & 1, sc3 = (u + 1) % 3;
                         C f[M][9];
                         C (*q)[6] = pre[k ^ 1];
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
-                            const int x = c[m];  // the lane's LDS column
-                            f[m][4] = rg[L][sa][0][x];       // (0, -1)
-                            f[m][7] = rg[L][sa][1][x];       // (-1, -1)
-                            f[m][8] = rg[L][sa][2][x];       // (1, -1)
-                            q[m][0] = rg[L][2 + sa][0][x];   // (0, 0)
-                            q[m][1] = rg[L][2 + sa][1][x];   // (1, 0)
-                            q[m][3] = rg[L][2 + sa][2][x];   // (-1, 0)
-                            q[m][2] = rg[L][4 + sc3][0][x];  // (0, 1)
-                            q[m][4] = rg[L][4 + sc3][1][x];  // (1, 1)
-                            q[m][5] = rg[L][4 + sc3][2][x];  // (-1, 1)
+                            // at the lane's own LDS column
+                            f[m][4] = at(orx[m], sa, 0);       // (0, -1)
+                            f[m][7] = at(orx[m], sa, 1);       // (-1, -1)
+                            f[m][8] = at(orx[m], sa, 2);       // (1, -1)
+                            q[m][0] = at(orx[m], 2 + sa, 0);   // (0, 0)
+                            q[m][1] = at(orx[m], 2 + sa, 1);   // (1, 0)
+                            q[m][3] = at(orx[m], 2 + sa, 2);   // (-1, 0)
+                            q[m][2] = at(orx[m], 4 + sc3, 0);  // (0, 1)
+                            q[m][4] = at(orx[m], 4 + sc3, 1);  // (1, 1)
+                            q[m][5] = at(orx[m], 4 + sc3, 2);  // (-1, 1)
                             // this row's c_y >= 0 pulls, read a step ago
                             f[m][0] = pre[k][m][0];
                             f[m][1] = pre[k][m][1];
@@ -1339,7 +1394,7 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
                             f[m][5] = pre[k][m][4];
                             f[m][6] = pre[k][m][5];
                         }
-                        finish(f, y);
+                        finish(f, y, u);
                     }
                     __syncthreads();
                 }
@@ -1370,6 +1425,23 @@ __device__ inline int fused_job_of(const FusedJob *jobs, int njobs, int64_t wk) 
     return lo;
 }
 
+// The table entry of a work item, in scalar registers. Every lane of the
+// workgroup reads the same entry, but the compiler cannot tell, and a job's
+// pointers built from vector registers would put every buffer access of the
+// pipeline in a loop over the distinct descriptors (v_readfirstlane per
+// access); each dword goes through readfirstlane once per item instead.
+__device__ inline FusedJob fused_entry(const FusedJob *jobs, int njobs, int64_t wk) {
+    static_assert(sizeof(FusedJob) % 4 == 0, "FusedJob is a whole number of dwords");
+    constexpr int NW = (int)(sizeof(FusedJob) / 4);
+    uint32_t w[NW];
+    __builtin_memcpy(w, &jobs[fused_job_of(jobs, njobs, wk)], sizeof(FusedJob));
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    FusedJob q;
+    __builtin_memcpy(&q, w, sizeof(FusedJob));
+    return q;
+}
+
 // Batched form: every chunk of every sample of every job in the table, N
 // steps per launch; launch number `launch` of a tick reads the slab of
 // parity par ^ (launch & 1) of its job (the state of step t + launch N;
@@ -1380,7 +1452,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepR_multi(const FusedJob *jobs
     __shared__ typename RowsRing<P, N, K, M>::Array rg;
     const int64_t G = gridDim.x;
     for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const FusedJob q = fused_entry(jobs, njobs, wk);
         const JobDev j = q.j;
         const int64_t local = wk - q.work0;
         const int64_t smp = local / q.chunks;
@@ -1396,7 +1468,7 @@ __global__ __launch_bounds__(64 * N) void k_stepW_multi(const FusedJob *jobs, in
     const int lvl = window_level<N>();
     const int64_t G = gridDim.x;
     for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const FusedJob q = fused_entry(jobs, njobs, wk);
         const JobDev j = q.j;
         const int64_t local = wk - q.work0;
         const int64_t smp = local / ((int64_t)q.chunks * q.strips);
@@ -1637,7 +1709,7 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC_multi(const FusedJob *job
     __shared__ typename RowsRingCh<P, N, K, M>::Array rq;
     const int64_t G = gridDim.x;
     for (int64_t wk = xcd_logical(blockIdx.x, G); wk < nwork; wk += G) {
-        const FusedJob &q = jobs[fused_job_of(jobs, njobs, wk)];
+        const FusedJob q = fused_entry(jobs, njobs, wk);
         const JobDev j = q.j;
         const int64_t local = wk - q.work0;
         const int64_t smp = local / q.chunks;

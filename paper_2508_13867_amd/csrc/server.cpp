@@ -409,6 +409,26 @@ uq_status Server::rebuild_table() {
         fused.push_back(f);
         tptrs.push_back(l.job->d_t);
     }
+    // an instance whose jobs give fewer work items than the GPU has CUs
+    // takes shorter row chunks: more items, each a shorter pipeline (the
+    // extra halo rows cost less than idle CUs). The chunking does not change
+    // any node's arithmetic.
+    constexpr int64_t kTargetItems = 256;
+    for (Group &g : groups) {
+        if (g.kind == 2 || g.nwork >= kTargetItems) continue;
+        const int hmin = g.N >= 6 ? 32 : 16;
+        int64_t w = 0;
+        for (int q = g.first; q < g.first + g.count; ++q) {
+            FusedJob &f = fused[(size_t)q];
+            const int64_t want = (f.chunks * kTargetItems + g.nwork - 1) / g.nwork;
+            const int H = std::min(f.H, std::max(hmin, (int)((f.j.ny + want - 1) / want)));
+            f.H = H;
+            f.chunks = (f.j.ny + H - 1) / H;
+            f.work0 = w;
+            w += (int64_t)f.j.S * f.chunks * f.strips;
+        }
+        g.nwork = w;
+    }
     for (Live &l : live) {
         if (l.r.shape.kind >= 0) continue;
         MultiJob m;

@@ -5,9 +5,13 @@ step: level L computes row y = yb - (N-1) + it - 2(L-1) at step `it`, over
 [yb - span, ye + span) with span = N - L. Level 1 pulls from the lattice;
 levels above pull from LDS rings of the level below:
 
-- c_y = -1 directions (pulled from row y + 1): 2 slots, (r + 12) mod 2;
-- c_y =  0 directions (row y):                2 slots, (r + 12) mod 2;
-- c_y = +1 directions (row y - 1):            3 slots, (r + 12) mod 3;
+- c_y = -1 directions (pulled from row y + 1): 2 slots, s mod 2;
+- c_y =  0 directions (row y):                2 slots, s mod 2;
+- c_y = +1 directions (row y - 1):            3 slots, s mod 3;
+
+where s is the step in which the level below wrote the row (the same step
+count for every level, so the kernel's six-step unrolled loops name every
+slot by a constant);
 
 a level writes direction i of column c at LDS column (c + c_ix) mod nx,
 so every pull reads the puller's own column; the c_y >= 0 pulls of the next
@@ -46,13 +50,17 @@ def plain_steps(f, omega, n):
     return f
 
 
-def slot(level, r, i, col):
-    """LDS location of row r, direction i, column col of `level`'s ring."""
+def slot(level, r, i, col, y0):
+    """LDS location of row r, direction i, column col of ring `level` (the
+    output of level + 1), in a chunk whose level 1 starts at row y0: the row
+    is written in step r - y0 + 2 level."""
+    s = r - y0 + 2 * level
+    assert s >= 0
     if CY[i] < 0:
-        return (level, (r + 12) % 2, GJ[i], col)
+        return (level, s % 2, GJ[i], col)
     if CY[i] == 0:
-        return (level, 2 + (r + 12) % 2, GJ[i], col)
-    return (level, 4 + (r + 12) % 3, GJ[i], col)
+        return (level, 2 + s % 2, GJ[i], col)
+    return (level, 4 + s % 3, GJ[i], col)
 
 
 def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
@@ -71,7 +79,9 @@ def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
             def read(level, lane, c, i, r):
                 # pull of direction i for row r of `level`: row r - c_y of the
                 # level below, at the lane's own column
-                key = slot(level - 2, r - CY[i], i, c)
+                key = slot(level - 2, r - CY[i], i, c, yb - rg)
+                # the kernel's slots in step it: (it + 1) mod 2, (it + 1) mod 3
+                assert key[1] == [(it + 1) % 2, 2 + (it + 1) % 2, 4 + (it + 1) % 3][CY[i] + 1]
                 assert tag.get(key) == (r - CY[i], (c - CX[i]) % nx, i), (level, it, lane, i, r)
                 reads.add(key)
                 return lds[key]
@@ -99,8 +109,9 @@ def run_schedule(nx, ny, n_lvl, rows, lanes, omega=1.3, seed=0):
                                                            for i in range(9) if CY[i] >= 0}
                     g = collide(f[:, None], omega)[:, 0]
                     if level < n_lvl:
-                        writes += [(slot(level - 1, y, i, (c + CX[i]) % nx), (y, c, i), g[i])
+                        writes += [(slot(level - 1, y, i, (c + CX[i]) % nx, yb - rg), (y, c, i), g[i])
                                    for i in range(9)]
+                        assert slot(level - 1, y, 0, 0, yb - rg)[1] == 2 + it % 2  # written in step it
                     else:
                         assert 0 <= y < ny
                         if lane < nx:
