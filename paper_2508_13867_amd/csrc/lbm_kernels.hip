@@ -2456,11 +2456,12 @@ static void stepR_k(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s
     k_stepR<P, N, K, M, 2><<<(unsigned)G, 64 * N * K, 0, s>>>(j, src2, H, chunks, nwork, nt);
 }
 
-// Shapes of the full-row kernels: K waves per level of M columns per lane,
-// N K <= 16 waves, and (N - 1) LDS rings of ROWS direction-rows (21 on the
-// periodic lattice, 30 on the channel) of about 64 K M compute values within
-// 160 KB. The shape used for a lattice nx wide: the fewest columns per lane
-// (M = 1, else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
+// Shapes of the full-row kernels: K waves per level of M columns per lane
+// (K <= 4 with one column, <= 6 with two: rows up to 768 columns), N K <= 16
+// waves, and (N - 1) LDS rings of ROWS direction-rows (21 on the periodic
+// lattice, 30 on the channel) of about 64 K M compute values within 160 KB.
+// The shape used for a lattice nx wide: the fewest columns per lane (M = 1,
+// else 2) whose K = ceil(nx / 64 M) fits; 0 if none.
 static constexpr int RING_ROWS_TGV = 21, RING_ROWS_CH = 30;
 
 // Registers: in single precision a lane of the periodic kernel colliding two
@@ -2480,7 +2481,7 @@ static constexpr bool rows_regs_fit(int prec, int waves, int M, bool channel) {
 static constexpr int ring_cols(int rows, int K, int M) { return 64 * K * M + (rows == RING_ROWS_CH ? 64 : 0); }
 
 static constexpr bool rows_fit(int prec, int n, int rows, int K, int M) {
-    return n * K <= 16 && K <= 4 && rows_regs_fit(prec, n * K, M, rows == RING_ROWS_CH) &&
+    return n * K <= 16 && K <= (M == 2 ? 6 : 4) && rows_regs_fit(prec, n * K, M, rows == RING_ROWS_CH) &&
            (int64_t)(n - 1) * rows * ring_cols(rows, K, M) * (prec == UQ_FP64 ? 8 : 4) <= 160 * 1024;
 }
 
@@ -2498,7 +2499,7 @@ static int rows_shape(int prec, int n, int rows, int nx, int *K, int *M) {
 
 static int rows_max_nx(int prec, int n, int rows) {
     int best = 0;
-    for (int nx = 64; nx <= 512; nx += 64) {
+    for (int nx = 64; nx <= 768; nx += 64) {
         int K, M;
         if (rows_shape(prec, n, rows, nx, &K, &M)) best = nx;
     }
@@ -2509,7 +2510,8 @@ int full_rows_max_nx(int prec, int n) { return rows_max_nx(prec, n, RING_ROWS_TG
 int channel_rows_max_nx(int prec, int n) { return rows_max_nx(prec, n, RING_ROWS_CH); }
 
 // the instances (K, M) a launcher may take
-#define UQ_ROWS_CASES(CASE) CASE(2, 1) CASE(3, 1) CASE(4, 1) CASE(2, 2) CASE(3, 2) CASE(4, 2)
+#define UQ_ROWS_CASES(CASE) \
+    CASE(2, 1) CASE(3, 1) CASE(4, 1) CASE(2, 2) CASE(3, 2) CASE(4, 2) CASE(5, 2) CASE(6, 2)
 
 template <int P, int N>
 static void stepR_p(const JobDev &j, bool src2, int rows, bool nt, hipStream_t s) {

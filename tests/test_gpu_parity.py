@@ -707,6 +707,62 @@ def test_full_row_kernel_wide_rows(prec, nx, ny, monkeypatch):
         assert np.abs(res["4"] - ref).max() < 1e-6
 
 
+@pytest.mark.parametrize("nx, ny, n", [(640, 9, 3), (600, 11, 3), (768, 7, 2), (700, 5, 2)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16s"])
+def test_full_row_kernel_widest_rows(prec, nx, ny, n, monkeypatch):
+    # rows of 600..768 columns: five or six waves of two columns per lane per
+    # level, 3 or 2 steps per launch; 600 and 700 leave lanes past the
+    # lattice. Bit for bit the single-step result; FP32 also against the
+    # oracle on one sample
+    monkeypatch.setenv("UQ_FUSE_TY", "8")
+    monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+    spec = W.scaled(TGV_RAGGED, nx=nx, ny=ny, layout="ab", precision=prec)
+    say("case widest rows", prec, nx, ny, n)
+    steps = 2 * n * 2 + 1
+    res = {}
+    for fuse in ("0", str(n)):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        with Job(spec) as job:
+            assert job.info().fused == (n if fuse != "0" else 0)
+            assert fuse == "0" or job.info().fused_window == 2
+            job.run(steps)
+            res[fuse] = job.populations(2)
+    assert np.array_equal(res["0"], res[str(n)])
+    if prec == "fp32":
+        with Job(spec) as job:
+            xi, _ = job.samples()
+        p = O.sample_params(spec, xi[2])
+        ref = O.tgv_run(nx, ny, p["nu"], p["u0"], steps, p["phase_x"], p["phase_y"], want_f=True)["f"]
+        assert np.abs(res[str(n)] - ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "bf16s"])
+def test_fused_channel_widest_rows(prec, monkeypatch):
+    # a 616-column channel (five waves of two columns per level, 2 steps per
+    # launch) with walls, cylinder and Zou-He ends: bit for bit the single
+    # steps (populations and drag); FP32 single steps against the oracle
+    spec = W.scaled(CHANNEL_SMALL, nx=616, ny=23, D=8, cx=60, cy=11, precision=prec, layout="ab", ramp=10,
+                    steps=25)
+    say("case fused channel widest rows", prec)
+    res = {}
+    for fuse in ("0", "2"):
+        monkeypatch.setenv("UQ_FUSE", fuse)
+        monkeypatch.setenv("UQ_FUSE_TY", "8")
+        monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+        with Job(spec) as job:
+            assert job.info().fused == (2 if fuse == "2" else 0)
+            job.run(25)
+            res[fuse] = (job.populations(1), job.qoi_samples("cd")[:, 0])
+            if prec == "fp32" and fuse == "0":
+                xi, _ = job.samples()
+    assert np.array_equal(res["0"][0], res["2"][0])
+    assert np.array_equal(res["0"][1], res["2"][1])
+    if prec == "fp32":
+        p = O.sample_params(spec, xi[1])
+        ref = O.channel_run(616, 23, p["nu"], p["u_peak"], 25, D=8, cx=60, cy=11, ramp=10, want_f=True)["f"]
+        assert np.abs(res["2"][0] - ref).max() < 1e-5
+
+
 @pytest.mark.parametrize("steps, launches", [(3, 1), (5, 1), (7, 3), (8, 2), (13, 3), (20, 4), (25, 5)])
 def test_steps_left_over_run_as_odd_fused_launches(steps, launches, monkeypatch):
     # 6 steps per launch in pairs (12); what is left goes in odd fused

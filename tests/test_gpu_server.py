@@ -98,9 +98,10 @@ def test_plain_mode_agrees_with_batched():
 def test_batched_instances_equal_standalone_single_steps(prec):
     # jobs that land in different batched instances (vortex rows of 64, 200,
     # 256 and 384 columns: one or two columns per lane, 8 or 4 steps per
-    # launch; a 640-column vortex in strips of 4 steps; channels of 220 and
-    # 440 columns: 4 or 3 steps) and one that runs the single-step AA launch
-    # (a 616-column channel), with step counts that leave the last steps to
+    # launch; a 640-column vortex in strips of 4 steps; channels of 220, 440
+    # and 616 columns: 4, 3 or 2 steps, the last with five waves of two
+    # columns per level) and one that runs the single-step AA launch (an
+    # 880-column channel), with step counts that leave the last steps to
     # each job's own launches: every result is bitwise that of the job
     # alone, one step per launch
     say("case batched instances", prec)
@@ -111,6 +112,8 @@ def test_batched_instances_equal_standalone_single_steps(prec):
     specs += [dict(CYL_C, name="c220", precision=prec, steps=233),
               dict(CYL_C, name="c440", precision=prec, nx=440, ny=82, D=20, cx=40, cy=41, steps=149, ramp=60),
               dict(CYL_C, name="c616", precision=prec, nx=616, ny=115, D=28, cx=56, cy=57, nu=0.07, steps=61,
+                   ramp=30),
+              dict(CYL_C, name="c880", precision=prec, nx=880, ny=164, D=40, cx=80, cy=82, nu=0.1, steps=53,
                    ramp=30)]
     with Server(memory_budget_gb=4, max_jobs=16, steps_per_tick=48, precision=prec) as srv:
         ts = [srv.submit(s) for s in specs]
