@@ -250,8 +250,10 @@ __device__ inline double ramp_factor(int64_t t, double T) {
 // inflow profile u_x at row y, time t: s(t) 4 u_peak (y+1/2)(H-y-1/2)/H^2,
 // from a = s(t) 4 u_peak
 __device__ inline double inflow_u_a(double a, int ny, int y) {
-    const double H = (double)ny, yy = (double)y + 0.5;
-    return a * yy * (H - yy) / (H * H);
+    // 1/H^2 depends on the lattice only: the compiler hoists its division
+    // out of the row loops, leaving three multiplies per row
+    const double H = (double)ny, yy = (double)y + 0.5, inv_h2 = 1.0 / (H * H);
+    return a * yy * (H - yy) * inv_h2;
 }
 __device__ inline double inflow_u(int ny, double ramp, int y, int64_t t, double u_peak) {
     return inflow_u_a(ramp_factor(t, ramp) * 4.0 * u_peak, ny, y);
@@ -265,8 +267,10 @@ template <typename C>
 __device__ inline void zou_he_u(C f[9], bool inlet, C u) {
     const C h = C(0.5) * (f[2] - f[4]);
     if (inlet) {
+        // 1/(1 - u) depends on the row's imposed velocity only, so it is
+        // formed off the chain that waits for the pulled populations
         const C S = fma_c(C(2), (f[3] + f[6]) + f[7], (f[0] + f[2]) + f[4]);
-        const C drho = (S + u) / (C(1) - u);
+        const C drho = (S + u) * recip(C(1) - u);
         const C ru = (C(1) + drho) * u;
         f[1] = fma_c(C(2) / C(3), ru, f[3]);
         f[5] = fma_c(C(1) / C(6), ru, f[7] - h);
@@ -1524,11 +1528,15 @@ __device__ __forceinline__ void stepRC_item(const JobDev &j, const int64_t *d_t,
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lvl = wave / K + 1;  // 1..N
     const int64_t t_lvl = t0 + (lvl - 1);
+    // the level's K column blocks rotate with the level, so that the blocks
+    // with the open end columns (and the cylinder) fall on different SIMDs
+    // at different levels (wave w runs on SIMD w mod 4)
+    const int kb = (wave - (lvl - 1) * K + (lvl - 1)) % K;
     int c[M], vo0[M], vom[M], vop[M], mvo[M];
     bool on[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        c[m] = ((wave - (lvl - 1) * K) * M + m) * 64 + lane;
+        c[m] = (kb * M + m) * 64 + lane;
         on[m] = c[m] < nx;
         const int cc = on[m] ? c[m] : nx - 1;
         mvo[m] = cc * 4;
