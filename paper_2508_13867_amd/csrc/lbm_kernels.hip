@@ -267,10 +267,8 @@ template <typename C>
 __device__ inline void zou_he_u(C f[9], bool inlet, C u) {
     const C h = C(0.5) * (f[2] - f[4]);
     if (inlet) {
-        // 1/(1 - u) depends on the row's imposed velocity only, so it is
-        // formed off the chain that waits for the pulled populations
         const C S = fma_c(C(2), (f[3] + f[6]) + f[7], (f[0] + f[2]) + f[4]);
-        const C drho = (S + u) * recip(C(1) - u);
+        const C drho = (S + u) / (C(1) - u);
         const C ru = (C(1) + drho) * u;
         f[1] = fma_c(C(2) / C(3), ru, f[3]);
         f[5] = fma_c(C(1) / C(6), ru, f[7] - h);
@@ -1595,8 +1593,16 @@ __device__ __forceinline__ void stepRC_item(const JobDev &j, const int64_t *d_t,
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 if (mm[m] & OPEN_BITS) {
+                    // Zou-He overwrites every pull from beyond the column
+                    // (inlet 1, 5, 8; outlet 3, 6, 7) without reading it, so
+                    // where it runs (t > 0) and the inlet is not also the
+                    // outlet (nx > 1) those pulls need not be zeroed first:
+                    // the same values as the single-step gather, which
+                    // zeroes them at every step (both conditions uniform)
+                    if (t_lvl == 0 || nx == 1) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) f[m][i] = ((mm[m] >> (M_OPEN + i)) & 1u) ? C(0) : f[m][i];
+                        for (int i = 0; i < 9; ++i) f[m][i] = ((mm[m] >> (M_OPEN + i)) & 1u) ? C(0) : f[m][i];
+                    }
                     if (t_lvl > 0)
                         zou_he_u(f[m], c[m] == 0, c[m] == 0 ? (C)inflow_u_a(a_in, ny, y) : C(0));
                 }
