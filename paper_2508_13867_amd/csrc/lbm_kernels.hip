@@ -1286,22 +1286,29 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
                 C drho, ux, uy;
                 bgk(f[m], omega, drho, ux, uy);
             }
+            // one uniform branch for all the lane's columns, so that both
+            // collisions stay in one block
+            if (lvl < N) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (lvl < N) {
+                for (int m = 0; m < M; ++m) {
                     C v[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
                     put(u, m, v);
-                } else if (nt) {
+                }
+            } else if (nt) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
                     const int own = y * (int)j.pitch + c[m];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) PR::st_nt(dst + (i * plane + own), f[m][i], sc);
-                } else {
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m)
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
                         BufSt<P>::st(wrsrc, f[m][i], vo0[m], i * plane_b + y * pitch_b, sc);
-                }
             }
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
@@ -1396,6 +1403,10 @@ __device__ __forceinline__ void stepR_item(const JobDev &j, bool src2, int H, in
                             f[m][5] = pre[k][m][4];
                             f[m][6] = pre[k][m][5];
                         }
+                        // every LDS read of the step (both columns, and the
+                        // next row's read-ahead) is issued before the first
+                        // collision, which then waits only for its own three
+                        __builtin_amdgcn_sched_barrier(0);
                         finish(f, y, u);
                     }
                     __syncthreads();
@@ -1612,10 +1623,11 @@ __device__ __forceinline__ void stepRC_item(const JobDev &j, const int64_t *d_t,
                 C drho, ux, uy;
                 bgk(f[m], omega, drho, ux, uy);
             }
+            // one uniform branch for all the lane's columns (see stepR_item)
+            if (lvl < N) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (!on[m] || (mm[m] & M_SOLID)) continue;
-                if (lvl < N) {
+                for (int m = 0; m < M; ++m) {
+                    if (!on[m] || (mm[m] & M_SOLID)) continue;
                     C v[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) v[i] = PR::rt(f[m][i], sc, inv);
@@ -1623,7 +1635,11 @@ __device__ __forceinline__ void stepRC_item(const JobDev &j, const int64_t *d_t,
                     // end-column copies (read only when x is periodic)
                     if (c[m] == nx - 1) put(lvl - 1, y, 0, v);
                     if (c[m] == 0) put(lvl - 1, y, nx + 1, v);
-                } else {
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (!on[m] || (mm[m] & M_SOLID)) continue;
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
                         BufSt<P>::st(wrsrc, f[m][i], vo0[m], i * plane_b + y * pitch_b, sc);
