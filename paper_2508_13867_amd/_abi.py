@@ -239,6 +239,15 @@ class TorchAllocator:
         self.live.pop(ptr, None)
 
 
+def _pinned(shape):
+    """An uninitialised float64 host array in page-locked memory (torch's
+    caching host allocator: blocks are reused across calls); the array keeps
+    its tensor, and so the memory, alive."""
+    import torch
+
+    return torch.empty(shape, dtype=torch.float64, pin_memory=True).numpy()
+
+
 def torch_device(device: int = 0, stream=None, allocator=True):
     """uq_device for `device`, torch's current stream and torch memory."""
     import torch
@@ -333,16 +342,19 @@ class Job:
         return out
 
     def moments(self, qoi: str, noalloc: bool = False) -> dict:
-        """uq_moments, or uq_moments_noalloc (no device allocation) if asked."""
+        """uq_moments, or uq_moments_noalloc (no device allocation) if asked.
+        The result arrays are page-locked host memory (every entry is written
+        by the library), so that its device-to-host copies of field moments
+        (tens of MB) run at the link's rate."""
         n = C.c_int64()
         check(lib().uq_qoi_samples(self.h, QOI[qoi], None, C.byref(n)))
         n = n.value
-        mean, var, alt = np.zeros(n), np.zeros(n), np.zeros(n)
+        mean, var, alt = _pinned(n), _pinned(n), _pinned(n)
         res = {"mean": mean, "var": var, "var_alt": alt}
         m = MomentsOut()
         m.mean, m.var, m.var_alt = mean.ctypes.data, var.ctypes.data, alt.ctypes.data
         if self.K > 0:
-            coeffs = np.zeros((self.K, n))
+            coeffs = _pinned((self.K, n))
             alpha = np.zeros((self.K, self.d), np.int32)
             m.coeffs, m.alpha = coeffs.ctypes.data, alpha.ctypes.data
             res["coeffs"], res["alpha"] = coeffs, alpha
