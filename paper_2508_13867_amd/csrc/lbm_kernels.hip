@@ -1766,7 +1766,7 @@ __global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int nj
         }
         const MultiJob &q = jobs[lo];
         const int64_t t = q.t + k;
-        if (t >= q.n_steps) continue;
+        if (t >= q.n_steps || k >= q.adv) continue;
         const int64_t per_sample = (int64_t)q.tiles_x * q.tiles_y;
         const int64_t local = tile - q.tile0;
         const int64_t smp = local / per_sample;
@@ -1782,9 +1782,9 @@ __global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int nj
     }
 }
 
-__global__ void k_advance_multi(MultiJob *jobs, int njobs, int64_t n) {
+__global__ void k_advance_multi(MultiJob *jobs, int njobs) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < njobs) jobs[q].t += n;
+    if (q < njobs) jobs[q].t += jobs[q].adv;
 }
 
 // ------------------------------------------------------------------ init
@@ -2422,9 +2422,9 @@ hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, in
     return hipGetLastError();
 }
 
-hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_t s) {
+hipError_t launch_advance_multi(MultiJob *jobs, int njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    k_advance_multi<<<(unsigned)((njobs + 63) / 64), 64, 0, s>>>(jobs, njobs, n);
+    k_advance_multi<<<(unsigned)((njobs + 63) / 64), 64, 0, s>>>(jobs, njobs);
     return hipGetLastError();
 }
 

@@ -220,14 +220,22 @@ struct Live {
     uq_job *job = nullptr;
     double t_admit = 0.0;
     int tiles_x = 0, tiles_y = 0;
+    int mult = 1;  // ticks advance this job mult times the tick's steps
 };
 
 // Jobs of the live set that share one batched instance; their table entries
 // are fused[first .. first + count).
 struct Group {
-    int kind = 0, N = 0, K = 0, M = 0;
+    int kind = 0, N = 0, K = 0, M = 0, mult = 1;
     int first = 0, count = 0;
     int64_t nwork = 0;
+};
+
+// Consecutive single-step jobs of one multiple of the tick: their entries
+// end at jobs_end in the table and their tiles at tiles_end.
+struct SingleRun {
+    int mult = 1, jobs_end = 0;
+    int64_t tiles_end = 0;
 };
 
 // Steps per tick of the batched mode: a multiple of 48, which holds a whole
@@ -273,6 +281,7 @@ struct Server {
     int table_cap = 0;
     int n_single = 0, n_fused = 0, n_all = 0;
     std::vector<Group> groups;
+    std::vector<SingleRun> single_runs;  // single-step jobs by multiple, largest first
     bool dirty = true;
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
@@ -374,9 +383,45 @@ uq_status Server::rebuild_table() {
     std::vector<size_t> order;
     for (size_t q = 0; q < live.size(); ++q)
         if (live[q].r.shape.kind >= 0) order.push_back(q);
+    // Work-fair ticks: a tick advances every job by the same number of
+    // steps, so a cheap job with many steps (few samples, a small lattice)
+    // would need as many ticks as its steps allow, each as long as the
+    // whole live set's work, and finish long after the rest. The cheapest
+    // jobs take 8, 4 or 2 times the tick's steps (batched instances: in
+    // launches of their own instance group; single steps: in the first
+    // launches of the tick, which cover the jobs in order of multiple), as
+    // long as the extra work stays within a quarter of the live set's work
+    // per tick and within the job's remaining steps. A single step moves
+    // about four times the bytes of a node update of a temporally blocked
+    // launch and is weighted so.
+    const int64_t T = batched_tick(cfg.steps_per_tick);
+    {
+        auto work = [&](size_t q) {
+            return (double)live[q].job->S * live[q].r.p.nx * live[q].r.p.ny * (live[q].r.shape.kind < 0 ? 4.0 : 1.0);
+        };
+        double wtot = 0.0;
+        std::vector<size_t> cheap;
+        for (size_t q = 0; q < live.size(); ++q) {
+            wtot += work(q);
+            cheap.push_back(q);
+        }
+        std::stable_sort(cheap.begin(), cheap.end(), [&](size_t x, size_t y) { return work(x) < work(y); });
+        double budget = 0.25 * wtot;
+        for (size_t q : cheap) {
+            Live &l = live[q];
+            l.mult = 1;
+            const int64_t rem = l.r.steps - l.job->t;
+            for (int m : {8, 4, 2})
+                if (m * T <= rem && (m - 1) * work(q) <= budget) {
+                    l.mult = m;
+                    budget -= (m - 1) * work(q);
+                    break;
+                }
+        }
+    }
     auto key = [&](size_t q) {
         const ServeShape &h = live[q].r.shape;
-        return std::make_tuple(h.kind, h.N, h.K, h.M);
+        return std::make_tuple(h.kind, h.N, h.K, h.M, live[q].mult);
     };
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
     groups.clear();
@@ -384,12 +429,13 @@ uq_status Server::rebuild_table() {
         const Live &l = live[q];
         const ServeShape &h = l.r.shape;
         if (groups.empty() || key(q) != std::make_tuple(groups.back().kind, groups.back().N, groups.back().K,
-                                                        groups.back().M)) {
+                                                        groups.back().M, groups.back().mult)) {
             Group g;
             g.kind = h.kind;
             g.N = h.N;
             g.K = h.K;
             g.M = h.M;
+            g.mult = l.mult;
             g.first = (int)fused.size();
             groups.push_back(g);
         }
@@ -429,19 +475,30 @@ uq_status Server::rebuild_table() {
         }
         g.nwork = w;
     }
-    for (Live &l : live) {
-        if (l.r.shape.kind >= 0) continue;
+    // single-step jobs in order of multiple, largest first: launch k of a
+    // tick covers the prefix of jobs that take more than k steps in it
+    std::vector<size_t> sorder;
+    for (size_t q = 0; q < live.size(); ++q)
+        if (live[q].r.shape.kind < 0) sorder.push_back(q);
+    std::stable_sort(sorder.begin(), sorder.end(), [&](size_t x, size_t y) { return live[x].mult > live[y].mult; });
+    single_runs.clear();
+    for (size_t q : sorder) {
+        const Live &l = live[q];
         MultiJob m;
         std::memset(&m, 0, sizeof m);
         m.j = l.job->jd;
         m.t = l.job->t;
         m.n_steps = l.r.steps;
         m.tile0 = tile;
+        m.adv = l.mult * T;
         m.tiles_x = l.tiles_x;
         m.tiles_y = l.tiles_y;
         tile += (int64_t)l.job->S * l.tiles_x * l.tiles_y;
         single.push_back(m);
         tptrs.push_back(l.job->d_t);
+        if (single_runs.empty() || single_runs.back().mult != l.mult) single_runs.push_back({l.mult, 0, 0});
+        single_runs.back().jobs_end = (int)single.size();
+        single_runs.back().tiles_end = tile;
     }
     total_tiles = tile;
     if ((int)tptrs.size() > table_cap) return fail(UQ_ESTATE, "more live jobs than the table holds");
@@ -463,20 +520,33 @@ uq_status Server::rebuild_table() {
     return UQ_OK;
 }
 
-// T steps of every job in the tables: each batched instance in T/N launches
-// (launch k reads the slab of parity t ^ k of each of its jobs), the
-// single-step jobs in T launches, then every job's step counter.
+// T steps of every job in the tables (mult T for the jobs of a group with
+// a multiplier): each batched instance group in mult T/N launches (launch k
+// reads the slab of parity t ^ k of each of its jobs), the single-step jobs
+// in T launches, then every job's step counter (a group's counters are
+// d_tptrs[first .. first + count), the single-step jobs' follow them).
 uq_status Server::enqueue_tick(int64_t T) {
     for (const Group &g : groups)
-        for (int k = 0; k < (int)(T / g.N); ++k)
+        for (int k = 0; k < (int)(g.mult * T / g.N); ++k)
             UQ_HIP_TRY(launch_fused_multi(g.kind, cfg.precision, g.N, g.K, g.M, d_fused + g.first, g.count, g.nwork,
                                           k, stream));
     if (n_single) {
-        for (int k = 0; k < (int)T; ++k)
-            UQ_HIP_TRY(launch_step_multi(d_table, n_single, total_tiles, k, cfg.precision, stream));
-        UQ_HIP_TRY(launch_advance_multi(d_table, n_single, T, stream));
+        // runs of equal multiple, largest first: launch k covers the runs
+        // whose jobs take more than k steps
+        for (int k = 0; k < (int)(single_runs.front().mult * T); ++k) {
+            size_t r = 0;
+            while (r + 1 < single_runs.size() && single_runs[r + 1].mult * T > k) ++r;
+            UQ_HIP_TRY(launch_step_multi(d_table, single_runs[r].jobs_end, single_runs[r].tiles_end, k, cfg.precision,
+                                         stream));
+        }
+        UQ_HIP_TRY(launch_advance_multi(d_table, n_single, stream));
     }
-    UQ_HIP_TRY(launch_advance_ptrs(d_tptrs, n_all, T, stream));
+    for (const Group &g : groups) UQ_HIP_TRY(launch_advance_ptrs(d_tptrs + g.first, g.count, g.mult * T, stream));
+    int prev = 0;
+    for (const SingleRun &r : single_runs) {
+        UQ_HIP_TRY(launch_advance_ptrs(d_tptrs + n_fused + prev, r.jobs_end - prev, r.mult * T, stream));
+        prev = r.jobs_end;
+    }
     return UQ_OK;
 }
 
@@ -522,7 +592,7 @@ uq_status Server::tick(int64_t K) {
         if (st != UQ_OK) return st;
     }
     UQ_HIP_TRY(hipStreamSynchronize(stream));
-    for (Live &l : live) l.job->t += K;
+    for (Live &l : live) l.job->t += K * l.mult;
     return UQ_OK;
 }
 
@@ -609,6 +679,10 @@ void Server::loop() {
                 live.swap(keep);
                 dirty = true;
             }
+            // a job whose multiple of the tick no longer fits its remaining
+            // steps gets a smaller one
+            for (const Live &l : live)
+                if (l.mult > 1 && l.r.steps - l.job->t < l.mult * K) dirty = true;
             if (dirty && !live.empty()) {
                 uq_status st = rebuild_table();
                 if (st != UQ_OK) return die(uq_last_error());

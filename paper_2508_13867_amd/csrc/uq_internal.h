@@ -115,6 +115,7 @@ struct alignas(16) MultiJob {
     int64_t t;        // steps done at the current base
     int64_t n_steps;  // the job's target; tiles of finished jobs are skipped
     int64_t tile0;    // first global tile of the job
+    int64_t adv;      // steps of this job per tick (launches k >= adv skip it)
     int32_t tiles_x, tiles_y;
 };
 
@@ -195,7 +196,7 @@ hipError_t launch_advance_ptrs(int64_t *const *d_t, int njobs, int64_t n, hipStr
 // one step of every job in a table (AA layout, one row per thread); all jobs
 // must share precision `prec`
 hipError_t launch_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k, int prec, hipStream_t s);
-hipError_t launch_advance_multi(MultiJob *jobs, int njobs, int64_t n, hipStream_t s);
+hipError_t launch_advance_multi(MultiJob *jobs, int njobs, hipStream_t s);  // t += adv
 void tile_counts(const JobDev &j, int cpt, int *tiles_x, int *tiles_y);
 // *d_t += n (one thread; keeps the device copy of the step count current)
 hipError_t launch_advance(int64_t *d_t, int64_t n, hipStream_t s);
