@@ -109,17 +109,6 @@ __device__ constexpr int OPPd[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // index of a direction among the three that share its c_y
 __device__ constexpr int GJd[9] = {0, 1, 0, 2, 0, 1, 2, 1, 2};
 
-// f(integral_constant<int, 0>) ... f(integral_constant<int, U - 1>) in order:
-// a loop body unrolled in the source, for bodies past the compiler's
-// unrolling budget whose constants (ring slots) depend on the index
-template <int U, int I = 0, class F>
-__device__ __forceinline__ void unrolled(F &&f) {
-    if constexpr (I < U) {
-        f(std::integral_constant<int, I>{});
-        unrolled<U, I + 1>(f);
-    }
-}
-
 template <typename C>
 __device__ inline C wgt(int i) {
     return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
@@ -981,16 +970,14 @@ __global__ __launch_bounds__(256) void k_stepN(JobDev j, bool src2, int tiles_x,
 // depends on the row is wave-uniform (scalar registers): a lane keeps one
 // column for the whole strip.
 // Between two levels each direction is read once, by the row that pulls it:
-// c_y = -1 directions one iteration after they are written (rows kept: 2,
-// slots 0-1), c_y = 0 two iterations after (3, slots 2-4), c_y = +1 three
-// after (4, slots 5-8). A row written in iteration s sits in slot s mod 2,
-// s mod 3 or s mod 4 of its group; the row loop turns over twelve
-// iterations, so in each unrolled iteration every slot is a constant.
+// c_y = -1 directions one iteration after they are written (rows kept: 2),
+// c_y = 0 two iterations after (3), c_y = +1 three after (4). Rows are
+// offset by 12 (a multiple of 2, 3 and 4) to keep slots positive.
 template <int P, int N>
 struct WindowRings {
     static constexpr int NR = N > 1 ? N - 1 : 1;
     using C = typename Prec<P>::C;
-    C r[NR][9][3][64];
+    C ra[NR][2][3][64], rb[NR][3][3][64], rc[NR][4][3][64];
 };
 
 // One work item of the strip window: strip `strip` (columns [strip W,
@@ -1004,6 +991,9 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
     using C = typename PR::C;
     using T = typename PR::T;
     constexpr int RG = N - 1;
+    auto &ra = rings.ra;
+    auto &rb = rings.rb;
+    auto &rc = rings.rc;
     const T *src_all = (const T *)(src2 ? j.f2 : j.f);
     T *dst_all = (T *)(src2 ? j.f : j.f2);
     const int nx = j.nx, ny = j.ny;
@@ -1028,19 +1018,6 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
         while (gc >= nx) gc -= nx;
         const int vo0 = gc * (int)sizeof(T), vom = (gc == 0 ? nx - 1 : gc - 1) * (int)sizeof(T),
                   vop = (gc == nx - 1 ? 0 : gc + 1) * (int)sizeof(T);
-        // LDS byte offsets: the lane's column in the ring this level writes
-        // (ring lvl - 1), and one column left of it in the ring it reads
-        // (ring lvl - 2), so that the pulls of column lc - c_x sit at
-        // non-negative constant offsets. Every access is one of the two plus
-        // a constant, the DS instructions' immediate offset; an empty asm
-        // once per turn of the row loop keeps the compiler from hoisting one
-        // address register per access out of the loop.
-        constexpr int GB = 64 * (int)sizeof(C), SB = 3 * GB, RB = 9 * SB;
-        char *const ring = reinterpret_cast<char *>(&rings.r);
-        int ow = (lvl - 1) * RB + lc * (int)sizeof(C), orr = (lvl - 2) * RB + (lc - 1) * (int)sizeof(C);
-        auto at = [&](int base, int slot, int g, int dx) -> C & {
-            return *reinterpret_cast<C *>(ring + base + slot * SB + g * GB + dx * (int)sizeof(C));
-        };
         // level 1 pulls row y + D while it collides row y: D rows of loads in
         // flight per strip. D + 1 register buffers in rotation: each step
         // collides one in place and refills the one the step before used, so
@@ -1064,14 +1041,18 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
         };
         const int y1_end = ye + RG;  // level 1 rows: [yb - RG, ye + RG)
         // collide a pulled row and hand it to the next level (or store it)
-        auto finish = [&](C *f, int y, int u) {
+        auto finish = [&](C *f, int y) {
             C drho, ux, uy;
             bgk(f, omega, drho, ux, uy);
             if (lvl < N) {
+                const int sa = (y + 12) & 1, sb = (y + 12) % 3, sc3 = (y + 12) & 3, L = lvl - 1;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    const int slot = CYd[i] < 0 ? u % 2 : (CYd[i] == 0 ? 2 + u % 3 : 5 + u % 4);
-                    at(ow, slot, GJd[i], 0) = PR::rt(f[i], sc, inv);
+                    const C v = PR::rt(f[i], sc, inv);
+                    const int g = GJd[i];
+                    if (CYd[i] < 0) ra[L][sa][g][lc] = v;
+                    else if (CYd[i] == 0) rb[L][sb][g][lc] = v;
+                    else rc[L][sc3][g][lc] = v;
                 }
             } else if (nt) {
                 const int own = y * pitch + x0 + lane;
@@ -1090,38 +1071,36 @@ __device__ __forceinline__ void stepW_item(const JobDev &j, bool src2, int W, in
             for (int k = 0; k < D; ++k) pull(buf[k], min(yb - RG + k, y1_end - 1));
         }
         const int n_it = (ye - yb) + 3 * RG;
-        static_assert(12 % B == 0, "the row loop turns over twelve iterations");
-        for (int it0 = 0; it0 < n_it; it0 += 12) {
-            unrolled<12>([&](auto uc) {
-                constexpr int u = decltype(uc)::value;
-                const int it = it0 + u;
-                if (it >= n_it) return;
-                if constexpr (u == 0) asm("" : "+v"(ow), "+v"(orr));
+        for (int it0 = 0; it0 < n_it; it0 += B) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int it = it0 + k;
+                if (it >= n_it) break;
                 const int y = yb - RG + it - 2 * (lvl - 1);  // this level's row (wave-uniform)
                 const bool row_on = y >= yb - span && y < ye + span;
                 if (lvl == 1) {
                     if (row_on) {
-                        pull(buf[(u + D) % B], min(y + D, y1_end - 1));
+                        pull(buf[(k + D) % B], min(y + D, y1_end - 1));
                         if (lane_on) {
                             C f[9];  // (buffers are written only by loads)
 #pragma unroll
-                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[u % B][i], inv);
-                            finish(f, y, u);
+                            for (int i = 0; i < 9; ++i) f[i] = BufLd<P>::cvt(buf[k][i], inv);
+                            finish(f, y);
                         }
                     }
                 } else if (row_on && lane_on) {
-                    // rows written in iterations it - 1, it - 2 and it - 3
                     C f[9];
+                    const int L = lvl - 2;
+                    const int sa = (y + 13) & 1, sb = (y + 12) % 3, sc3 = (y + 11) & 3;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
-                        const int slot =
-                            CYd[i] < 0 ? (u + 1) % 2 : (CYd[i] == 0 ? 2 + (u + 1) % 3 : 5 + (u + 1) % 4);
-                        f[i] = at(orr, slot, GJd[i], 1 - CXd[i]);
+                        const int g = GJd[i], c = lc - CXd[i];
+                        f[i] = CYd[i] < 0 ? ra[L][sa][g][c] : (CYd[i] == 0 ? rb[L][sb][g][c] : rc[L][sc3][g][c]);
                     }
-                    finish(f, y, u);
+                    finish(f, y);
                 }
                 __syncthreads();
-            });
+            }
         }
     }
 }

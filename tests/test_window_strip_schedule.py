@@ -7,15 +7,15 @@ computes row y = yb - (N-1) + it - 2(L-1) at iteration `it`, over
 each side (lane l holds global column x0 - span + l, LDS column l + L - 1).
 Level 1 pulls from the lattice; levels above pull direction i from LDS
 column lc - c_ix of the ring the level below wrote, by the group of its
-c_y, each group a ring of rows named by the iteration s a row was written
-in:
+c_y, each group a ring of rows named by the row r (offset by 12, a
+multiple of 2, 3 and 4, to keep slots positive):
 
-- c_y = -1 (read one iteration after it is written): slots 0-1, s mod 2;
-- c_y =  0 (two iterations after):                   slots 2-4, s mod 3;
-- c_y = +1 (three iterations after):                 slots 5-8, s mod 4;
+- c_y = -1 (read one iteration after it is written): 2 rows, (r + 12) mod 2;
+- c_y =  0 (two iterations after):                   3 rows, (r + 12) mod 3;
+- c_y = +1 (three iterations after):                 4 rows, (r + 12) mod 4;
 
-so that iteration it reads slots (it + 1) mod 2, 3 and 4, the constants
-of the kernel's twelve-iteration unrolled loop. The model checks that every
+so that the level computing row y reads slots (y + 13) mod 2, (y + 12)
+mod 3 and (y + 11) mod 4, the kernel's expressions. The model checks that every
 read finds the row, column and direction it expects, that no slot is read
 and written in the same iteration (no barrier between them), that every
 output node is written once, and that the result equals N plain periodic
@@ -27,12 +27,14 @@ import pytest
 from test_row_pipeline_schedule import CX, CY, GJ, collide, plain_steps
 
 
-def write_slot(i, s):
-    return [s % 2, 2 + s % 3, 5 + s % 4][CY[i] + 1]
+def write_slot(i, r):
+    """group and slot of row r's direction i in the ring it is written to"""
+    return [("a", (r + 12) % 2), ("b", (r + 12) % 3), ("c", (r + 12) % 4)][CY[i] + 1]
 
 
-def read_slot(i, it):
-    return [(it + 1) % 2, 2 + (it + 1) % 3, 5 + (it + 1) % 4][CY[i] + 1]
+def read_slot(i, y):
+    """group and slot the level computing row y reads direction i from"""
+    return [("a", (y + 13) % 2), ("b", (y + 12) % 3), ("c", (y + 11) % 4)][CY[i] + 1]
 
 
 def strips_of(nx, n):
@@ -73,14 +75,14 @@ def run_strips(nx, ny, n_lvl, rows, omega=1.2, seed=1):
                         else:
                             f = np.empty(9)
                             for i in range(9):
-                                key = (level - 2, read_slot(i, it), GJ[i], lc - CX[i])
+                                key = (level - 2, read_slot(i, y), GJ[i], lc - CX[i])
                                 # row y - c_y of the level below, global column gc - c_x
                                 assert tag.get(key) == (y - CY[i], (gc - CX[i]) % nx, i), (strip, yb, it, level, lane, i)
                                 reads.add(key)
                                 f[i] = lds[key]
                         g = collide(f[:, None], omega)[:, 0]
                         if level < n_lvl:
-                            writes += [((level - 1, write_slot(i, it), GJ[i], lc), (y, gc, i), g[i]) for i in range(9)]
+                            writes += [((level - 1, write_slot(i, y), GJ[i], lc), (y, gc, i), g[i]) for i in range(9)]
                         else:
                             assert span == 0 and lane < w and 0 <= y < ny
                             count[y, gc] += 1
