@@ -133,8 +133,9 @@ static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
 // one step per launch in the AA layout (the batched single-step kernel). A shape the
 // launch-shape tuner measured for the job's class is taken when it is a
 // batched instance; otherwise N is the largest of the instance's choices
-// whose LDS rings fit the row width (vortex 8, 6, 4; channel 4, 3, 2), the
-// vortex takes chunks of 256 rows, and the channel cuts its rows into
+// whose LDS rings fit the row width (vortex 8, 6, 4, or 6, 8, 4 up to 128
+// columns; channel 4, 3, 2), the vortex takes equal chunks of at most 256
+// rows, and the channel cuts its rows into
 // chunks so that its samples fill the GPU (at most 8, as the tuner tries).
 struct ServeShape {
     int kind = -1, N = 0, K = 0, M = 0, H = 0;
@@ -154,7 +155,11 @@ static ServeShape serve_shape(const uq_problem &p, int64_t S, int K, size_t aren
     else if (p.geometry == UQ_GEOM_CHANNEL && !needs_ab(p) && p.cyl_bc == UQ_CYL_HALFWAY) kind = 1;
     if (kind < 0) return sh;
     sh.W = p.nx;
-    const int pref[2][3] = {{8, 6, 4}, {4, 3, 2}};
+    // vortex lattices of at most 128 columns (one column per lane) run
+    // fastest at 6 steps per launch, wider ones at 8 (measured per width on
+    // the serving mix); channels take the deepest pipeline that fits
+    const bool narrow = p.nx <= 128;
+    const int pref[2][3] = {{narrow ? 6 : 8, narrow ? 8 : 6, 4}, {4, 3, 2}};
     StepShape tuned;
     const bool have = tuned_shape(p, S, &tuned) && tuned.fwin == 2 && tuned.fuse >= 2;
     for (int c = -1; c < 3; ++c) {
@@ -170,7 +175,10 @@ static ServeShape serve_shape(const uq_problem &p, int64_t S, int K, size_t aren
         if (c < 0) {
             sh.H = std::max(8, std::min(tuned.fty, p.ny));
         } else if (kind == 0) {
-            sh.H = std::max(8, std::min(256, p.ny));
+            // chunks of at most 256 rows, all of one height (a short last
+            // chunk would hold its work item's CU for a full pipeline fill)
+            const int chunks = (p.ny + 255) / 256;
+            sh.H = std::max(8, (p.ny + chunks - 1) / chunks);
         } else {
             const int chunks = (int)std::min<int64_t>(8, std::max<int64_t>(1, (256 + S - 1) / S));
             sh.H = std::max(8, (p.ny + chunks - 1) / chunks);
@@ -178,9 +186,9 @@ static ServeShape serve_shape(const uq_problem &p, int64_t S, int K, size_t aren
         return sh;
     }
     // vortex rows too wide for any whole-row instance: 4 steps per launch
-    // in strips, if the job's two slabs take at most a quarter of the arena
+    // in strips, if the job's two slabs take at most two fifths of the arena
     // (a larger job would hold back every other admission; it runs in AA)
-    if (kind == 0 && (size_t)job_footprint(p, S, K, true) <= arena / 4) {
+    if (kind == 0 && (size_t)job_footprint(p, S, K, true) <= arena * 2 / 5) {
         sh.kind = 2;
         sh.N = 4;
         sh.H = std::max(8, std::min(64, p.ny));
@@ -468,8 +476,8 @@ uq_status Server::rebuild_table() {
             FusedJob &f = fused[(size_t)q];
             const int64_t want = (f.chunks * kTargetItems + g.nwork - 1) / g.nwork;
             const int H = std::min(f.H, std::max(hmin, (int)((f.j.ny + want - 1) / want)));
-            f.H = H;
             f.chunks = (f.j.ny + H - 1) / H;
+            f.H = std::max(8, (f.j.ny + f.chunks - 1) / f.chunks);  // equal chunks
             f.work0 = w;
             w += (int64_t)f.j.S * f.chunks * f.strips;
         }
