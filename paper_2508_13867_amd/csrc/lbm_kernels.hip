@@ -121,14 +121,18 @@ __device__ inline C wgt(int i) {
 // which equals the textbook form in exact arithmetic. It is evaluated this way
 // so that single-precision rounding does not bias the flow:
 //  - the first-order term uses j itself, not rho * (j / rho);
-//  - 3 w_i (c_i.j) is (c_i.j)/3 rounded once, on the axes, and that value
-//    times 1/4 (exact) on the diagonals; (c_i.j)/3 is formed with a two-term
-//    split of 1/3 (hi + lo, one fused multiply-add), which rounds like the
-//    true quotient. Multiplying by the rounded constants fl(1/9) or fl(1/3)
-//    instead scales these terms by a fixed 1 + O(1e-8) every step; in single
-//    precision that systematically changes the decay of the kinetic energy by
-//    ~1e-5..1e-4 over a few thousand steps (measured), whereas this form keeps
-//    it at ~1e-7.
+//  - omega 3 w_i (c_i.j) is omega (c_i.j)/3 rounded once, on the axes, and
+//    that value times 1/4 (exact) on the diagonals, with omega/3 exact: in
+//    double precision omega/3 is carried as a two-term split (hi + lo, one
+//    fused multiply-add per term), in single precision the host gives each
+//    sample an omega whose third has 22 significant bits (omega itself then
+//    fits 24; a relative change of at most 2^-22, i.e. a viscosity within a
+//    few 1e-6 of the requested one), so that omega fl(1/3) rounds to that
+//    third exactly and the term is one multiply. Multiplying by a rounded
+//    omega/3 instead scales these terms by a fixed 1 + O(1e-8) every step: the
+//    collision then does not conserve momentum, and in single precision the
+//    decay of the kinetic energy drifts by ~1e-5..1e-4 over a few thousand
+//    steps (measured), against ~1e-7 in this form.
 // Returns rho - 1 and u.
 template <typename C>
 struct Third;
@@ -182,34 +186,40 @@ __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     // omega folded into the constants (per sample: the compiler hoists them
     // out of the node loops): omega w_i, and omega / 3 as an unevaluated sum
     // hi + lo (exact product of omega with the split of 1/3, rounded once to
-    // the pair), so that the first-order term omega (c_i . j) / 3 is still
-    // formed with a single rounding. Every multiply-add is an explicit fma.
+    // the pair; in single precision lo is about 0 and unused), so that the
+    // first-order term omega (c_i . j) / 3 is still formed with a single
+    // rounding. Every multiply-add is an explicit fma.
     const C ow0 = omega * (C(4) / C(9)), ow1 = omega * (C(1) / C(9)), ow2 = omega * (C(1) / C(36));
     const C o3h = omega * Third<C>::hi;
     const C o3l = fma_c(omega, Third<C>::lo, fma_c(omega, Third<C>::hi, -o3h));
     const C o12h = o3h * C(0.25), o12l = o3l * C(0.25);
+    // omega (c.j) / 3 rounded once (single precision: omega / 3 = o3h exactly)
+    auto first = [&](C cj, C h, C l) -> C {
+        if constexpr (std::is_same<C, float>::value) return cj * h;
+        else return fma_c(cj, h, cj * l);
+    };
     const C om1 = C(1) - omega;
     f[0] = fma_c(om1, f[0], ow0 * db);
     {
-        const C q = fma_c(C(4.5), px, db), l = fma_c(jx, o3h, jx * o3l);
+        const C q = fma_c(C(4.5), px, db), l = first(jx, o3h, o3l);
         f[1] = fma_c(om1, f[1], fma_c(q, ow1, l));
         f[3] = fma_c(om1, f[3], fma_c(q, ow1, -l));
     }
     {
-        const C q = fma_c(C(4.5), py, db), l = fma_c(jy, o3h, jy * o3l);
+        const C q = fma_c(C(4.5), py, db), l = first(jy, o3h, o3l);
         f[2] = fma_c(om1, f[2], fma_c(q, ow1, l));
         f[4] = fma_c(om1, f[4], fma_c(q, ow1, -l));
     }
     const C t = fma_c(C(4.5), pp, db), jx9 = C(9) * jx;
     {
         const C cj = jx + jy;
-        const C q = fma_c(jx9, uy, t), l = fma_c(cj, o12h, cj * o12l);
+        const C q = fma_c(jx9, uy, t), l = first(cj, o12h, o12l);
         f[5] = fma_c(om1, f[5], fma_c(q, ow2, l));
         f[7] = fma_c(om1, f[7], fma_c(q, ow2, -l));
     }
     {
         const C cj = jy - jx;
-        const C q = fma_c(-jx9, uy, t), l = fma_c(cj, o12h, cj * o12l);
+        const C q = fma_c(-jx9, uy, t), l = first(cj, o12h, o12l);
         f[6] = fma_c(om1, f[6], fma_c(q, ow2, l));
         f[8] = fma_c(om1, f[8], fma_c(q, ow2, -l));
     }
