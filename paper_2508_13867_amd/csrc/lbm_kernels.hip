@@ -121,18 +121,21 @@ __device__ inline C wgt(int i) {
 // which equals the textbook form in exact arithmetic. It is evaluated this way
 // so that single-precision rounding does not bias the flow:
 //  - the first-order term uses j itself, not rho * (j / rho);
-//  - omega 3 w_i (c_i.j) is omega (c_i.j)/3 rounded once, on the axes, and
-//    that value times 1/4 (exact) on the diagonals, with omega/3 exact: in
-//    double precision omega/3 is carried as a two-term split (hi + lo, one
-//    fused multiply-add per term), in single precision the host gives each
-//    sample an omega whose third has 22 significant bits (omega itself then
-//    fits 24; a relative change of at most 2^-22, i.e. a viscosity within a
-//    few 1e-6 of the requested one), so that omega fl(1/3) rounds to that
-//    third exactly and the term is one multiply. Multiplying by a rounded
-//    omega/3 instead scales these terms by a fixed 1 + O(1e-8) every step: the
-//    collision then does not conserve momentum, and in single precision the
-//    decay of the kinetic energy drifts by ~1e-5..1e-4 over a few thousand
-//    steps (measured), against ~1e-7 in this form.
+//  - the first-order term omega 3 w_i (c_i.j) is one rounded product per
+//    direction pair, a1 (c_i.j) on the axes and a2 (c_i.j) on the diagonals,
+//    with coefficients whose momentum sum 2 a1 + 4 a2 is omega exactly, so
+//    that the collision conserves momentum to rounding. In double precision
+//    a1 = omega/3 is carried as a two-term split (hi + lo, one fused
+//    multiply-add per term) and a2 = a1/4. In single precision a1 =
+//    fl(omega fl(1/3)) and a2 = (omega - 2 a1)/4, whose subtraction is exact
+//    (Sterbenz: omega and 2 a1 are within a factor of two), one multiply per
+//    term; a2 then differs from omega/12 by O(1e-7), which touches only a
+//    third moment of the equilibrium (Q_xyy), not mass, momentum or stress.
+//    Multiplying both by a rounded omega/3 instead scales these terms by a
+//    fixed 1 + O(1e-8) every step: the collision then does not conserve
+//    momentum, and in single precision the decay of the kinetic energy
+//    drifts by ~1e-5..1e-4 over a few thousand steps (measured), against
+//    ~1e-7 in this form.
 // Returns rho - 1 and u.
 template <typename C>
 struct Third;
@@ -186,14 +189,17 @@ __device__ inline void bgk(C f[9], C omega, C &drho_o, C &ux_o, C &uy_o) {
     // omega folded into the constants (per sample: the compiler hoists them
     // out of the node loops): omega w_i, and omega / 3 as an unevaluated sum
     // hi + lo (exact product of omega with the split of 1/3, rounded once to
-    // the pair; in single precision lo is about 0 and unused), so that the
-    // first-order term omega (c_i . j) / 3 is still formed with a single
-    // rounding. Every multiply-add is an explicit fma.
+    // the pair; unused in single precision), so that the first-order term is
+    // still formed with a single rounding. Every multiply-add is an explicit
+    // fma.
     const C ow0 = omega * (C(4) / C(9)), ow1 = omega * (C(1) / C(9)), ow2 = omega * (C(1) / C(36));
     const C o3h = omega * Third<C>::hi;
     const C o3l = fma_c(omega, Third<C>::lo, fma_c(omega, Third<C>::hi, -o3h));
-    const C o12h = o3h * C(0.25), o12l = o3l * C(0.25);
-    // omega (c.j) / 3 rounded once (single precision: omega / 3 = o3h exactly)
+    // diagonal coefficient: in single precision the exact remainder of omega
+    // after the two axis terms, so that 2 o3h + 4 o12h = omega
+    const C o12h = std::is_same<C, float>::value ? (omega - C(2) * o3h) * C(0.25) : o3h * C(0.25);
+    const C o12l = o3l * C(0.25);
+    // the first-order term, rounded once (single precision: one multiply)
     auto first = [&](C cj, C h, C l) -> C {
         if constexpr (std::is_same<C, float>::value) return cj * h;
         else return fma_c(cj, h, cj * l);

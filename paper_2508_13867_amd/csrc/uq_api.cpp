@@ -203,19 +203,6 @@ uq_status Job::own_stat_bufs(int qoi, bool fields, StatBufs *b) {
 
 namespace uqi {
 
-// The relaxation rate a single-precision job runs at: the nearest omega whose
-// third has 22 significant bits. omega then fits 24 bits, its float product
-// with the float nearest 1/3 rounds to that third exactly, and the collision's
-// first-order term omega (c.j)/3 is a single multiply that conserves momentum
-// to rounding (an inexact omega/3 would scale it by the same 1 + O(1e-8) every
-// step). The change of omega is at most 2^-22 of it; of nu = (1/omega - 1/2)/3
-// at most 2^-22 tau / (tau - 1/2).
-static double single_omega(double omega) {
-    int e = 0;
-    const double m = std::frexp(omega / 3.0, &e);  // omega/3 = m 2^e, m in [1/2, 1)
-    return 3.0 * std::ldexp(std::nearbyint(std::ldexp(m, 22)), e - 22);
-}
-
 uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepShape *forced, uq_job **out) {
     const uq_problem *p = &prob;
     *out = nullptr;
@@ -257,7 +244,6 @@ uq_status create_job(const uq_problem &prob, const uq_device *dev, const StepSha
         SampleDev d;
         std::memset(&d, 0, sizeof d);
         d.omega = 1.0 / tau;
-        if (P.precision != UQ_FP64) d.omega = single_omega(d.omega);
         d.u0 = in.u0;
         d.phase_x = in.phase_x;
         d.phase_y = in.phase_y;
