@@ -41,10 +41,7 @@ typedef enum {
 } uq_status;
 
 /* Storage precision of the populations. Collision always runs on shifted
- * populations f_i - w_i; FP64 computes in double, the others in float. A
- * float-compute job relaxes each sample at the nearest omega whose third has
- * 22 significant bits (within 2^-22 of 1/tau), so that the collision's
- * first-order term conserves momentum to rounding with one multiply. */
+ * populations f_i - w_i; FP64 computes in double, the others in float. */
 typedef enum {
     UQ_FP64 = 0,  /* double storage, double compute                        */
     UQ_FP32 = 1,  /* float storage, float compute                          */
