@@ -523,6 +523,34 @@ def test_mc4096_full_size_precisions_vs_fp64_and_oracle():
         assert rel_l2(ke[prec], ke["fp64"]) < TOL[prec]
 
 
+@pytest.mark.parametrize("fuse", ["0", "8"])
+def test_fp32_kinetic_energy_does_not_drift(fuse, monkeypatch):
+    # The single-precision collision forms its first-order term with axis and
+    # diagonal coefficients whose momentum sum is omega exactly. With a
+    # rounded omega/3 on both it would scale the momentum by the same
+    # 1 + O(1e-8) every step, and the kinetic energy of a decaying vortex
+    # would drift by ~1e-4 (a float32 model of that arithmetic: 7e-4 over 3000
+    # steps). Per-sample KE of FP32 runs, single steps and 8 fused steps per
+    # launch, against the device's FP64 run of the same inputs.
+    spec = dict(name="tgv64_drift", geometry="tgv", precision="fp64", nx=64, ny=64, steps=3000, u0=0.02, nu=0.005,
+                dists=[("nu", 0.004, 0.006), ("u0", 0.018, 0.022)], rule=dict(kind="gl", n=2, order=1), layout="ab")
+    say("case fp32 drift, fuse", fuse)
+    ke = {}
+    for prec in ("fp64", "fp32"):
+        if prec == "fp32" and fuse != "0":
+            monkeypatch.setenv("UQ_FUSE", fuse)
+            monkeypatch.setenv("UQ_FUSE_TY", "64")
+            monkeypatch.setenv("UQ_FUSE_WINDOW", "2")
+        with Job(dict(spec, precision=prec)) as job:
+            if prec == "fp32":
+                assert job.info().fused == int(fuse)
+            job.run(spec["steps"])
+            ke[prec] = job.qoi_samples("ke")[:, 0]
+    err = np.abs(ke["fp32"] / ke["fp64"] - 1.0)
+    say("largest relative KE error", err.max())
+    assert err.max() < 2e-6, err
+
+
 @pytest.mark.parametrize("rule", [dict(kind="smolyak", level=2, order=2), dict(kind="halton", N=40),
                                   dict(kind="lhs", N=40, seed=77)])
 def test_sparse_grid_qmc_lhs_rules_fp64(rule):
