@@ -1749,6 +1749,17 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC_multi(const FusedJob *job
 // are the global tiles [tile0_q, tile0_{q+1}); a job whose step count has
 // reached its target is skipped, so the same launch (or captured graph) stays
 // valid while jobs finish.
+// The same address as a pointer into global memory. A pointer loaded from a
+// table in device memory is generic to the compiler, and the accesses through
+// it compile to flat instructions (64-bit addresses in vector registers, and
+// waits on the LDS counter as well); rebuilt from its integer value in the
+// global address space, they compile to global loads and stores, as those of
+// a kernel argument do.
+template <typename T>
+__device__ inline T *global_ptr(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k) {
     const int64_t G = gridDim.x;
@@ -1762,17 +1773,21 @@ __global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int nj
         const MultiJob &q = jobs[lo];
         const int64_t t = q.t + k;
         if (t >= q.n_steps || k >= q.adv) continue;
+        JobDev jd = q.j;
+        jd.f = global_ptr(jd.f);
+        jd.smp = global_ptr(jd.smp);
+        jd.mask = global_ptr(jd.mask);
         const int64_t per_sample = (int64_t)q.tiles_x * q.tiles_y;
         const int64_t local = tile - q.tile0;
         const int64_t smp = local / per_sample;
         const int64_t rem = local - smp * per_sample;
         const int ty = (int)(rem / q.tiles_x), tx = (int)(rem - (int64_t)ty * q.tiles_x);
-        if (q.j.geom == 1) {
-            if (t & 1) tile_update<P, true, 1, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
-            else tile_update<P, true, 0, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
+        if (jd.geom == 1) {
+            if (t & 1) tile_update<P, true, 1, 1, UQ_LAYOUT_AA, false>(jd, t, smp, tx, ty);
+            else tile_update<P, true, 0, 1, UQ_LAYOUT_AA, false>(jd, t, smp, tx, ty);
         } else {
-            if (t & 1) tile_update<P, false, 1, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
-            else tile_update<P, false, 0, 1, UQ_LAYOUT_AA, false>(q.j, t, smp, tx, ty);
+            if (t & 1) tile_update<P, false, 1, 1, UQ_LAYOUT_AA, false>(jd, t, smp, tx, ty);
+            else tile_update<P, false, 0, 1, UQ_LAYOUT_AA, false>(jd, t, smp, tx, ty);
         }
     }
 }
