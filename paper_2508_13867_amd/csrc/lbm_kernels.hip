@@ -1743,12 +1743,6 @@ __global__ __launch_bounds__(64 * N * K) void k_stepRC_multi(const FusedJob *job
     }
 }
 
-// One step for every live node of every sample of every job in a table
-// (continuous batching). Jobs may differ in geometry, lattice, sample count
-// and step parity; all use the AA layout, one row per thread. Tiles of job q
-// are the global tiles [tile0_q, tile0_{q+1}); a job whose step count has
-// reached its target is skipped, so the same launch (or captured graph) stays
-// valid while jobs finish.
 // The same address as a pointer into global memory. A pointer loaded from a
 // table in device memory is generic to the compiler, and the accesses through
 // it compile to flat instructions (64-bit addresses in vector registers, and
@@ -1760,6 +1754,12 @@ __device__ inline T *global_ptr(T *p) {
     return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
 }
 
+// One step for every live node of every sample of every job in a table
+// (continuous batching). Jobs may differ in geometry, lattice, sample count
+// and step parity; all use the AA layout, one row per thread. Tiles of job q
+// are the global tiles [tile0_q, tile0_{q+1}); a job whose step count has
+// reached its target is skipped, so the same launch (or captured graph) stays
+// valid while jobs finish.
 template <int P>
 __global__ __launch_bounds__(256) void k_step_multi(const MultiJob *jobs, int njobs, int64_t ntiles, int k) {
     const int64_t G = gridDim.x;
